@@ -1,0 +1,130 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the
+benchmark.
+
+This module holds problem parameters only -- no arithmetic of the method.
+Each workload is a plain dict understood by both the GPU binding
+(``paper_1102_4666_amd``) and the oracle binding (``oracle``).
+
+The option model is the log-price local-volatility model of Section 5 of
+Labart & Lelong (arXiv:1102.4666), eq. 4, with the uniform-correlation
+Brownian motion of Section 6.2; payoffs are the basket puts and calls of
+eqs. put_payoff / call_payoff (plus a geometric basket).  The paper's
+experiments use synthetic model parameters, never a dataset.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+
+def problem(**kw) -> dict:
+    """A d=1 Black-Scholes European put with small sizes, overridden by kw."""
+    cfg = {
+        "d": 1,
+        "vol_kind": "const",   # "const" | "bump"
+        "vol_level": [0.2],
+        "bump_a": 0.0,
+        "bump_c": 100.0,
+        "rho": 0.0,
+        "r": 0.05,
+        "div": 0.0,
+        "payoff": "put",       # put | call | put_geom | call_geom | fwd | quad
+        "K": 100.0,
+        "T": 1.0,
+        "S0": [100.0],
+        "grid": "tensor",      # tensor | random
+        "n_t": 8,
+        "n_x": 16,
+        "width": 4.0,
+        "eta": 6,
+        "q": 1.0,
+        "M": 64,
+        "N": 8,
+        "K_it": 2,
+        "omega": 0.0,
+        "seed": 0,
+        "precision": "fp64",   # fp64 | fp32 (FP32 paths, FP64 sums/update)
+    }
+    cfg.update(kw)
+    d = cfg["d"]
+    for key in ("vol_level", "S0"):
+        v = np.broadcast_to(np.asarray(cfg[key], float), (d,))
+        cfg[key] = [float(x) for x in v]
+    return cfg
+
+
+def vol_levels(d: int, seed: int = 0, lo: float = 0.15, hi: float = 0.35):
+    """Per-asset volatility levels drawn uniformly in [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed)
+    return [float(x) for x in rng.uniform(lo, hi, size=d)]
+
+
+# The five benchmark workloads (sizes of the hot-path scope table).
+def config1() -> dict:
+    """d=1 European put, Black-Scholes sigma=0.2, 64 space x 8 time points,
+    M=1000, N=20, 5 Picard iterations, FP64, seed 0."""
+    return problem(d=1, vol_kind="const", vol_level=0.2, r=0.05, K=100.0,
+                   S0=100.0, T=1.0, payoff="put", omega=0.0, grid="tensor",
+                   n_t=8, n_x=64, eta=6, M=1000, N=20, K_it=5,
+                   precision="fp64", seed=0)
+
+
+def config2(omega: float = 100.0, precision: str = "fp32") -> dict:
+    """d=1 American put (penalised BSDE, penalty 100), local volatility
+    0.2 (1 + 0.25 exp(-(log(S/100))^2)), 128 space x 16 time points,
+    M=4000, N=50, 8 Picard iterations."""
+    return problem(d=1, vol_kind="bump", vol_level=0.2, bump_a=0.25,
+                   bump_c=100.0, r=0.05, K=100.0, S0=100.0, T=1.0,
+                   payoff="put", omega=omega, grid="tensor", n_t=16,
+                   n_x=128, eta=6, M=4000, N=50, K_it=8,
+                   precision=precision, seed=0)
+
+
+def config3(omega: float = 100.0, precision: str = "fp32") -> dict:
+    """d=2 American arithmetic-basket put, independent bump local vols,
+    rho=0.3, 32^2 space x 16 time points, M=2000, N=50, 8 iterations."""
+    return problem(d=2, vol_kind="bump", vol_level=0.2, bump_a=0.25,
+                   bump_c=100.0, rho=0.3, r=0.05, K=100.0, S0=100.0, T=1.0,
+                   payoff="put", omega=omega, grid="tensor", n_t=16, n_x=32,
+                   eta=5, M=2000, N=50, K_it=8, precision=precision, seed=0)
+
+
+def config4(omega: float = 100.0, precision: str = "fp32") -> dict:
+    """d=5 American geometric-basket put, per-asset levels U[0.15, 0.35]
+    (seeded), rho=0.2, 4096 random spatial points x 10 times, M=1000,
+    N=50, 10 iterations."""
+    return problem(d=5, vol_kind="bump", vol_level=vol_levels(5, seed=0),
+                   bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, K=100.0,
+                   S0=100.0, T=1.0, payoff="put_geom", omega=omega,
+                   grid="random", n_t=10, n_x=4096, eta=3, M=1000, N=50,
+                   K_it=10, precision=precision, seed=0)
+
+
+def serving_request(idx: int, rng: np.random.Generator) -> dict:
+    """One request of the serving mix: d in {1,2,5,10}, strike U[80,120],
+    European/American 50/50, M in {500,1000,2000,4000}, FP32 paths."""
+    d = int(rng.choice([1, 2, 5, 10]))
+    K = float(rng.uniform(80.0, 120.0))
+    american = bool(rng.integers(0, 2))
+    M = int(rng.choice([500, 1000, 2000, 4000]))
+    if d == 1:
+        base = config2()
+    elif d == 2:
+        base = config3()
+    elif d == 5:
+        base = config4()
+    else:
+        base = problem(d=10, vol_kind="bump", vol_level=vol_levels(10, 0),
+                       bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, S0=100.0,
+                       T=1.0, payoff="put", grid="random", n_t=10,
+                       n_x=8192, eta=3, N=50, K_it=10)
+        M = 500 if M > 500 and idx % 2 else M
+    cfg = copy.deepcopy(base)
+    cfg.update(K=K, M=M, omega=(1.0 if american else 0.0), seed=1 + idx,
+               precision="fp32")
+    return cfg
+
+
+CONFIGS = {"config1": config1, "config2": config2, "config3": config3,
+           "config4": config4}
