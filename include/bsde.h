@@ -1,0 +1,210 @@
+/*
+ * bsde.h -- C ABI of the MI355X (gfx950) BSDE solver library (libbsde.so).
+ *
+ * The library computes the Picard iteration with an adaptive Monte Carlo
+ * control variate of Labart & Lelong, "A Parallel Algorithm for solving
+ * BSDEs -- Application to the pricing and hedging of American options"
+ * (arXiv:1102.4666): Algorithm 1 of Section 3.1 in the detailed form of
+ * Algorithm "algodetail" (Section 4.1), applied to the option model of
+ * Section 5 (log-prices, eq. 4; penalised BSDE, eq. bsde-penal-2) with the
+ * correlated Brownian motion of Section 6.2.  Every step of a solve runs in
+ * hand-written HIP kernels on the GPU; the host only prepares the fixed
+ * grid and the least-squares factorisation once per problem.
+ *
+ * Conventions for every entry point:
+ *  - plain C types; pointers are HOST pointers unless stated otherwise;
+ *  - inputs are copied, the caller keeps ownership of its arrays;
+ *  - outputs go to caller-allocated buffers of the documented size;
+ *  - every call returns a bsde_status and never aborts; on error nothing
+ *    is written to the outputs;
+ *  - a problem handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef BSDE_H
+#define BSDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsde_problem_s *bsde_problem; /* owned by the library */
+
+typedef enum {
+    BSDE_OK = 0,
+    BSDE_EINVAL = 1,   /* an argument is out of range                       */
+    BSDE_ENOMEM = 2,   /* host or device allocation failed                  */
+    BSDE_ERANK = 3,    /* fewer points than basis functions, or the basis
+                          matrix is numerically rank deficient             */
+    BSDE_EDEVICE = 4,  /* a HIP call failed (no GPU, launch failure, ...)    */
+    BSDE_ESTATE = 5,   /* call not valid in the current state (e.g. query
+                          before solve)                                    */
+    BSDE_EUNSUPPORTED = 6 /* no kernel is built for this (d, eta)            */
+} bsde_status;
+
+/* Volatility sigma_j(t, S) of asset j (eq. 4 of Section 5, diagonal form:
+ * the diffusion of X_j is sigma_j (L dW)_j with L the Cholesky factor of the
+ * correlation matrix). */
+typedef enum {
+    BSDE_VOL_CONST = 0, /* sigma_j = level_j                               */
+    BSDE_VOL_BUMP = 1   /* sigma_j = level_j (1 + bump_a e^{-(log(S/bump_c))^2}) */
+} bsde_vol_kind;
+
+typedef struct {
+    int kind;               /* bsde_vol_kind                                 */
+    const double *level;    /* d levels, > 0                                 */
+    double bump_a;          /* bump height (BSDE_VOL_BUMP)                   */
+    double bump_c;          /* bump centre in price units (> 0)              */
+    double rho;             /* uniform correlation (Section 6.2), must lie in
+                               (-1/(d-1), 1) so that rho 11' + (1-rho) I is
+                               positive definite                            */
+    const double *dividend; /* d dividend rates delta_j, or NULL for zeros   */
+} bsde_sigma;
+
+/* Payoff Phi of the log-price x (eqs. put_payoff, call_payoff). */
+typedef enum {
+    BSDE_PUT_ARITH = 0,  /* (K - (1/d) sum_j e^{x_j})_+                     */
+    BSDE_CALL_ARITH = 1, /* ((1/d) sum_j e^{x_j} - K)_+                     */
+    BSDE_PUT_GEOM = 2,   /* (K - exp((1/d) sum_j x_j))_+                    */
+    BSDE_CALL_GEOM = 3,  /* (exp((1/d) sum_j x_j) - K)_+                    */
+    BSDE_FWD_ARITH = 4,  /* (1/d) sum_j e^{x_j} - K  (call minus put)       */
+    BSDE_QUAD = 5        /* (sum_j x_j)^2 (test payoff with a polynomial
+                            solution when r = 0)                           */
+} bsde_payoff_kind;
+
+typedef struct {
+    int kind;          /* bsde_payoff_kind                                   */
+    double K;          /* strike                                             */
+    double T;          /* maturity (> 0)                                     */
+    const double *S0;  /* d spot prices (> 0); centre of the domain D        */
+} bsde_payoff;
+
+/* The n points (t_i, x_i) of Algorithm "algodetail" and the basis of the
+ * least-squares extrapolating operator (Section 4.2, eqs. lspb and
+ * hyper_set).  Points are fixed for all iterations.  Point i is
+ * a * n_spatial + b for time node a (t_a = a T / (n_t - 1)) and spatial
+ * point b.  The domain is D_j = log S0_j +- width * level_j * sqrt(T);
+ * polynomials are Chebyshev in the variables mapped to [-1, 1]^{d+1}. */
+typedef enum {
+    BSDE_GRID_TENSOR = 0, /* n_x equispaced nodes per asset (endpoints
+                             included); spatial point b has base-n_x digits
+                             b_j, asset 1 least significant               */
+    BSDE_GRID_RANDOM = 1  /* n_x points uniform in D, drawn once from the
+                             counter-based generator (substream 2)        */
+} bsde_grid_kind;
+
+typedef struct {
+    int kind;      /* bsde_grid_kind                                        */
+    int n_t;       /* time nodes, >= 2                                      */
+    int n_x;       /* tensor: nodes per asset; random: spatial points       */
+    double width;  /* half-width of D in units of level_j sqrt(T), > 0      */
+    int eta;       /* maximal total degree of the polynomial basis          */
+    double q;      /* hyperbolic index set parameter in (0, 1]; 1 = total
+                      degree                                               */
+} bsde_grid;
+
+typedef enum {
+    BSDE_FP64 = 0,       /* paths, driver, sums and update in FP64           */
+    BSDE_FP32_PATHS = 1  /* paths, basis and driver in FP32; Monte Carlo
+                            sums, least-squares update and coefficient
+                            tables in FP64                                 */
+} bsde_precision;
+
+/* Creates a pricing problem and performs its one-time set-up: index set,
+ * grid, basis matrix, rank-checked Householder QR, the pseudo-inverse
+ * R^{-1} Q' and the derivative (channel) matrices, all uploaded to the
+ * current HIP device.
+ *   d         number of assets, 1 <= d <= 10 (a kernel must exist for
+ *             (d, eta); BSDE_EUNSUPPORTED otherwise)
+ *   sigma     volatility model (see bsde_sigma)
+ *   r         interest rate
+ *   payoff    payoff, strike, maturity and spots
+ *   grid      points and basis (see bsde_grid)
+ *   M         Monte Carlo paths per point and iteration, >= 1
+ *   N         Euler steps per path, >= 1 (equal steps on [t_i, T])
+ *   n_picard  Picard iterations K_it, >= 1
+ *   penalty   omega of eq. bsde-penal-2 (0 = European option), >= 0
+ *   seed      64-bit key of the Philox4x32-10 streams
+ *   precision bsde_precision
+ *   out       receives the handle (NULL on error)
+ * Errors: BSDE_EINVAL, BSDE_ERANK, BSDE_ENOMEM, BSDE_EDEVICE,
+ * BSDE_EUNSUPPORTED. */
+bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
+                                const bsde_payoff *payoff,
+                                const bsde_grid *grid, int M, int N,
+                                int n_picard, double penalty,
+                                unsigned long long seed, int precision,
+                                bsde_problem *out);
+
+/* Runs the remaining Picard iterations k_done..n_picard-1 (Algorithm
+ * "algodetail": per-point Monte Carlo correction, eq. chat; least-squares
+ * update, eq. alpha) on the given HIP stream (hipStream_t, NULL = the
+ * default stream) and returns once they are complete.  Starting
+ * coefficients are u^0 = 0 unless set with bsde_set_coefficients or
+ * bsde_fit_values.  Errors: BSDE_EDEVICE. */
+bsde_status bsde_solve(bsde_problem h, void *hip_stream);
+
+/* Price u(t, log S) and dollar deltas Delta_j = e^{-x_j} d_{x_j} u (the
+ * hedge of Section 5.1, in price units) from the last coefficients.
+ *   nq     number of queries
+ *   t      nq times
+ *   S      nq * d prices, row-major (query-major)
+ *   price  nq outputs; delta: nq * d outputs (row-major), may be NULL
+ * Errors: BSDE_ESTATE if no iteration has run and no coefficients were
+ * set, BSDE_EINVAL. */
+bsde_status bsde_query_price_delta(bsde_problem h, int nq, const double *t,
+                                   const double *S, double *price,
+                                   double *delta);
+
+/* Sizes of the problem: n points, p basis functions (full total-degree
+ * set of the kernel; entries outside a hyperbolic set stay zero), C
+ * derivative channels (u, d_t u, grad u, upper-triangular hessian). */
+bsde_status bsde_problem_sizes(bsde_problem h, int *n, int *p, int *C);
+
+/* The n * (d+1) grid points (t_i, x_i), row-major. */
+bsde_status bsde_get_points(bsde_problem h, double *pts);
+
+/* Coefficients alpha^k (Chebyshev basis, p doubles) after k iterations,
+ * 0 <= k <= k_done; k < 0 means the latest.  k_done receives the number
+ * of completed iterations (may be NULL). */
+bsde_status bsde_get_coefficients(bsde_problem h, int k, double *alpha,
+                                  int *k_done);
+
+/* Replaces the current coefficients and declares k_done iterations done
+ * (checkpoint / resume; the random streams are keyed by k, so resuming
+ * reproduces the remaining iterations). */
+bsde_status bsde_set_coefficients(bsde_problem h, const double *alpha,
+                                  int k_done);
+
+/* Sets alpha = argmin ||y - B alpha|| for values y (n doubles) at the grid
+ * points (least-squares fit of a known function) and declares k_done
+ * iterations done. */
+bsde_status bsde_fit_values(bsde_problem h, const double *y, int k_done);
+
+/* Per-point correction c^k_i (eq. chat) and the sample variance of the
+ * path terms a_m at iteration k (n doubles each; var may be NULL). */
+bsde_status bsde_get_corrections(bsde_problem h, int k, double *c,
+                                 double *var);
+
+/* Path tiling of the Monte Carlo kernel: each point's M paths are split
+ * over groups_per_point workgroups of 256 lanes, each lane running up to
+ * paths_per_lane paths (0, 0 = automatic choice).  The result depends only
+ * on the tiling through the summation order. */
+bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
+                            int paths_per_lane);
+
+/* Average duration in milliseconds of the last solve's kernels, measured
+ * with HIP events on the solve's stream: [0] Monte Carlo path kernel,
+ * [1] reduction of the per-point sums, [2] projection R^{-1} Q' c,
+ * [3] coefficient/channel update, [4] whole solve. */
+bsde_status bsde_last_timings(bsde_problem h, double *ms5);
+
+void bsde_destroy(bsde_problem h);
+const char *bsde_status_string(bsde_status s);
+/* Human-readable detail of the last error on this thread. */
+const char *bsde_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -119,6 +119,7 @@ def lib():
         L.oracle_solve.argtypes = [P, C.c_int, _dp, C.c_int, _dp, _dp, _dp,
                                    _dp]
         L.oracle_fit.argtypes = [P, _dp, _dp]
+        L.oracle_basis_matrix.argtypes = [P, _dp]
         L.oracle_price_delta.argtypes = [P, _dp, C.c_int, _dp, _dp, _dp,
                                          _dp]
         _lib = L
@@ -315,6 +316,59 @@ def solve(cfg, k_start=0, alpha_start=None, k_end=None):
     if st:
         raise RuntimeError("oracle_solve failed with status %d" % st)
     return {"alpha": ah, "c": ch, "var": vh, "u": uh, "n": n, "p": p}
+
+
+def basis_matrix(cfg):
+    pb = make_problem(cfg)
+    n = lib().oracle_num_points(C.byref(pb))
+    p = lib().oracle_num_basis(C.byref(pb))
+    B = np.zeros((n, p))
+    lib().oracle_basis_matrix(C.byref(pb), _d(B))
+    return B
+
+
+def solve_parallel(cfg, workers=8, chunk=64, k_start=0, alpha_start=None,
+                   k_end=None, progress=None):
+    """The same loop as ``solve`` (the same oracle functions, in the same
+    order per point), with the per-point corrections of each iteration
+    spread over worker processes.  Results are identical to ``solve``."""
+    import multiprocessing as mp
+    pb = make_problem(cfg)
+    if k_end is None:
+        k_end = pb.K_it
+    B = basis_matrix(cfg)
+    n, p = B.shape
+    alpha = np.zeros(p) if alpha_start is None else np.array(alpha_start, float)
+    have = alpha_start is not None
+    ah = [alpha.copy()]
+    ch, vh, uh = [], [], []
+    ranges = [(i, min(i + chunk, n)) for i in range(0, n, chunk)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for k in range(k_start, k_end):
+            args = [(cfg, alpha if have else None, k, a, b) for a, b in ranges]
+            parts = pool.starmap(corrections, args)
+            c = np.concatenate([x[0] for x in parts])
+            v = np.concatenate([x[1] for x in parts])
+            u = _rowdot(B, alpha)
+            alpha = lstsq(B, u + c)
+            have = True
+            ah.append(alpha.copy())
+            ch.append(c)
+            vh.append(v)
+            uh.append(u)
+            if progress:
+                progress(k)
+    return {"alpha": np.array(ah), "c": np.array(ch), "var": np.array(vh),
+            "u": np.array(uh), "n": n, "p": p}
+
+
+def _rowdot(B, alpha):
+    # u_i = sum_l alpha_l B_il summed in l order, as in oracle_solve
+    u = np.zeros(B.shape[0])
+    for l in range(B.shape[1]):
+        u = u + alpha[l] * B[:, l]
+    return u
 
 
 def fit(cfg, y):

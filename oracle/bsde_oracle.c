@@ -553,6 +553,17 @@ static void basis_matrix(const oracle_problem *pb, const int *nu, int p,
     }
 }
 
+void oracle_basis_matrix(const oracle_problem *pb, double *B)
+{
+    int d = pb->d, n = oracle_num_points(pb), p = oracle_num_basis(pb);
+    int *nu = (int *)malloc(sizeof(int) * (size_t)p * (d + 1));
+    double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
+    oracle_index_set(d + 1, pb->eta, pb->q, nu, p);
+    oracle_points(pb, pts);
+    basis_matrix(pb, nu, p, pts, n, B);
+    free(nu); free(pts);
+}
+
 int oracle_fit(const oracle_problem *pb, const double *y, double *alpha)
 {
     int d = pb->d, n = oracle_num_points(pb), p = oracle_num_basis(pb);

@@ -155,6 +155,8 @@ void oracle_corrections(const oracle_problem *pb, const double *alpha,
 int oracle_solve(const oracle_problem *pb, int k_start,
                  const double *alpha_start, int k_end, double *alpha_hist,
                  double *c_hist, double *var_hist, double *u_hist);
+/* B_{il} = B_l(t_i, x_i), row-major n x p (the least-squares design matrix). */
+void oracle_basis_matrix(const oracle_problem *pb, double *B);
 /* alpha = B^+ y for values y at the grid points (fit of a known function). */
 int oracle_fit(const oracle_problem *pb, const double *y, double *alpha);
 /* price u(t, log S) and dollar delta e^{-x_j} d_{x_j} u for nq queries. */

@@ -1,0 +1,175 @@
+// bsde_common.h -- definitions shared by the host set-up and the HIP kernels
+// of the BSDE library: the counter-based generator, the compile-time index
+// sets of the polynomial basis and the per-launch parameter block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace bsde {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1, so
+// that table reads indexed by I are constant expressions.
+template <typename F, int... Is>
+__host__ __device__ __forceinline__ void static_for_impl(
+    F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+
+template <int N, typename F>
+__host__ __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int kMaxD = 10;
+constexpr int kBlock = 256; // lanes per workgroup of the path kernel
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter words:
+// (path m, point i, iteration k, substream << 24 | block); key: the seed.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1,
+                                                   uint32_t c2, uint32_t c3,
+                                                   uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------------------------
+// Total-degree index set {nu in N^{DP} : |nu| <= ETA}, graded, and within a
+// degree lexicographically decreasing.  For every multi-index the table
+// gives the "parent" obtained by zeroing its last non-zero entry, the
+// variate of that entry and its degree: B_nu = B_parent * T_deg(z_var).
+// ---------------------------------------------------------------------------
+constexpr int binom(int n, int k)
+{
+    long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return (int)r;
+}
+
+template <int DP, int ETA>
+struct IndexTable {
+    static constexpr int P = binom(DP + ETA, ETA);
+    int8_t nu[P][DP];
+    int16_t parent[P];
+    int8_t var[P];
+    int8_t deg[P];
+};
+
+template <int DP, int ETA>
+constexpr IndexTable<DP, ETA> make_index_table()
+{
+    IndexTable<DP, ETA> t{};
+    int count = 0;
+    for (int g = 0; g <= ETA; ++g) {
+        // odometer over compositions of g into DP parts, first part largest
+        int cur[DP] = {};
+        cur[0] = g;
+        while (true) {
+            for (int v = 0; v < DP; ++v) t.nu[count][v] = (int8_t)cur[v];
+            ++count;
+            // next composition in lexicographically decreasing order
+            int j = DP - 2;
+            while (j >= 0 && cur[j] == 0) --j;
+            if (j < 0) break;
+            cur[j] -= 1;
+            int rest = 0;
+            for (int v = j + 1; v < DP; ++v) rest += cur[v];
+            for (int v = j + 1; v < DP; ++v) cur[v] = 0;
+            cur[j + 1] = rest + 1;
+        }
+    }
+    for (int l = 0; l < t.P; ++l) {
+        int last = -1;
+        for (int v = 0; v < DP; ++v)
+            if (t.nu[l][v]) last = v;
+        if (last < 0) {
+            t.parent[l] = -1;
+            t.var[l] = 0;
+            t.deg[l] = 0;
+            continue;
+        }
+        int8_t want[DP] = {};
+        for (int v = 0; v < DP; ++v) want[v] = t.nu[l][v];
+        want[last] = 0;
+        int par = -1;
+        for (int m = 0; m < l; ++m) {
+            bool eq = true;
+            for (int v = 0; v < DP; ++v) eq = eq && (t.nu[m][v] == want[v]);
+            if (eq) par = m;
+        }
+        t.parent[l] = (int16_t)par;
+        t.var[l] = (int8_t)last;
+        t.deg[l] = t.nu[l][last];
+    }
+    return t;
+}
+
+template <int DP, int ETA>
+struct Basis {
+    static constexpr int P = binom(DP + ETA, ETA);
+    static constexpr IndexTable<DP, ETA> tab = make_index_table<DP, ETA>();
+};
+
+// number of derivative channels: u, d_t u, d d_x u, d(d+1)/2 d_xx u
+__host__ __device__ constexpr int num_channels(int d)
+{
+    return 2 + d + d * (d + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Per-launch parameters of the path kernel (passed by value).
+// ---------------------------------------------------------------------------
+enum VolKind { kVolConst = 0, kVolBump = 1 };
+enum PayoffKind {
+    kPutArith = 0,
+    kCallArith = 1,
+    kPutGeom = 2,
+    kCallGeom = 3,
+    kFwdArith = 4,
+    kQuad = 5
+};
+
+struct PathParams {
+    uint64_t seed;
+    uint32_t k;          // Picard iteration (counter word 2)
+    int M, N;            // paths per point, Euler steps
+    int groups;          // workgroups per point
+    int paths_per_lane;  // paths run by one lane
+    int n;               // number of points
+    int vol_kind, payoff;
+    double r, omega, K, T;
+    double level[kMaxD];
+    double div[kMaxD];
+    double bump_a, log_bump_c;
+    double L[kMaxD * kMaxD];   // Cholesky factor, row-major lower
+    double rho;
+    double mid[kMaxD];         // domain centre
+    double scale[kMaxD];       // 2 / (hi - lo)
+};
+
+} // namespace bsde

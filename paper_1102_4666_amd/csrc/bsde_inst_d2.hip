@@ -1,0 +1,55 @@
+// bsde_inst_d2.hip -- path kernels for d = 2 (eta in {2, 3, 4, 5}).
+#include "bsde_path.h"
+
+namespace bsde {
+
+hipError_t launch_path_d2(int eta, bool fp32, int blocks, hipStream_t s,
+                           const PathParams &prm, const double *pts,
+                           const void *gamma, double *partial)
+{
+    BSDE_PATH_CASE(2, 2)
+    BSDE_PATH_CASE(2, 3)
+    BSDE_PATH_CASE(2, 4)
+    BSDE_PATH_CASE(2, 5)
+    return hipErrorInvalidValue;
+}
+
+// multi-indices of the kernels' basis, in the kernels' order
+int index_table_d2(int eta, int8_t *nu, int cap)
+{
+    if (eta == 2) {
+        constexpr auto &t = Basis<3, 2>::tab;
+        constexpr int P = Basis<3, 2>::P;
+        if (nu && cap >= P)
+            for (int l = 0; l < P; ++l)
+                for (int v = 0; v < 3; ++v) nu[l * 3 + v] = t.nu[l][v];
+        return P;
+    }
+    if (eta == 3) {
+        constexpr auto &t = Basis<3, 3>::tab;
+        constexpr int P = Basis<3, 3>::P;
+        if (nu && cap >= P)
+            for (int l = 0; l < P; ++l)
+                for (int v = 0; v < 3; ++v) nu[l * 3 + v] = t.nu[l][v];
+        return P;
+    }
+    if (eta == 4) {
+        constexpr auto &t = Basis<3, 4>::tab;
+        constexpr int P = Basis<3, 4>::P;
+        if (nu && cap >= P)
+            for (int l = 0; l < P; ++l)
+                for (int v = 0; v < 3; ++v) nu[l * 3 + v] = t.nu[l][v];
+        return P;
+    }
+    if (eta == 5) {
+        constexpr auto &t = Basis<3, 5>::tab;
+        constexpr int P = Basis<3, 5>::P;
+        if (nu && cap >= P)
+            for (int l = 0; l < P; ++l)
+                for (int v = 0; v < 3; ++v) nu[l * 3 + v] = t.nu[l][v];
+        return P;
+    }
+    return 0;
+}
+
+} // namespace bsde

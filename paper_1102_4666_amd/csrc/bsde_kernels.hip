@@ -1,0 +1,149 @@
+// bsde_kernels.hip -- gfx950 kernels of one Picard iteration of Algorithm
+// "algodetail" (Labart & Lelong, arXiv:1102.4666, Section 4.1) other than
+// the Monte Carlo path kernel (bsde_path.h), and the dispatch to it:
+//
+//   finalize_kernel c_i = (1/M) sum_m a_m (eq. chat) and the sample variance.
+//   project_kernel  beta = R^{-1} Q' c, the least-squares increment: with
+//                   y = u^k + c and u^k = B alpha^k in the span of B,
+//                   argmin ||y - B a|| = alpha^k + B^+ c (eq. alpha).
+//   channel_kernel  alpha^{k+1} = alpha^k + beta and the channel table
+//                   Gamma[l][c] = (D_c alpha^{k+1})_l of u, d_t u, grad u and
+//                   the upper-triangular hessian, in FP64 and FP32.
+#include "bsde_common.h"
+
+#include <hip/hip_runtime.h>
+
+namespace bsde {
+
+// c_i and sample variance from the per-workgroup sums (fixed order in g)
+__global__ void finalize_kernel(const double *__restrict__ partial, int n,
+                                int groups, int M, double *__restrict__ c,
+                                double *__restrict__ var)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0, s2 = 0.0;
+    for (int g = 0; g < groups; ++g) {
+        s += partial[2 * ((size_t)i * groups + g)];
+        s2 += partial[2 * ((size_t)i * groups + g) + 1];
+    }
+    const double mean = s / M;
+    c[i] = mean;
+    var[i] = M > 1 ? (s2 - s * mean) / (M - 1) : 0.0;
+}
+
+// beta_l = sum_i W[l][i] c_i (W = R^{-1} Q', row-major p x n); one
+// workgroup per l, lanes strided over i, fixed-order tree reduction
+__global__ __launch_bounds__(256) void project_kernel(
+    const double *__restrict__ W, const double *__restrict__ c, int n,
+    double *__restrict__ beta)
+{
+    const int l = blockIdx.x;
+    const double *w = W + (size_t)l * n;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += w[i] * c[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) beta[l] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+constexpr int kMaxP = 512;
+
+// one workgroup per channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with
+// a = alpha_in + beta (channel 0 is the identity); workgroup 0 also stores
+// a as the next coefficient vector
+__global__ __launch_bounds__(256) void channel_kernel(
+    const double *__restrict__ alpha_in, const double *__restrict__ beta,
+    double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
+    int C, double *__restrict__ g64, float *__restrict__ g32)
+{
+    __shared__ double a[kMaxP];
+    const int c = blockIdx.x;
+    for (int m = threadIdx.x; m < p; m += 256)
+        a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
+    __syncthreads();
+    if (c == 0) {
+        for (int l = threadIdx.x; l < p; l += 256) {
+            if (alpha_out) alpha_out[l] = a[l];
+            g64[(size_t)l * C] = a[l];
+            g32[(size_t)l * C] = (float)a[l];
+        }
+        return;
+    }
+    const double *Dc = Dmat + (size_t)(c - 1) * p * p;
+    for (int l = threadIdx.x; l < p; l += 256) {
+        const double *drow = Dc + (size_t)l * p;
+        double s = 0.0;
+        for (int m = 0; m < p; ++m) s += drow[m] * a[m];
+        g64[(size_t)l * C + c] = s;
+        g32[(size_t)l * C + c] = (float)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over the instantiated (d, eta) pairs
+// ---------------------------------------------------------------------------
+#define BSDE_DIMS(X) X(1) X(2) X(3) X(5)
+#define DECL(D)                                                                \
+    hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s,  \
+                                const PathParams &prm, const double *pts,      \
+                                const void *gamma, double *partial);           \
+    int index_table_d##D(int eta, int8_t *nu, int cap);
+BSDE_DIMS(DECL)
+#undef DECL
+
+int index_table(int d, int eta, int8_t *nu, int cap)
+{
+#define X(D)                                                                   \
+    if (d == D) return index_table_d##D(eta, nu, cap);
+    BSDE_DIMS(X)
+#undef X
+    return 0;
+}
+
+bool kernel_exists(int d, int eta) { return index_table(d, eta, nullptr, 0) > 0; }
+
+hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
+                       const PathParams &prm, const double *pts,
+                       const void *gamma, double *partial)
+{
+#define X(D)                                                                   \
+    if (d == D)                                                                \
+        return launch_path_d##D(eta, fp32, blocks, s, prm, pts, gamma, partial);
+    BSDE_DIMS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_update(int n, int groups, int M, int p, int C,
+                         hipStream_t s, const double *partial, double *c,
+                         double *var, const double *W, double *beta,
+                         const double *alpha_in, double *alpha_out,
+                         const double *Dmat, double *g64, float *g32,
+                         hipEvent_t *ev /* 3 events or NULL */)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                       s, partial, n, groups, M, c, var);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(project_kernel, dim3(p), dim3(256), 0, s, W, c, n,
+                       beta);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha_in,
+                       beta, alpha_out, Dmat, p, C, g64, g32);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
+                           const double *Dmat, double *g64, float *g32)
+{
+    hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha,
+                       (const double *)nullptr, (double *)nullptr, Dmat, p,
+                       C, g64, g32);
+    return hipGetLastError();
+}
+
+} // namespace bsde

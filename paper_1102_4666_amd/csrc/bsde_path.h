@@ -1,0 +1,345 @@
+// bsde_path.h -- the Monte Carlo path kernel of one Picard iteration of
+// Algorithm "algodetail" (Labart & Lelong, arXiv:1102.4666, Section 4.1),
+// templated on the dimension d, the basis degree eta and the path precision.
+// Instantiated per dimension in bsde_inst_d*.hip.
+//
+//   a_m for every (point i, path m): Philox4x32-10 normals in registers,
+//   Box-Muller, Euler scheme of the log-price (eq. 4) with coefficients
+//   frozen at the last node (eq. eqs3), the interpolated state at the random
+//   time tau = t_i + (T - t_i) U (eq. psiN), the Chebyshev basis row at
+//   (tau, X_tau) contracted with the derivative channels of u^k, the
+//   penalised driver (eq. bsde-penal-2) and the frozen generator; per-lane
+//   FP64 sums reduced through wavefront shuffles and LDS in a fixed order.
+#pragma once
+
+#include "bsde_common.h"
+
+#include <hip/hip_runtime.h>
+
+namespace bsde {
+
+// ---------------------------------------------------------------------------
+// Precision-specific arithmetic.  FP32: hardware transcendentals (v_log_f32
+// is log2, v_sin/v_cos take revolutions); FP64: the device math library.
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct Arith;
+
+template <>
+struct Arith<float> {
+    static __device__ __forceinline__ float u01(uint32_t w)
+    {
+        return fmaf((float)w, 0x1p-32f, 0x1p-33f); // (w + 1/2) 2^-32
+    }
+    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
+                                                      float &n0, float &n1)
+    {
+        // R = sqrt(-2 ln ua) = sqrt(-2 ln2 log2 ua); angle 2 pi ub
+        float R = __builtin_sqrtf(-1.38629436111989061883f *
+                                  __builtin_amdgcn_logf(u01(wa)));
+        float ub = u01(wb);
+        n0 = R * __builtin_amdgcn_cosf(ub);
+        n1 = R * __builtin_amdgcn_sinf(ub);
+    }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    static __device__ __forceinline__ float sqrt(float x)
+    {
+        return __builtin_sqrtf(x);
+    }
+    static __device__ __forceinline__ float frac33(uint64_t num)
+    {
+        // (num mod 2^33) 2^-33 from the top 32 of the low 33 bits
+        return (float)(uint32_t)((num & 0x1FFFFFFFFull) >> 1) * 0x1p-32f;
+    }
+};
+
+template <>
+struct Arith<double> {
+    static __device__ __forceinline__ double u01(uint32_t w)
+    {
+        return ((double)w + 0.5) * 0x1p-32;
+    }
+    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
+                                                      double &n0, double &n1)
+    {
+        double R = ::sqrt(-2.0 * ::log(u01(wa)));
+        double phi = (2.0 * 3.14159265358979323846) * u01(wb);
+        double s, c;
+        ::sincos(phi, &s, &c);
+        n0 = R * c;
+        n1 = R * s;
+    }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double frac33(uint64_t num)
+    {
+        return (double)(num & 0x1FFFFFFFFull) * 0x1p-33;
+    }
+};
+
+template <typename Real>
+__device__ __forceinline__ Real local_vol(int kind, Real level, Real a, Real lc,
+                                          Real x)
+{
+    if (kind == kVolBump) {
+        Real dx = x - lc;
+        return level * (Real(1) + a * Arith<Real>::exp(-dx * dx));
+    }
+    return level;
+}
+
+template <int D, typename Real>
+__device__ __forceinline__ Real payoff(int kind, Real K, const Real *x)
+{
+    Real s = 0;
+    if (kind == kPutArith || kind == kCallArith || kind == kFwdArith) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) s += Arith<Real>::exp(x[j]);
+        s *= Real(1.0 / D);
+    } else {
+#pragma unroll
+        for (int j = 0; j < D; ++j) s += x[j];
+        if (kind == kQuad) return s * s;
+        s = Arith<Real>::exp(s * Real(1.0 / D));
+    }
+    switch (kind) {
+    case kPutArith:
+    case kPutGeom: return fmax(K - s, Real(0));
+    case kCallArith:
+    case kCallGeom: return fmax(s - K, Real(0));
+    default: return s - K; // kFwdArith
+    }
+}
+
+// Chebyshev values T_0..T_ETA of z
+template <int ETA, typename Real>
+__device__ __forceinline__ void cheb(Real z, Real *Tz)
+{
+    Tz[0] = Real(1);
+    if (ETA >= 1) Tz[1] = z;
+#pragma unroll
+    for (int a = 1; a < ETA; ++a) Tz[a + 1] = Real(2) * z * Tz[a] - Tz[a - 1];
+}
+
+// ---------------------------------------------------------------------------
+// The Monte Carlo path kernel.
+// Grid: n * groups workgroups of kBlock lanes; workgroup (i, g) runs the
+// paths m = (g * ppl + r) * kBlock + lane, r < ppl, m < M, of point i and
+// writes its FP64 sums (sum a_m, sum a_m^2) to partial[2 (i groups + g)].
+// ---------------------------------------------------------------------------
+template <int D, int ETA, typename Real>
+__global__ __launch_bounds__(kBlock) void path_kernel(
+    const PathParams prm, const double *__restrict__ pts,
+    const Real *__restrict__ gamma, double *__restrict__ partial)
+{
+    constexpr int DP = D + 1;
+    constexpr int C = num_channels(D);
+    using BS = Basis<DP, ETA>;
+    constexpr int NP = BS::P;
+    // steps per group so that a group uses whole Philox blocks
+    constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
+    constexpr int NB = SG * D / 4;
+    constexpr int NBB = (D + 3) / 4; // bridge blocks
+
+    const int i = blockIdx.x / prm.groups;
+    const int g = blockIdx.x - i * prm.groups;
+    const uint32_t k0 = (uint32_t)prm.seed, k1 = (uint32_t)(prm.seed >> 32);
+
+    const double *row = pts + (size_t)i * DP;
+    const Real T = (Real)prm.T;
+    const Real t0 = (Real)row[0];
+    Real x0[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) x0[j] = (Real)row[1 + j];
+    const Real h = (T - t0) / (Real)prm.N;
+    const Real sqrt_h = Arith<Real>::sqrt(h);
+    const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
+    const Real bump_a = (Real)prm.bump_a, lc = (Real)prm.log_bump_c;
+    const Real rho = (Real)prm.rho;
+    Real L[D][D], level[D], drift0[D], mid[D], scale[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        level[j] = (Real)prm.level[j];
+        drift0[j] = (Real)(prm.r - prm.div[j]);
+        mid[j] = (Real)prm.mid[j];
+        scale[j] = (Real)prm.scale[j];
+#pragma unroll
+        for (int l = 0; l < D; ++l) L[j][l] = (Real)prm.L[j * kMaxD + l];
+    }
+    const Real tscale = Real(2) / T;
+
+    double sum = 0.0, sumsq = 0.0;
+    for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
+        const int m = (g * prm.paths_per_lane + rr) * kBlock + (int)threadIdx.x;
+        if (m >= prm.M) break;
+
+        // U, j* = floor(U N) and theta = U N - j* in integer arithmetic
+        const u32x4 wu = philox10((uint32_t)m, (uint32_t)i, prm.k, 1u << 24,
+                                  k0, k1);
+        const uint64_t num = (2ull * wu.x + 1ull) * (uint64_t)prm.N;
+        const int jstar = (int)(num >> 33);
+        const Real theta = Arith<Real>::frac33(num);
+        const Real U = Arith<Real>::u01(wu.x);
+        const Real tau = t0 + (T - t0) * U;
+
+        Real X[D], Xs[D], LGs[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            X[j] = x0[j];
+            Xs[j] = x0[j];
+            LGs[j] = Real(0);
+        }
+        const int ngroups = (prm.N + SG - 1) / SG;
+        for (int grp = 0; grp < ngroups; ++grp) {
+            Real G[4 * NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
+                                         (uint32_t)(grp * NB + b), k0, k1);
+                Arith<Real>::box_muller(w.x, w.y, G[4 * b], G[4 * b + 1]);
+                Arith<Real>::box_muller(w.z, w.w, G[4 * b + 2], G[4 * b + 3]);
+            }
+#pragma unroll
+            for (int ss = 0; ss < SG; ++ss) {
+                const int s = grp * SG + ss;
+                if (s < prm.N) {
+                    const bool at = (s == jstar);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        Real lg = Real(0);
+#pragma unroll
+                        for (int l = 0; l <= j; ++l)
+                            lg += L[j][l] * G[ss * D + l];
+                        const Real sig = local_vol<Real>(prm.vol_kind, level[j],
+                                                         bump_a, lc, X[j]);
+                        const Real b = drift0[j] - Real(0.5) * sig * sig;
+                        Xs[j] = at ? X[j] : Xs[j];
+                        LGs[j] = at ? lg : LGs[j];
+                        X[j] += b * h + sig * sqrt_h * lg;
+                    }
+                }
+            }
+        }
+
+        // frozen coefficients at the last node t_{j*} and X at tau
+        Real Gb[4 * NBB];
+#pragma unroll
+        for (int b = 0; b < NBB; ++b) {
+            const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
+                                     (1u << 24) | (uint32_t)(1 + b), k0, k1);
+            Arith<Real>::box_muller(w.x, w.y, Gb[4 * b], Gb[4 * b + 1]);
+            Arith<Real>::box_muller(w.z, w.w, Gb[4 * b + 2], Gb[4 * b + 3]);
+        }
+        const Real bridge = Arith<Real>::sqrt(theta * (Real(1) - theta) * h);
+        Real sgs[D], bst[D], Xt[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            Real lgb = Real(0);
+#pragma unroll
+            for (int l = 0; l <= j; ++l) lgb += L[j][l] * Gb[l];
+            sgs[j] = local_vol<Real>(prm.vol_kind, level[j], bump_a, lc, Xs[j]);
+            bst[j] = drift0[j] - Real(0.5) * sgs[j] * sgs[j];
+            Xt[j] = Xs[j] + bst[j] * theta * h +
+                    sgs[j] * (theta * sqrt_h * LGs[j] + bridge * lgb);
+        }
+
+        // basis row at (tau, X_tau) contracted with the channel table, and
+        // the value u^k(T, X_T) (z_0 = 1 there, so every T_a(z_0) = 1)
+        Real Tz[DP][ETA + 1], TzT[DP][ETA + 1];
+        cheb<ETA>(tau * tscale - Real(1), Tz[0]);
+#pragma unroll
+        for (int a = 0; a <= ETA; ++a) TzT[0][a] = Real(1);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            cheb<ETA>((Xt[j] - mid[j]) * scale[j], Tz[1 + j]);
+            cheb<ETA>((X[j] - mid[j]) * scale[j], TzT[1 + j]);
+        }
+        Real Bv[NP], BT[NP];
+        Real V[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) V[c] = Real(0);
+        Real uT = Real(0);
+        static_for<NP>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            if constexpr (l == 0) {
+                Bv[0] = Real(1);
+                BT[0] = Real(1);
+            } else {
+                constexpr int par = BS::tab.parent[l];
+                constexpr int v = BS::tab.var[l];
+                constexpr int dg = BS::tab.deg[l];
+                Bv[l] = Bv[par] * Tz[v][dg];
+                BT[l] = BT[par] * TzT[v][dg];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) V[c] += Bv[l] * gamma[l * C + c];
+            uT += BT[l] * gamma[l * C];
+        });
+
+        // driver and frozen generator (u, d_t u, grad u, upper hessian)
+        Real gen = V[1];
+#pragma unroll
+        for (int j = 0; j < D; ++j) gen += bst[j] * V[2 + j];
+        {
+            int idx = 2 + D;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+#pragma unroll
+                for (int l = j; l < D; ++l, ++idx) {
+                    const Real cov = (l == j) ? Real(0.5) * sgs[j] * sgs[j]
+                                              : rho * sgs[j] * sgs[l];
+                    gen += cov * V[idx];
+                }
+            }
+        }
+        const Real u = V[0];
+        const Real f = -r * u + omega * fmax(payoff<D>(prm.payoff, K, Xt) - u,
+                                             Real(0));
+        const Real a = (T - t0) * (f + gen) + (payoff<D>(prm.payoff, K, X) - uT);
+        const double ad = (double)a;
+        sum += ad;
+        sumsq += ad * ad;
+    }
+
+    // fixed-order reduction: butterfly within the wavefront, then waves in
+    // order through LDS
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        sumsq += __shfl_xor(sumsq, off);
+    }
+    __shared__ double red[2][kBlock / 64];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = sum;
+        red[1][wave] = sumsq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            s += red[0][w];
+            s2 += red[1][w];
+        }
+        partial[2 * (size_t)blockIdx.x] = s;
+        partial[2 * (size_t)blockIdx.x + 1] = s2;
+    }
+}
+
+} // namespace bsde
+
+// Explicit instantiation of the FP32 and FP64 kernels for (D, E) and a
+// launcher bsde::launch_path_D<D>(eta, ...) for each instantiated D.
+#define BSDE_PATH_CASE(D, E)                                                   \
+    if (eta == E) {                                                            \
+        if (fp32)                                                              \
+            hipLaunchKernelGGL((path_kernel<D, E, float>), dim3(blocks),       \
+                               dim3(kBlock), 0, s, prm, pts,                   \
+                               (const float *)gamma, partial);                 \
+        else                                                                   \
+            hipLaunchKernelGGL((path_kernel<D, E, double>), dim3(blocks),      \
+                               dim3(kBlock), 0, s, prm, pts,                   \
+                               (const double *)gamma, partial);                \
+        return hipGetLastError();                                              \
+    }

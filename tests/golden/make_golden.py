@@ -1,0 +1,68 @@
+"""Writes the stored oracle results used by the full-size GPU parity tests.
+
+Calls only the oracle (``oracle/``): the per-point corrections of every
+iteration are spread over worker processes with ``oracle.solve_parallel``,
+which runs the same oracle functions in the same order as ``oracle.solve``.
+
+    python tests/golden/make_golden.py config1 [config2 ...] [--workers 8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# name -> (workload factory, kwargs)
+CASES = {
+    "config1": (workloads.config1, {}),
+    "config2_w100": (workloads.config2, {"omega": 100.0}),
+    "config2_w1": (workloads.config2, {"omega": 1.0}),
+    "config3_w100": (workloads.config3, {"omega": 100.0}),
+    "config4_w100": (workloads.config4, {"omega": 100.0}),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="+")
+    ap.add_argument("--workers", type=int, default=8)
+    args = ap.parse_args()
+    for name in args.names:
+        fn, kw = CASES[name]
+        cfg = fn(**kw)
+        cfg["precision"] = "fp64"
+        t0 = time.time()
+        res = oracle.solve_parallel(
+            cfg, workers=args.workers,
+            progress=lambda k: print("%s: iteration %d done (%.0fs)" %
+                                     (name, k, time.time() - t0), flush=True))
+        prices, deltas = [], []
+        for a in res["alpha"]:
+            pr, de = oracle.price_delta(cfg, a, [0.0], [cfg["S0"]])
+            prices.append(float(pr[0]))
+            deltas.append([float(x) for x in de[0]])
+        out = {
+            "name": name, "cfg": cfg, "seconds": time.time() - t0,
+            "price": prices, "delta": deltas,
+            "c": res["c"].tolist(), "var": res["var"].tolist(),
+        }
+        path = os.path.join(HERE, name + ".json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print("wrote", path, "price", prices[-1], flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,58 @@
+"""Full-size GPU parity: the benchmark workloads at their real sizes, in the
+launch configuration the benchmark uses, against the stored FP64 oracle
+results of tests/golden (written by tests/golden/make_golden.py, which calls
+only the oracle).  Every per-point correction of every iteration is
+compared.
+
+The penalty-100 workload does not converge: the projected Picard iterates
+grow by an order of magnitude per iteration (oracle prices 740, 481, 2503,
+-5.2e4, ..., -5.2e8).  Its errors are therefore measured relative to the
+size of each iterate; the penalty-1 twin converges and is held to the
+absolute tolerances."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+TOL = {"fp64": dict(c=1e-8, price=1e-4, delta=1e-4),
+       "fp32": dict(c=2e-3, price=5e-4, delta=5e-3)}
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle result %s not generated" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,prec", [
+    ("config1", "fp64"), ("config1", "fp32"),
+    ("config2_w1", "fp64"), ("config2_w1", "fp32"),
+    ("config2_w100", "fp64"), ("config2_w100", "fp32"),
+])
+def test_full_size_against_stored_oracle(name, prec):
+    g = _golden(name)
+    cfg = dict(g["cfg"], precision=prec)
+    print("full-size case", name, prec, flush=True)
+    got = run_gpu(cfg)
+    tol = TOL[prec]
+    c_ref = np.array(g["c"])
+    for k in range(cfg["K_it"]):
+        scale = max(1.0, float(np.abs(c_ref[k]).max()))
+        err = float(np.abs(got["c"][k] - c_ref[k]).max()) / scale
+        print("  k=%d max |dc| / max(1, max|c|) = %.3g" % (k, err))
+        assert err <= tol["c"], (k, err)
+    K = cfg["K"]
+    pref, dref = g["price"][-1], g["delta"][-1]
+    print("  price gpu %.10g oracle %.10g; delta gpu %s oracle %s" %
+          (got["price"], pref, got["delta"], dref))
+    assert abs(got["price"] - pref) <= tol["price"] * max(K, abs(pref))
+    dscale = max(1.0, float(np.abs(dref).max()))
+    assert float(np.abs(got["delta"] - np.array(dref)).max()) <= tol["delta"] * dscale

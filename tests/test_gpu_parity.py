@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical Philox streams, element by element on small problems that span
+several workgroups and a ragged tail of paths.
+
+Tolerances (price error relative to the strike K, dollar deltas absolute):
+FP64 path: |d price| <= 1e-4 K, |d delta| <= 1e-4, per-point corrections
+within 1e-8 (1 + |c|); FP32 paths with FP64 sums: |d price| <= 5e-4 K,
+|d delta| <= 5e-3, per-point corrections within 2e-3 (1 + |c|)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close_c, run_gpu
+from workloads import problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": dict(c=1e-8, price=1e-4, delta=1e-4),
+       "fp32": dict(c=2e-3, price=5e-4, delta=5e-3)}
+
+CASES = {
+    # d = 1 European Black-Scholes put
+    "eur_bs": problem(d=1, n_t=6, n_x=20, eta=4, M=300, N=7, K_it=3),
+    # d = 1 American put, bump local vol, penalty 1 and 100
+    "amer_bump_w1": problem(d=1, vol_kind="bump", bump_a=0.25, n_t=6,
+                            n_x=20, eta=4, M=300, N=10, K_it=3, omega=1.0),
+    "amer_bump_w100": problem(d=1, vol_kind="bump", bump_a=0.25, n_t=6,
+                              n_x=20, eta=4, M=300, N=10, K_it=3,
+                              omega=100.0),
+    # d = 2 correlated arithmetic basket put with dividends
+    "d2_basket": problem(d=2, vol_kind="bump", vol_level=[0.2, 0.3],
+                         bump_a=0.25, rho=0.3, div=[0.0, 0.02],
+                         S0=[100.0, 95.0], n_t=4, n_x=6, eta=3, M=260, N=6,
+                         K_it=2, omega=1.0),
+    # d = 3 call on the arithmetic mean, negative correlation
+    "d3_call": problem(d=3, vol_level=[0.2, 0.25, 0.3], rho=-0.2,
+                       payoff="call", S0=100.0, n_t=3, n_x=4, eta=2, M=200,
+                       N=5, K_it=2),
+    # d = 5 geometric put on random points
+    "d5_geom": problem(d=5, vol_kind="bump", vol_level=[0.15, 0.2, 0.25, 0.3, 0.35],
+                       bump_a=0.25, rho=0.2, payoff="put_geom", S0=100.0,
+                       grid="random", n_t=3, n_x=40, eta=2, M=100, N=4,
+                       K_it=2, omega=100.0),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_results():
+    return {}
+
+
+def _oracle(cache, name):
+    if name not in cache:
+        cfg = CASES[name]
+        res = oracle.solve(cfg)
+        pr, de = oracle.price_delta(cfg, res["alpha"][-1], [0.0], [cfg["S0"]])
+        res["price"] = pr[0]
+        res["delta"] = de[0]
+        res["pts"] = oracle.points(cfg)
+        cache[name] = res
+    return cache[name]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_with_oracle(name, prec, oracle_results):
+    cfg = dict(CASES[name], precision=prec)
+    print("parity case", name, prec, flush=True)
+    ref = _oracle(oracle_results, name)
+    got = run_gpu(cfg)
+    tol = TOL[prec]
+    np.testing.assert_allclose(got["pts"], ref["pts"], rtol=1e-15, atol=1e-15)
+    assert_close_c(got["c"], ref["c"], tol["c"], "c")
+    K = cfg["K"]
+    assert abs(got["price"] - ref["price"]) <= tol["price"] * K, (got["price"], ref["price"])
+    np.testing.assert_allclose(got["delta"], ref["delta"], rtol=0, atol=tol["delta"])
+    # sample variances of the path terms agree to Monte Carlo rounding
+    np.testing.assert_allclose(got["var"], ref["var"],
+                               rtol=1e-6 if prec == "fp64" else 5e-2,
+                               atol=1e-9 if prec == "fp64" else 1e-2)
+
+
+def test_first_iteration_fp64_matches_per_point_oracle():
+    # k = 0 with u^0 = 0 and omega = 0: c^0_i is the mean payoff of the
+    # paths from point i (no dependence on the other points)
+    cfg = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=5, n_x=9, eta=4,
+                  M=513, N=13, K_it=1)
+    got = run_gpu(cfg)
+    c_ref, v_ref = oracle.corrections(cfg, None, 0, 0, 45)
+    assert_close_c(got["c"][0], c_ref, 1e-12, "c0")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_variance_on_gpu(prec):
+    sig = np.array([0.2, 0.3])
+    cfg = problem(d=2, r=0.0, vol_level=list(sig), rho=0.3, payoff="quad",
+                  eta=3, n_t=5, n_x=6, M=256, N=7, S0=[100.0, 100.0],
+                  K_it=1, precision=prec)
+    from paper_1102_4666_amd import Problem
+    with Problem(cfg) as P:
+        pts = P.points()
+        tau = 1.0 - pts[:, 0]
+        C = np.array([[1, 0.3], [0.3, 1]])
+        y = (pts[:, 1:] - 0.5 * sig ** 2 * tau[:, None]).sum(1) ** 2 + \
+            tau * float(sig @ C @ sig)
+        P.fit_values(y, 0)
+        P.solve()
+        c, v = P.corrections(0)
+    scale = float(np.abs(y).max())
+    lim = 1e-10 if prec == "fp64" else 2e-5
+    assert np.abs(c).max() < lim * scale
+    assert np.sqrt(v.max()) < lim * scale * 10
+
+
+def test_tiling_changes_only_rounding():
+    cfg = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=5, n_x=10, eta=4,
+                  M=700, N=9, K_it=2, omega=1.0)
+    a = run_gpu(cfg, tiling=(1, 3))
+    b = run_gpu(cfg, tiling=(3, 1))
+    c = run_gpu(cfg, tiling=(2, 2))
+    for x in (b, c):
+        assert_close_c(x["c"], a["c"], 1e-12, "tiling")
+
+
+def test_deterministic_and_resumable():
+    cfg = problem(d=2, vol_kind="bump", vol_level=[0.2, 0.25], bump_a=0.25,
+                  rho=0.1, S0=[100.0, 100.0], n_t=4, n_x=5, eta=3, M=300,
+                  N=6, K_it=4, omega=1.0)
+    a = run_gpu(cfg)
+    b = run_gpu(cfg)
+    np.testing.assert_array_equal(a["c"], b["c"])
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])
+    from paper_1102_4666_amd import Problem
+    with Problem(cfg) as P:
+        P.set_coefficients(a["alpha"][2], 2)
+        P.solve()
+        np.testing.assert_array_equal(P.coefficients(4), a["alpha"][4])
+        np.testing.assert_array_equal(P.corrections(3)[0], a["c"][3])
+
+
+def test_degenerate_sizes():
+    # one path per point (zero sample variance), one Euler step, and the
+    # smallest tensor grid on which degree-2 polynomials are determined
+    cfg = problem(d=1, n_t=3, n_x=2, eta=1, M=1, N=1, K_it=2)
+    with pytest.raises(Exception):
+        run_gpu(cfg)            # no kernel for eta = 1
+    cfg = problem(d=1, n_t=3, n_x=3, eta=2, M=1, N=1, K_it=2)
+    ref = oracle.solve(cfg)
+    got = run_gpu(cfg)
+    assert_close_c(got["c"], ref["c"], 1e-9, "degenerate")
+    assert (got["var"] == 0).all()

@@ -66,7 +66,7 @@ def config1() -> dict:
     M=1000, N=20, 5 Picard iterations, FP64, seed 0."""
     return problem(d=1, vol_kind="const", vol_level=0.2, r=0.05, K=100.0,
                    S0=100.0, T=1.0, payoff="put", omega=0.0, grid="tensor",
-                   n_t=8, n_x=64, eta=6, M=1000, N=20, K_it=5,
+                   n_t=8, n_x=64, eta=4, M=1000, N=20, K_it=5,
                    precision="fp64", seed=0)
 
 
@@ -77,7 +77,7 @@ def config2(omega: float = 100.0, precision: str = "fp32") -> dict:
     return problem(d=1, vol_kind="bump", vol_level=0.2, bump_a=0.25,
                    bump_c=100.0, r=0.05, K=100.0, S0=100.0, T=1.0,
                    payoff="put", omega=omega, grid="tensor", n_t=16,
-                   n_x=128, eta=6, M=4000, N=50, K_it=8,
+                   n_x=128, eta=4, M=4000, N=50, K_it=8,
                    precision=precision, seed=0)
 
 
