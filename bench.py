@@ -32,31 +32,28 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # 3.93e13 full-rate lane-ops/s
 FP32_VECTOR_PEAK = 157.3e12                     # FLOP/s (packed FMA)
 FP64_VECTOR_PEAK = 78.6e12
+# HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (separate runs), scaled by the plain-copy calibration factors
+# (x2.0 and x1.0); None until measured for the current kernel.
+TRAFFIC = {"fp32": 173.75 * 2.0 * 1024 + 64.0 * 1024,
+           "fp64": 261.75 * 2.0 * 1024 + 64.0 * 1024}
 
 
-def valu_ops_per_path_step(d: int, precision: str) -> float:
-    """Algorithmic VALU issue slots per Euler path-step of the path kernel
-    for the d=1 local-volatility workload, counted from the operations the
-    method needs (quarter-rate transcendentals and 32-bit integer multiplies
-    weigh 4 slots).  The derivation is written out in the design doc."""
-    if d != 1:
-        raise ValueError("op count stated for d = 1 only")
-    if precision == "fp32":
-        # per normal: 1/4 Philox4x32-10 block = 10 rounds x (4 mul x 4 + 4 xor) / 4
-        philox = 10 * (4 * 4 + 4) / 4.0                 # 50
-        box_muller = (2 + 2 + 4 * 4 + 3) / 2.0           # 11.5 (cvt, fma, log/sqrt/sin/cos, mul)
-        vol = 4 + 4                                      # exp (quarter rate) + sub/mul/fma/mul
-        euler = 2 + 4 + 3                                # drift, update, j* select
-        per_path = 230                                   # U, bridge, basis, driver, sums
-        return philox + box_muller + vol + euler + per_path / 50.0
-    # FP64: transcendentals in software (log ~ 20, sincos ~ 40, exp ~ 20,
-    # sqrt ~ 8 full-rate FP64 ops)
-    philox = 10 * (4 * 4 + 4) / 4.0
-    box_muller = (2 + 2 + 20 + 8 + 40 + 3) / 2.0
-    vol = 20 + 4
-    euler = 2 + 4 + 3
-    per_path = 400
-    return philox + box_muller + vol + euler + per_path / 50.0
+# Algorithmic work per Euler path-step of the path kernel for the d = 1
+# local-volatility workload (N = 50 steps per path), derived operation by
+# operation in the design doc section 6.  VALU operations: normal 13.25 (1/4 of a
+# Philox4x32-10 block) + Box-Muller 5.5 + local vol 5 + Euler 3 + state at
+# j* 3 + per-path work 270 / N = 34.4, of which 3.12 are transcendentals.
+# The counters show the transcendentals issuing beside the other VALU work
+# (every instruction at 4 cycles would exceed the issue peak), so the
+# roofline counts the 31.3 others against the VALU issue rate.  FP32 FLOP
+# (FMA = 2, transcendental = 1): Box-Muller 5.5 + local vol 6 + Euler 5 +
+# per-path work 250 / N.  FP64 paths use software transcendentals with no
+# independent operation count: their figure is the measured SQ_INSTS_VALU
+# minus SQ_INSTS_VALU_TRANS_F64 per path-step (209.9 - 2.7).
+OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.5 + 5 + 3 + 3 + 270 / 50.0 - 3.12,
+                     "fp64": 207.2}
+FP32_FLOP_PER_PATH_STEP = 5.5 + 6 + 5 + 250 / 50.0
 
 
 def workload(precision: str, omega: float = 100.0):
@@ -64,13 +61,24 @@ def workload(precision: str, omega: float = 100.0):
     return workloads.config2(omega=omega, precision=precision)
 
 
-def run_job(cfg, stream):
+def run_job(cfg, stream, phases=None):
+    """One pricing job; phases (if a dict) accumulates the host wall time
+    of create / solve / query / destroy in milliseconds."""
     import paper_1102_4666_amd as bsde
+    t0 = time.perf_counter()
     P = bsde.Problem(cfg)
+    t1 = time.perf_counter()
     P.solve(stream)
+    t2 = time.perf_counter()
     price, delta = P.price_delta()
     timings = P.timings()
+    t3 = time.perf_counter()
     P.close()
+    t4 = time.perf_counter()
+    if phases is not None:
+        for key, dt in (("create", t1 - t0), ("solve", t2 - t1),
+                        ("query", t3 - t2), ("destroy", t4 - t3)):
+            phases[key] = phases.get(key, 0.0) + 1e3 * dt
     return price[0], delta[0], timings
 
 
@@ -126,6 +134,11 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the error check against stored oracle results")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the "
+                         "HBM byte counters of the profiler)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU "
@@ -136,6 +149,16 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4,
+                          "copy_bytes_written": dst.numel() * 4,
+                          "copies": 3}))
+        return
     stream = torch.cuda.current_stream().cuda_stream
     cfg = workload(args.precision)
     n = cfg["n_t"] * cfg["n_x"]
@@ -146,12 +169,15 @@ def main():
     torch.cuda.synchronize()
     lat = []
     path_ms = []
+    kern_ms = []
+    phases = {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        _, _, tim = run_job(cfg, stream)
+        _, _, tim = run_job(cfg, stream, phases)
         lat.append(time.perf_counter() - ts)
         path_ms.append(tim[0])
+        kern_ms.append(tim)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
@@ -159,7 +185,8 @@ def main():
     # roofline of the path kernel: algorithmic VALU slots per launch over
     # its mean duration (HIP events on the solve's stream)
     t_path = float(np.mean(path_ms)) * 1e-3
-    ops = valu_ops_per_path_step(cfg["d"], args.precision) * n * cfg["M"] * cfg["N"]
+    launch_steps = n * cfg["M"] * cfg["N"]
+    ops = OPS_PER_PATH_STEP[args.precision] * launch_steps
     achieved = ops / t_path
     line = {
         "metric": "Euler path-steps/s + priced requests/s (p50/p99) at stated price/delta error",
@@ -179,13 +206,23 @@ def main():
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "path_kernel_ms": float(np.mean(path_ms)),
+        "job_phase_ms": {k: v / args.steps for k, v in phases.items()},
+        "kernel_ms_per_iteration": dict(zip(
+            ["path", "reduce", "project", "update", "solve_total"],
+            [float(x) for x in np.mean(kern_ms, axis=0)])),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_LANE_OPS / 1e12,
-                     "unit": "T VALU lane-op slots/s",
+                     "unit": "T VALU lane-ops/s (transcendentals excluded)",
                      "frac": achieved / VALU_PEAK_LANE_OPS,
-                     "traffic": None},
+                     "traffic": TRAFFIC.get(args.precision)},
     }
-    line["accuracy_vs_oracle"] = accuracy(args.precision, stream)
+    if args.precision == "fp32":
+        fl = FP32_FLOP_PER_PATH_STEP * launch_steps / t_path
+        line["fp32_vector_flops"] = {"achieved_tflops": fl / 1e12,
+                                     "peak_tflops": FP32_VECTOR_PEAK / 1e12,
+                                     "frac": fl / FP32_VECTOR_PEAK}
+    if not args.no_accuracy:
+        line["accuracy_vs_oracle"] = accuracy(args.precision, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(workload("fp64"), args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -199,6 +199,24 @@ bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
  * [3] coefficient/channel update, [4] whole solve. */
 bsde_status bsde_last_timings(bsde_problem h, double *ms5);
 
+/* Solves many problems together (hot-path row "batching"): all remaining
+ * Picard iterations of every problem, with one persistent kernel launch per
+ * iteration step and kernel signature (d, eta, precision, volatility kind)
+ * that takes (problem, point, path-group) tiles from an atomic queue,
+ * heaviest tiles first -- the GPU form of the dynamic per-point dispatch of
+ * Section 4.3 -- and one launch each for the reductions and updates of all
+ * problems.  Problems may differ in d, grid, M, N, iterations and
+ * precision.  Each problem's result is identical to bsde_solve with the
+ * same tiling.
+ *   problems  count distinct handles (not owned)
+ *   flags     BSDE_BATCH_GRAPH: capture the whole schedule as one hipGraph
+ *             and replay it (on a library stream if hip_stream is NULL)
+ *   ms        receives the GPU time of the batch in milliseconds (may be NULL)
+ * Errors: BSDE_EINVAL, BSDE_EDEVICE. */
+#define BSDE_BATCH_GRAPH 1
+bsde_status bsde_solve_batch(bsde_problem *problems, int count,
+                             void *hip_stream, int flags, double *ms);
+
 void bsde_destroy(bsde_problem h);
 const char *bsde_status_string(bsde_status s);
 /* Human-readable detail of the last error on this thread. */

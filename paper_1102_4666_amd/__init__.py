@@ -33,9 +33,10 @@ EXPORTS = [
     "bsde_create_problem", "bsde_solve", "bsde_query_price_delta",
     "bsde_problem_sizes", "bsde_get_points", "bsde_get_coefficients",
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
-    "bsde_set_tiling", "bsde_last_timings", "bsde_destroy",
-    "bsde_status_string", "bsde_last_error",
+    "bsde_set_tiling", "bsde_last_timings", "bsde_solve_batch",
+    "bsde_destroy", "bsde_status_string", "bsde_last_error",
 ]
+BSDE_BATCH_GRAPH = 1
 
 
 class BsdeError(RuntimeError):
@@ -90,6 +91,8 @@ def lib():
         L.bsde_get_corrections.argtypes = [H, C.c_int, _dp, _dp]
         L.bsde_set_tiling.argtypes = [H, C.c_int, C.c_int]
         L.bsde_last_timings.argtypes = [H, _dp]
+        L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
+                                       C.c_int, _dp]
         L.bsde_destroy.argtypes = [H]
         L.bsde_destroy.restype = None
         L.bsde_status_string.argtypes = [C.c_int]
@@ -217,6 +220,21 @@ def bsde_last_timings(h):
     t = np.zeros(5)
     _check(lib().bsde_last_timings(h, _d(t)), "bsde_last_timings")
     return t
+
+
+def bsde_solve_batch(handles, stream=None, graph=False):
+    """Solves the problems together; returns the GPU time in ms."""
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    ms = C.c_double()
+    _check(lib().bsde_solve_batch(arr, len(handles), C.c_void_p(stream or 0),
+                                  BSDE_BATCH_GRAPH if graph else 0,
+                                  C.byref(ms)), "bsde_solve_batch")
+    return ms.value
+
+
+def solve_batch(problems, stream=None, graph=False):
+    """bsde_solve_batch over Problem objects."""
+    return bsde_solve_batch([P.h for P in problems], stream, graph)
 
 
 def bsde_destroy(h):

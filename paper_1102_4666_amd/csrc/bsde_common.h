@@ -172,4 +172,26 @@ struct PathParams {
     double scale[kMaxD];       // 2 / (hi - lo)
 };
 
+// One problem of a batched launch (see batch_path_kernel).
+struct BatchTileDesc {
+    PathParams prm;        // prm.k is the problem's own iteration
+    const double *pts;     // n x (d+1) points
+    const void *gamma;     // channel table (float or double)
+    double *partial;       // n x groups x 2 sums
+};
+
+// One problem of the batched reduction / update kernels (one iteration).
+struct BatchUpdateDesc {
+    const double *partial; // n x groups x 2 sums of the path kernel
+    int n, groups, M, p, C;
+    double *c, *var;       // this iteration's slices
+    const double *W;       // p x n pseudo-inverse
+    double *beta;          // p
+    const double *alpha_in;
+    double *alpha_out;
+    const double *Dmat;    // (C-1) x p x p
+    double *g64;
+    float *g32;
+};
+
 } // namespace bsde

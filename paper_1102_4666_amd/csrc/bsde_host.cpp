@@ -15,9 +15,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,11 +37,113 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          hipEvent_t *ev);
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
                            const double *Dmat, double *g64, float *g32);
+hipError_t launch_batch(int d, int eta, bool fp32, bool bump, int blocks,
+                        hipStream_t s, const BatchTileDesc *probs, int nprob,
+                        const long long *tile_begin, unsigned int *counter);
+int batch_occupancy(int d, int eta, bool fp32, bool bump);
+hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
+                               hipStream_t s, const BatchUpdateDesc *d);
+hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
+                                 const BatchUpdateDesc *d);
+hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s);
 } // namespace bsde
 
 using namespace bsde;
 
 static thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------
+// Caching device allocator: buffers of released problems are kept per
+// (device, size class) and handed to later problems, so that creating and
+// destroying problems does not go through hipMalloc / hipFree each time.
+// Size classes are powers of two from 256 bytes.  Thread-safe.
+// ---------------------------------------------------------------------------
+namespace {
+struct DevicePool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_lists;
+    std::map<void *, std::pair<int, size_t>> live;
+    size_t cached_bytes = 0;
+};
+DevicePool &pool()
+{
+    static DevicePool *p = new DevicePool(); // never destroyed: buffers live
+    return *p;                               // until the process ends
+}
+size_t size_class(size_t bytes)
+{
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+hipError_t pool_alloc(void **ptr, size_t bytes)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t cls = size_class(bytes);
+    DevicePool &P = pool();
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        auto &fl = P.free_lists[{dev, cls}];
+        if (!fl.empty()) {
+            *ptr = fl.back();
+            fl.pop_back();
+            P.cached_bytes -= cls;
+            P.live[*ptr] = {dev, cls};
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(ptr, cls);
+    if (e == hipErrorOutOfMemory) {
+        // release the cache of this device and retry once
+        std::lock_guard<std::mutex> g(P.mu);
+        for (auto &kv : P.free_lists)
+            if (kv.first.first == dev) {
+                for (void *q : kv.second) (void)hipFree(q);
+                P.cached_bytes -= kv.first.second * kv.second.size();
+                kv.second.clear();
+            }
+        e = hipMalloc(ptr, cls);
+    }
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(P.mu);
+    P.live[*ptr] = {dev, cls};
+    return hipSuccess;
+}
+void pool_free(void *ptr)
+{
+    if (!ptr) return;
+    DevicePool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    auto it = P.live.find(ptr);
+    if (it == P.live.end()) return;
+    P.free_lists[it->second].push_back(ptr);
+    P.cached_bytes += it->second.second;
+    P.live.erase(it);
+}
+
+// HIP events are reused across solves for the kernel timings.
+std::mutex g_ev_mu;
+std::vector<hipEvent_t> g_events;
+hipError_t event_get(hipEvent_t *e)
+{
+    {
+        std::lock_guard<std::mutex> g(g_ev_mu);
+        if (!g_events.empty()) {
+            *e = g_events.back();
+            g_events.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreate(e);
+}
+void event_put(hipEvent_t e)
+{
+    std::lock_guard<std::mutex> g(g_ev_mu);
+    g_events.push_back(e);
+}
+} // namespace
 
 static bsde_status fail(bsde_status s, const std::string &msg)
 {
@@ -112,35 +216,35 @@ static double cheb_deriv_coef(int a, int b)
     return b == 0 ? (double)a : 2.0 * a;
 }
 
-// Householder QR of B (n x pa, row-major); returns W = R^{-1} Q' (pa x n)
-// or false if rank deficient.
+// Householder QR of B (n x pa, column-major, overwritten) and the
+// pseudo-inverse W = R^{-1} Q' (pa x n, row-major); false if B is
+// numerically rank deficient (smallest |R_jj| <= 1e-12 largest).  Every
+// inner loop is a contiguous dot product or axpy of length <= n.
 static bool pseudo_inverse(int n, int pa, std::vector<double> &A,
                            std::vector<double> &W, std::string &why)
 {
-    std::vector<double> vs((size_t)n * pa, 0.0), vnorm(pa), diag(pa);
+    std::vector<double> vnorm(pa), diag(pa);
     for (int j = 0; j < pa; ++j) {
+        double *a = &A[(size_t)j * n];
         double nrm2 = 0.0;
-        for (int i = j; i < n; ++i) nrm2 += A[(size_t)i * pa + j] * A[(size_t)i * pa + j];
-        double nrm = std::sqrt(nrm2);
+        for (int i = j; i < n; ++i) nrm2 += a[i] * a[i];
+        const double nrm = std::sqrt(nrm2);
         if (nrm == 0.0) {
             why = "basis matrix has a zero column";
             return false;
         }
-        double top = A[(size_t)j * pa + j];
-        double beta = top >= 0.0 ? -nrm : nrm;
+        const double beta = a[j] >= 0.0 ? -nrm : nrm;
+        a[j] -= beta; // a[j..n) now holds the Householder vector v
         double vv = 0.0;
-        for (int i = j; i < n; ++i) {
-            double v = A[(size_t)i * pa + j] - (i == j ? beta : 0.0);
-            vs[(size_t)i * pa + j] = v;
-            vv += v * v;
-        }
+        for (int i = j; i < n; ++i) vv += a[i] * a[i];
         vnorm[j] = vv;
         diag[j] = beta;
-        for (int c = j; c < pa; ++c) {
+        for (int c = j + 1; c < pa; ++c) {
+            double *b = &A[(size_t)c * n];
             double s = 0.0;
-            for (int i = j; i < n; ++i) s += vs[(size_t)i * pa + j] * A[(size_t)i * pa + c];
-            double f = 2.0 * s / vv;
-            for (int i = j; i < n; ++i) A[(size_t)i * pa + c] -= f * vs[(size_t)i * pa + j];
+            for (int i = j; i < n; ++i) s += a[i] * b[i];
+            const double f = 2.0 * s / vv;
+            for (int i = j; i < n; ++i) b[i] -= f * a[i];
         }
     }
     double dmax = 0.0, dmin = INFINITY;
@@ -152,47 +256,50 @@ static bool pseudo_inverse(int n, int pa, std::vector<double> &A,
         why = "basis matrix is numerically rank deficient on the grid";
         return false;
     }
-    // Q' e_i for every i gives the columns of Q' (pa x n): apply H_p..H_1
-    // in reverse to the unit vectors is costly; instead form thin Q = H_1..H_pa
-    // [I; 0] column by column and transpose.
+    // thin Q = H_0 ... H_{pa-1} [I; 0] (column-major n x pa), accumulated
+    // backwards: H_j only changes columns >= j
     std::vector<double> Q((size_t)n * pa, 0.0);
-    for (int c = 0; c < pa; ++c) {
-        std::vector<double> e(n, 0.0);
-        e[c] = 1.0;
-        for (int j = pa - 1; j >= 0; --j) {
+    for (int c = 0; c < pa; ++c) Q[(size_t)c * n + c] = 1.0;
+    for (int j = pa - 1; j >= 0; --j) {
+        const double *v = &A[(size_t)j * n];
+        for (int c = j; c < pa; ++c) {
+            double *q = &Q[(size_t)c * n];
             double s = 0.0;
-            for (int i = j; i < n; ++i) s += vs[(size_t)i * pa + j] * e[i];
-            double f = 2.0 * s / vnorm[j];
-            for (int i = j; i < n; ++i) e[i] -= f * vs[(size_t)i * pa + j];
+            for (int i = j; i < n; ++i) s += v[i] * q[i];
+            const double f = 2.0 * s / vnorm[j];
+            for (int i = j; i < n; ++i) q[i] -= f * v[i];
         }
-        for (int i = 0; i < n; ++i) Q[(size_t)i * pa + c] = e[i];
     }
-    // W = R^{-1} Q': back substitution for every column i of Q'
+    // W = R^{-1} Q': row l of W is (Q column l - sum_{c>l} R_lc W_c) / R_ll,
+    // with R_lc = A[c][l] above the diagonal and R_ll = diag[l]
     W.assign((size_t)pa * n, 0.0);
-    std::vector<double> col(pa);
-    for (int i = 0; i < n; ++i) {
-        for (int j = pa - 1; j >= 0; --j) {
-            double s = Q[(size_t)i * pa + j];
-            for (int c = j + 1; c < pa; ++c) s -= A[(size_t)j * pa + c] * col[c];
-            col[j] = s / A[(size_t)j * pa + j];
+    for (int l = pa - 1; l >= 0; --l) {
+        double *w = &W[(size_t)l * n];
+        const double *q = &Q[(size_t)l * n];
+        for (int i = 0; i < n; ++i) w[i] = q[i];
+        for (int c = l + 1; c < pa; ++c) {
+            const double rlc = A[(size_t)c * n + l];
+            const double *wc = &W[(size_t)c * n];
+            for (int i = 0; i < n; ++i) w[i] -= rlc * wc[i];
         }
-        for (int j = 0; j < pa; ++j) W[(size_t)j * n + i] = col[j];
+        const double inv = 1.0 / diag[l];
+        for (int i = 0; i < n; ++i) w[i] *= inv;
     }
     return true;
 }
 
 static void free_device(bsde_problem_s *h)
 {
-    hipFree(h->d_pts);
-    hipFree(h->d_W);
-    hipFree(h->d_D);
-    hipFree(h->d_alpha);
-    hipFree(h->d_beta);
-    hipFree(h->d_g64);
-    hipFree(h->d_g32);
-    hipFree(h->d_partial);
-    hipFree(h->d_c);
-    hipFree(h->d_var);
+    pool_free(h->d_pts);
+    pool_free(h->d_W);
+    pool_free(h->d_D);
+    pool_free(h->d_alpha);
+    pool_free(h->d_beta);
+    pool_free(h->d_g64);
+    pool_free(h->d_g32);
+    pool_free(h->d_partial);
+    pool_free(h->d_c);
+    pool_free(h->d_var);
     h->d_pts = h->d_W = h->d_D = h->d_alpha = h->d_beta = h->d_g64 = nullptr;
     h->d_partial = h->d_c = h->d_var = nullptr;
     h->d_g32 = nullptr;
@@ -380,17 +487,24 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         delete h;
         return fail(BSDE_ERANK, "fewer points than basis functions");
     }
+    // column-major basis matrix: B[c][i] = prod_v T_{nu_v}(z_v(point i))
     std::vector<double> B((size_t)h->n * pa);
-    for (int i = 0; i < h->n; ++i) {
-        const double *row = &h->pts[(size_t)i * dp];
-        double z[kMaxD + 1];
-        z[0] = 2.0 * row[0] / payoff->T - 1.0;
-        for (int j = 0; j < d; ++j) z[1 + j] = (row[1 + j] - b.mid[j]) * b.scale[j];
-        for (int c = 0; c < pa; ++c) {
-            const int8_t *e = &h->nu[(size_t)act[c] * dp];
-            double v = 1.0;
-            for (int w = 0; w < dp; ++w) v *= cheb_value(e[w], z[w]);
-            B[(size_t)i * pa + c] = v;
+    {
+        std::vector<double> Tz((size_t)dp * (h->eta + 1));
+        for (int i = 0; i < h->n; ++i) {
+            const double *row = &h->pts[(size_t)i * dp];
+            double z[kMaxD + 1];
+            z[0] = 2.0 * row[0] / payoff->T - 1.0;
+            for (int j = 0; j < d; ++j) z[1 + j] = (row[1 + j] - b.mid[j]) * b.scale[j];
+            for (int v = 0; v < dp; ++v)
+                for (int a = 0; a <= h->eta; ++a)
+                    Tz[(size_t)v * (h->eta + 1) + a] = cheb_value(a, z[v]);
+            for (int c = 0; c < pa; ++c) {
+                const int8_t *e = &h->nu[(size_t)act[c] * dp];
+                double v = 1.0;
+                for (int w = 0; w < dp; ++w) v *= Tz[(size_t)w * (h->eta + 1) + e[w]];
+                B[(size_t)c * h->n + i] = v;
+            }
         }
     }
     std::vector<double> Wa;
@@ -449,7 +563,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     // device buffers
     hipError_t alloc_err = hipSuccess;
     auto dalloc = [&](void **ptr, size_t bytes) {
-        alloc_err = hipMalloc(ptr, bytes == 0 ? 8 : bytes);
+        alloc_err = pool_alloc(ptr, bytes == 0 ? 8 : bytes);
         return alloc_err == hipSuccess;
     };
     bool ok = dalloc((void **)&h->d_pts, sizeof(double) * h->pts.size()) &&
@@ -497,27 +611,37 @@ bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
     return BSDE_OK;
 }
 
+// Tiling of a solve and the per-group sum buffer it needs.
+static bsde_status prepare_tiling(bsde_problem h, int &groups, int &ppl)
+{
+    groups = h->groups;
+    ppl = h->ppl;
+    if (groups == 0) auto_tiling(h, groups, ppl);
+    const size_t need = (size_t)h->n * groups * 2;
+    if (need > h->partial_cap) {
+        pool_free(h->d_partial);
+        h->d_partial = nullptr;
+        h->partial_cap = 0;
+        HIP_TRY(pool_alloc((void **)&h->d_partial, sizeof(double) * need));
+        h->partial_cap = need;
+    }
+    return BSDE_OK;
+}
+
 bsde_status bsde_solve(bsde_problem h, void *hip_stream)
 {
     if (!h) return fail(BSDE_EINVAL, "null handle");
     hipStream_t s = (hipStream_t)hip_stream;
-    int groups = h->groups, ppl = h->ppl;
-    if (groups == 0) auto_tiling(h, groups, ppl);
-    const size_t need = (size_t)h->n * groups * 2;
-    if (need > h->partial_cap) {
-        hipFree(h->d_partial);
-        h->d_partial = nullptr;
-        h->partial_cap = 0;
-        HIP_TRY(hipMalloc((void **)&h->d_partial, sizeof(double) * need));
-        h->partial_cap = need;
-    }
+    int groups, ppl;
+    bsde_status st = prepare_tiling(h, groups, ppl);
+    if (st != BSDE_OK) return st;
     const bool fp32 = h->precision == BSDE_FP32_PATHS;
     const int iters = h->K_it - h->k_done;
     // events: start, end, and 4 per iteration (before path, after path,
     // after reduction, after projection; the next iteration's first event
     // closes the channel update)
     std::vector<hipEvent_t> ev(2 + 4 * (size_t)iters + 1);
-    for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
+    for (auto &x : ev) HIP_TRY(event_get(&x));
     HIP_TRY(hipEventRecord(ev[0], s));
     // channel table of the starting coefficients
     HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
@@ -554,7 +678,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     }
     float tot;
     hipEventElapsedTime(&tot, ev[0], ev[1]);
-    for (auto &x : ev) hipEventDestroy(x);
+    for (auto &x : ev) event_put(x);
     HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
                       sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
     if (iters > 0) {
@@ -567,6 +691,242 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     h->k_done = h->K_it;
     h->have_alpha = true;
     return BSDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: all remaining iterations of many problems.  Per iteration
+// step and kernel signature (d, eta, precision, volatility kind) one
+// persistent launch drains the tiles of every active problem of that
+// signature; one launch each then reduces, projects and updates all active
+// problems.  With BSDE_BATCH_GRAPH the whole schedule is captured once as a
+// hipGraph and replayed.
+// ---------------------------------------------------------------------------
+namespace {
+struct Sig {
+    int d, eta;
+    bool fp32, bump;
+    bool operator<(const Sig &o) const
+    {
+        return std::tie(d, eta, fp32, bump) < std::tie(o.d, o.eta, o.fp32, o.bump);
+    }
+};
+
+int num_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
+{
+    BatchUpdateDesc u{};
+    u.partial = h->d_partial;
+    u.n = h->n;
+    u.groups = groups;
+    u.M = h->M;
+    u.p = h->p;
+    u.C = h->C;
+    u.c = h->d_c + (size_t)std::min(k, h->K_it - 1) * h->n;
+    u.var = h->d_var + (size_t)std::min(k, h->K_it - 1) * h->n;
+    u.W = h->d_W;
+    u.beta = h->d_beta;
+    u.alpha_in = h->d_alpha + (size_t)k * h->p;
+    u.alpha_out = advance ? h->d_alpha + (size_t)(k + 1) * h->p : nullptr;
+    u.Dmat = h->d_D;
+    u.g64 = h->d_g64;
+    u.g32 = h->d_g32;
+    return u;
+}
+} // namespace
+
+// Runs `steps` iterations (at most the remaining ones) of every problem.
+// Copies the coefficient histories back when copy_back is set.
+static bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s,
+                             int steps, bool graph, bool copy_back, double *ms)
+{
+    std::vector<int> G(count), PPL(count);
+    int S = 0;
+    for (int q = 0; q < count; ++q) {
+        bsde_status st = prepare_tiling(probs[q], G[q], PPL[q]);
+        if (st != BSDE_OK) return st;
+        S = std::max(S, std::min(steps, probs[q]->K_it - probs[q]->k_done));
+    }
+    std::map<Sig, std::vector<int>> sigs;
+    for (int q = 0; q < count; ++q) {
+        bsde_problem h = probs[q];
+        sigs[{h->d, h->eta, h->precision == BSDE_FP32_PATHS,
+              h->base.vol_kind == kVolBump}].push_back(q);
+    }
+    // host-side descriptor tables, laid out in one byte buffer
+    std::vector<char> blob;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t off = (blob.size() + 255) & ~(size_t)255;
+        blob.resize(off + bytes);
+        std::memcpy(blob.data() + off, src, bytes);
+        return off;
+    };
+    struct PathLaunch { Sig sig; size_t desc_off, begin_off; int nprob; long long tiles; int counter; };
+    struct StepPlan { std::vector<PathLaunch> paths; size_t upd_off; int nact, max_n, max_p, max_C; };
+    std::vector<StepPlan> plan(S);
+    int n_counters = 0;
+    int max_C_all = 0;
+    for (int step = 0; step < S; ++step) {
+        std::vector<BatchUpdateDesc> upd;
+        int max_n = 0, max_p = 0, max_C = 0;
+        for (auto &kv : sigs) {
+            std::vector<int> act;
+            for (int q : kv.second)
+                if (probs[q]->k_done + step < probs[q]->K_it) act.push_back(q);
+            if (act.empty()) continue;
+            // heaviest tiles first (paths per lane x Euler steps)
+            std::stable_sort(act.begin(), act.end(), [&](int a, int b) {
+                return (long long)PPL[a] * probs[a]->N > (long long)PPL[b] * probs[b]->N;
+            });
+            std::vector<BatchTileDesc> td;
+            std::vector<long long> begin(1, 0);
+            for (int q : act) {
+                bsde_problem h = probs[q];
+                BatchTileDesc t{};
+                t.prm = h->base;
+                t.prm.k = (uint32_t)(h->k_done + step);
+                t.prm.groups = G[q];
+                t.prm.paths_per_lane = PPL[q];
+                t.prm.n = h->n;
+                t.pts = h->d_pts;
+                t.gamma = kv.first.fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64;
+                t.partial = h->d_partial;
+                td.push_back(t);
+                begin.push_back(begin.back() + (long long)h->n * G[q]);
+                upd.push_back(update_desc(h, h->k_done + step, G[q], true));
+                max_n = std::max(max_n, h->n);
+                max_p = std::max(max_p, h->p);
+                max_C = std::max(max_C, h->C);
+            }
+            PathLaunch pl{kv.first, put(td.data(), sizeof(BatchTileDesc) * td.size()),
+                          put(begin.data(), sizeof(long long) * begin.size()),
+                          (int)act.size(), begin.back(), n_counters++};
+            plan[step].paths.push_back(pl);
+        }
+        plan[step].upd_off = put(upd.data(), sizeof(BatchUpdateDesc) * upd.size());
+        plan[step].nact = (int)upd.size();
+        plan[step].max_n = max_n;
+        plan[step].max_p = max_p;
+        plan[step].max_C = max_C;
+        max_C_all = std::max(max_C_all, max_C);
+    }
+    std::vector<BatchUpdateDesc> init;
+    for (int q = 0; q < count; ++q) {
+        init.push_back(update_desc(probs[q], probs[q]->k_done, G[q], false));
+        max_C_all = std::max(max_C_all, probs[q]->C);
+    }
+    const size_t init_off = put(init.data(), sizeof(BatchUpdateDesc) * init.size());
+    const size_t ctr_off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(ctr_off + sizeof(unsigned int) * std::max(1, n_counters), 0);
+
+    char *dblob = nullptr;
+    HIP_TRY(pool_alloc((void **)&dblob, blob.size()));
+    struct Release {
+        char *p;
+        ~Release() { pool_free(p); }
+    } release{dblob};
+    HIP_TRY(hipMemcpyAsync(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+    unsigned int *counters = (unsigned int *)(dblob + ctr_off);
+
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = launch_reset_counters(counters, std::max(1, n_counters), s);
+        if (e != hipSuccess) return e;
+        e = launch_batch_channels(count, max_C_all, s,
+                                  (const BatchUpdateDesc *)(dblob + init_off));
+        if (e != hipSuccess) return e;
+        for (int step = 0; step < S; ++step) {
+            for (const PathLaunch &pl : plan[step].paths) {
+                const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta,
+                                                            pl.sig.fp32, pl.sig.bump));
+                const long long cap = (long long)occ * num_cus();
+                const int blocks = (int)std::max(1LL, std::min(pl.tiles, cap));
+                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.fp32, pl.sig.bump, blocks, s,
+                                 (const BatchTileDesc *)(dblob + pl.desc_off), pl.nprob,
+                                 (const long long *)(dblob + pl.begin_off),
+                                 counters + pl.counter);
+                if (e != hipSuccess) return e;
+            }
+            e = launch_batch_update(plan[step].nact, plan[step].max_n, plan[step].max_p,
+                                    plan[step].max_C, s,
+                                    (const BatchUpdateDesc *)(dblob + plan[step].upd_off));
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+
+    hipEvent_t e0, e1;
+    HIP_TRY(event_get(&e0));
+    HIP_TRY(event_get(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    if (graph) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t le = enqueue();
+        hipError_t ce = hipStreamEndCapture(s, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(BSDE_EDEVICE, std::string("graph capture: ") +
+                                          hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
+        if (ie == hipSuccess) ie = hipStreamSynchronize(s);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess)
+            return fail(BSDE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
+    } else {
+        HIP_TRY(enqueue());
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    event_put(e0);
+    event_put(e1);
+    if (ms) *ms = t;
+    for (int q = 0; q < count; ++q) {
+        bsde_problem h = probs[q];
+        h->k_done = std::min(h->K_it, h->k_done + S);
+        h->have_alpha = true;
+        if (copy_back)
+            HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
+                              sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
+    }
+    return BSDE_OK;
+}
+
+extern "C" bsde_status bsde_solve_batch(bsde_problem *problems, int count,
+                                        void *hip_stream, int flags, double *ms)
+{
+    if (!problems || count < 1) return fail(BSDE_EINVAL, "no problems");
+    for (int q = 0; q < count; ++q) {
+        if (!problems[q]) return fail(BSDE_EINVAL, "null handle in batch");
+        for (int r = 0; r < q; ++r)
+            if (problems[r] == problems[q]) return fail(BSDE_EINVAL, "duplicate handle in batch");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipStream_t own = nullptr;
+    const bool graph = (flags & BSDE_BATCH_GRAPH) != 0;
+    if (graph && !s) { // capture needs a stream other than the null stream
+        HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        s = own;
+    }
+    bsde_status st = run_batch(problems, count, s, 1 << 30, graph, true, ms);
+    if (own) (void)hipStreamDestroy(own);
+    return st;
 }
 
 bsde_status bsde_last_timings(bsde_problem h, double *ms5)

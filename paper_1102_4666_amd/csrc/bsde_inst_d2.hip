@@ -52,4 +52,51 @@ int index_table_d2(int eta, int8_t *nu, int cap)
     return 0;
 }
 
+hipError_t launch_batch_d2(int eta, bool fp32, bool bump, int blocks,
+                            hipStream_t s, const BatchTileDesc *probs,
+                            int nprob, const long long *tile_begin,
+                            unsigned int *counter)
+{
+    BSDE_BATCH_CASE(2, 2)
+    BSDE_BATCH_CASE(2, 3)
+    BSDE_BATCH_CASE(2, 4)
+    BSDE_BATCH_CASE(2, 5)
+    return hipErrorInvalidValue;
+}
+
+// blocks of the batched kernel resident per CU
+int batch_occupancy_d2(int eta, bool fp32, bool bump)
+{
+    int nb = 0;
+#define OCC(E, R, V)                                                           \
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(                        \
+        &nb, batch_path_kernel<2, E, R, V>, kBlock, 0)
+    if (eta == 2) {
+        if (fp32 && bump) OCC(2, float, kVolBump);
+        else if (fp32) OCC(2, float, kVolConst);
+        else if (bump) OCC(2, double, kVolBump);
+        else OCC(2, double, kVolConst);
+    }
+    if (eta == 3) {
+        if (fp32 && bump) OCC(3, float, kVolBump);
+        else if (fp32) OCC(3, float, kVolConst);
+        else if (bump) OCC(3, double, kVolBump);
+        else OCC(3, double, kVolConst);
+    }
+    if (eta == 4) {
+        if (fp32 && bump) OCC(4, float, kVolBump);
+        else if (fp32) OCC(4, float, kVolConst);
+        else if (bump) OCC(4, double, kVolBump);
+        else OCC(4, double, kVolConst);
+    }
+    if (eta == 5) {
+        if (fp32 && bump) OCC(5, float, kVolBump);
+        else if (fp32) OCC(5, float, kVolConst);
+        else if (bump) OCC(5, double, kVolBump);
+        else OCC(5, double, kVolConst);
+    }
+#undef OCC
+    return nb;
+}
+
 } // namespace bsde

@@ -16,12 +16,11 @@
 namespace bsde {
 
 // c_i and sample variance from the per-workgroup sums (fixed order in g)
-__global__ void finalize_kernel(const double *__restrict__ partial, int n,
-                                int groups, int M, double *__restrict__ c,
-                                double *__restrict__ var)
+__device__ __forceinline__ void finalize_point(const double *__restrict__ partial,
+                                               int i, int groups, int M,
+                                               double *__restrict__ c,
+                                               double *__restrict__ var)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     double s = 0.0, s2 = 0.0;
     for (int g = 0; g < groups; ++g) {
         s += partial[2 * ((size_t)i * groups + g)];
@@ -32,13 +31,21 @@ __global__ void finalize_kernel(const double *__restrict__ partial, int n,
     var[i] = M > 1 ? (s2 - s * mean) / (M - 1) : 0.0;
 }
 
-// beta_l = sum_i W[l][i] c_i (W = R^{-1} Q', row-major p x n); one
-// workgroup per l, lanes strided over i, fixed-order tree reduction
-__global__ __launch_bounds__(256) void project_kernel(
-    const double *__restrict__ W, const double *__restrict__ c, int n,
-    double *__restrict__ beta)
+__global__ void finalize_kernel(const double *__restrict__ partial, int n,
+                                int groups, int M, double *__restrict__ c,
+                                double *__restrict__ var)
 {
-    const int l = blockIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) finalize_point(partial, i, groups, M, c, var);
+}
+
+// beta_l = sum_i W[l][i] c_i (W = R^{-1} Q', row-major p x n): lanes
+// strided over i, fixed-order tree reduction; one workgroup of 256 lanes
+__device__ __forceinline__ void project_row(const double *__restrict__ W,
+                                            const double *__restrict__ c,
+                                            int n, int l,
+                                            double *__restrict__ beta)
+{
     const double *w = W + (size_t)l * n;
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) acc += w[i] * c[i];
@@ -50,18 +57,23 @@ __global__ __launch_bounds__(256) void project_kernel(
     if (threadIdx.x == 0) beta[l] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+__global__ __launch_bounds__(256) void project_kernel(
+    const double *__restrict__ W, const double *__restrict__ c, int n,
+    double *__restrict__ beta)
+{
+    project_row(W, c, n, blockIdx.x, beta);
+}
+
 constexpr int kMaxP = 512;
 
-// one workgroup per channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with
-// a = alpha_in + beta (channel 0 is the identity); workgroup 0 also stores
-// a as the next coefficient vector
-__global__ __launch_bounds__(256) void channel_kernel(
+// channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with a = alpha_in + beta
+// (channel 0 is the identity and also stores a as the next coefficients)
+__device__ __forceinline__ void channel_col(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
     double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, double *__restrict__ g64, float *__restrict__ g32)
+    int C, int c, double *__restrict__ g64, float *__restrict__ g32)
 {
     __shared__ double a[kMaxP];
-    const int c = blockIdx.x;
     for (int m = threadIdx.x; m < p; m += 256)
         a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
     __syncthreads();
@@ -83,6 +95,76 @@ __global__ __launch_bounds__(256) void channel_kernel(
     }
 }
 
+// one workgroup per channel
+__global__ __launch_bounds__(256) void channel_kernel(
+    const double *__restrict__ alpha_in, const double *__restrict__ beta,
+    double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
+    int C, double *__restrict__ g64, float *__restrict__ g32)
+{
+    channel_col(alpha_in, beta, alpha_out, Dmat, p, C, blockIdx.x, g64, g32);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: blockIdx.y selects the problem; each problem is reduced
+// and updated by the same device functions as above.
+// ---------------------------------------------------------------------------
+__global__ void batch_finalize_kernel(const BatchUpdateDesc *__restrict__ d)
+{
+    const BatchUpdateDesc &q = d[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q.n) finalize_point(q.partial, i, q.groups, q.M, q.c, q.var);
+}
+
+__global__ __launch_bounds__(256) void batch_project_kernel(
+    const BatchUpdateDesc *__restrict__ d)
+{
+    const BatchUpdateDesc &q = d[blockIdx.y];
+    if ((int)blockIdx.x < q.p) project_row(q.W, q.c, q.n, blockIdx.x, q.beta);
+}
+
+__global__ __launch_bounds__(256) void batch_channel_kernel(
+    const BatchUpdateDesc *__restrict__ d, int with_beta)
+{
+    const BatchUpdateDesc &q = d[blockIdx.y];
+    if ((int)blockIdx.x < q.C)
+        channel_col(q.alpha_in, with_beta ? q.beta : nullptr,
+                    with_beta ? q.alpha_out : nullptr, q.Dmat, q.p, q.C,
+                    blockIdx.x, q.g64, q.g32);
+}
+
+__global__ void reset_counters_kernel(unsigned int *c, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0u;
+}
+
+hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
+                               hipStream_t s, const BatchUpdateDesc *d)
+{
+    hipLaunchKernelGGL(batch_finalize_kernel,
+                       dim3((max_n + 255) / 256, nprob), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(batch_project_kernel, dim3(max_p, nprob), dim3(256), 0,
+                       s, d);
+    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_C, nprob), dim3(256), 0,
+                       s, d, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
+                                 const BatchUpdateDesc *d)
+{
+    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_C, nprob), dim3(256), 0,
+                       s, d, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counters_kernel, dim3((n + 255) / 256), dim3(256),
+                       0, s, c, n);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over the instantiated (d, eta) pairs
 // ---------------------------------------------------------------------------
@@ -91,7 +173,12 @@ __global__ __launch_bounds__(256) void channel_kernel(
     hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s,  \
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial);           \
-    int index_table_d##D(int eta, int8_t *nu, int cap);
+    int index_table_d##D(int eta, int8_t *nu, int cap);                        \
+    hipError_t launch_batch_d##D(int eta, bool fp32, bool bump, int blocks,     \
+                                 hipStream_t s, const BatchTileDesc *probs,    \
+                                 int nprob, const long long *tile_begin,       \
+                                 unsigned int *counter);                       \
+    int batch_occupancy_d##D(int eta, bool fp32, bool bump);
 BSDE_DIMS(DECL)
 #undef DECL
 
@@ -116,6 +203,28 @@ hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
     BSDE_DIMS(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(int d, int eta, bool fp32, bool bump, int blocks,
+                        hipStream_t s, const BatchTileDesc *probs, int nprob,
+                        const long long *tile_begin, unsigned int *counter)
+{
+#define X(D)                                                                   \
+    if (d == D)                                                                \
+        return launch_batch_d##D(eta, fp32, bump, blocks, s, probs, nprob,     \
+                                 tile_begin, counter);
+    BSDE_DIMS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int batch_occupancy(int d, int eta, bool fp32, bool bump)
+{
+#define X(D)                                                                   \
+    if (d == D) return batch_occupancy_d##D(eta, fp32, bump);
+    BSDE_DIMS(X)
+#undef X
+    return 0;
 }
 
 hipError_t launch_update(int n, int groups, int M, int p, int C,

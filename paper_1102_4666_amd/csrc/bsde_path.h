@@ -31,12 +31,17 @@ struct Arith<float> {
     {
         return fmaf((float)w, 0x1p-32f, 0x1p-33f); // (w + 1/2) 2^-32
     }
-    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
-                                                      float &n0, float &n1)
+    // Box-Muller pair scaled by sqrt(v): R = sqrt(-2 v ln ua), computed as
+    // sqrt((-2 ln2 v) log2 ua); angle 2 pi ub (v_sin/v_cos take revolutions)
+    static __device__ __forceinline__ float bm_scale(float v)
     {
-        // R = sqrt(-2 ln ua) = sqrt(-2 ln2 log2 ua); angle 2 pi ub
-        float R = __builtin_sqrtf(-1.38629436111989061883f *
-                                  __builtin_amdgcn_logf(u01(wa)));
+        return -1.38629436111989061883f * v;
+    }
+    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
+                                                      float scale, float &n0,
+                                                      float &n1)
+    {
+        float R = __builtin_amdgcn_sqrtf(scale * __builtin_amdgcn_logf(u01(wa)));
         float ub = u01(wb);
         n0 = R * __builtin_amdgcn_cosf(ub);
         n1 = R * __builtin_amdgcn_sinf(ub);
@@ -44,7 +49,7 @@ struct Arith<float> {
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
     static __device__ __forceinline__ float sqrt(float x)
     {
-        return __builtin_sqrtf(x);
+        return __builtin_amdgcn_sqrtf(x); // v_sqrt_f32, no refinement
     }
     static __device__ __forceinline__ float frac33(uint64_t num)
     {
@@ -59,10 +64,16 @@ struct Arith<double> {
     {
         return ((double)w + 0.5) * 0x1p-32;
     }
-    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
-                                                      double &n0, double &n1)
+    static __device__ __forceinline__ double bm_scale(double v)
     {
-        double R = ::sqrt(-2.0 * ::log(u01(wa)));
+        return -2.0 * v;
+    }
+    // Box-Muller pair scaled by sqrt(v), scale = -2 v: R = sqrt(-2 v ln ua)
+    static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
+                                                      double scale, double &n0,
+                                                      double &n1)
+    {
+        double R = ::sqrt(scale * ::log(u01(wa)));
         double phi = (2.0 * 3.14159265358979323846) * u01(wb);
         double s, c;
         ::sincos(phi, &s, &c);
@@ -77,13 +88,14 @@ struct Arith<double> {
     }
 };
 
-template <typename Real>
-__device__ __forceinline__ Real local_vol(int kind, Real level, Real a, Real lc,
+// sigma_j = level (1 + a e^{-(x - log c)^2}) = level + (level a) e^{...}
+template <int VOL, typename Real>
+__device__ __forceinline__ Real local_vol(Real level, Real level_a, Real lc,
                                           Real x)
 {
-    if (kind == kVolBump) {
+    if constexpr (VOL == kVolBump) {
         Real dx = x - lc;
-        return level * (Real(1) + a * Arith<Real>::exp(-dx * dx));
+        return fma(level_a, Arith<Real>::exp(-dx * dx), level);
     }
     return level;
 }
@@ -127,10 +139,12 @@ __device__ __forceinline__ void cheb(Real z, Real *Tz)
 // paths m = (g * ppl + r) * kBlock + lane, r < ppl, m < M, of point i and
 // writes its FP64 sums (sum a_m, sum a_m^2) to partial[2 (i groups + g)].
 // ---------------------------------------------------------------------------
-template <int D, int ETA, typename Real>
-__global__ __launch_bounds__(kBlock) void path_kernel(
-    const PathParams prm, const double *__restrict__ pts,
-    const Real *__restrict__ gamma, double *__restrict__ partial)
+template <int D, int ETA, typename Real, int VOL>
+__device__ __forceinline__ void run_tile(const PathParams &prm,
+                                         const double *__restrict__ pts,
+                                         const Real *__restrict__ gamma,
+                                         const int i, const int g,
+                                         double *__restrict__ out)
 {
     constexpr int DP = D + 1;
     constexpr int C = num_channels(D);
@@ -141,8 +155,6 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
     constexpr int NB = SG * D / 4;
     constexpr int NBB = (D + 3) / 4; // bridge blocks
 
-    const int i = blockIdx.x / prm.groups;
-    const int g = blockIdx.x - i * prm.groups;
     const uint32_t k0 = (uint32_t)prm.seed, k1 = (uint32_t)(prm.seed >> 32);
 
     const double *row = pts + (size_t)i * DP;
@@ -152,14 +164,16 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
 #pragma unroll
     for (int j = 0; j < D; ++j) x0[j] = (Real)row[1 + j];
     const Real h = (T - t0) / (Real)prm.N;
-    const Real sqrt_h = Arith<Real>::sqrt(h);
+    // step normals come out of Box-Muller already scaled by sqrt(h)
+    const Real step_scale = Arith<Real>::bm_scale(h);
     const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
-    const Real bump_a = (Real)prm.bump_a, lc = (Real)prm.log_bump_c;
+    const Real lc = (Real)prm.log_bump_c;
     const Real rho = (Real)prm.rho;
-    Real L[D][D], level[D], drift0[D], mid[D], scale[D];
+    Real L[D][D], level[D], level_a[D], drift0[D], mid[D], scale[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         level[j] = (Real)prm.level[j];
+        level_a[j] = (Real)(prm.level[j] * prm.bump_a);
         drift0[j] = (Real)(prm.r - prm.div[j]);
         mid[j] = (Real)prm.mid[j];
         scale[j] = (Real)prm.scale[j];
@@ -167,6 +181,10 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
         for (int l = 0; l < D; ++l) L[j][l] = (Real)prm.L[j * kMaxD + l];
     }
     const Real tscale = Real(2) / T;
+    const Real neg_half_h = Real(-0.5) * h;
+    Real drift_h[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) drift_h[j] = drift0[j] * h;
 
     double sum = 0.0, sumsq = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
@@ -196,8 +214,10 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
             for (int b = 0; b < NB; ++b) {
                 const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
                                          (uint32_t)(grp * NB + b), k0, k1);
-                Arith<Real>::box_muller(w.x, w.y, G[4 * b], G[4 * b + 1]);
-                Arith<Real>::box_muller(w.z, w.w, G[4 * b + 2], G[4 * b + 3]);
+                Arith<Real>::box_muller(w.x, w.y, step_scale, G[4 * b],
+                                        G[4 * b + 1]);
+                Arith<Real>::box_muller(w.z, w.w, step_scale, G[4 * b + 2],
+                                        G[4 * b + 3]);
             }
 #pragma unroll
             for (int ss = 0; ss < SG; ++ss) {
@@ -206,41 +226,53 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
                     const bool at = (s == jstar);
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
-                        Real lg = Real(0);
+                        // sqrt(h) (L G)_j; the first row of the Cholesky
+                        // factor of a correlation matrix is (1, 0, ..., 0)
+                        Real lg = G[ss * D];
+                        if (j > 0) {
+                            lg = L[j][0] * lg;
 #pragma unroll
-                        for (int l = 0; l <= j; ++l)
-                            lg += L[j][l] * G[ss * D + l];
-                        const Real sig = local_vol<Real>(prm.vol_kind, level[j],
-                                                         bump_a, lc, X[j]);
-                        const Real b = drift0[j] - Real(0.5) * sig * sig;
+                            for (int l = 1; l <= j; ++l)
+                                lg += L[j][l] * G[ss * D + l];
+                        }
+                        const Real sig = local_vol<VOL>(level[j], level_a[j], lc, X[j]);
                         Xs[j] = at ? X[j] : Xs[j];
                         LGs[j] = at ? lg : LGs[j];
-                        X[j] += b * h + sig * sqrt_h * lg;
+                        // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
+                        //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2)
+                        X[j] = fma(sig, fma(neg_half_h, sig, lg), X[j]) + drift_h[j];
                     }
                 }
             }
         }
 
-        // frozen coefficients at the last node t_{j*} and X at tau
+        // frozen coefficients at the last node t_{j*} and X at tau: the
+        // bridge normals are scaled by sqrt(theta (1 - theta) h)
+        const Real bridge_scale =
+            Arith<Real>::bm_scale(theta * (Real(1) - theta) * h);
         Real Gb[4 * NBB];
 #pragma unroll
         for (int b = 0; b < NBB; ++b) {
             const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
                                      (1u << 24) | (uint32_t)(1 + b), k0, k1);
-            Arith<Real>::box_muller(w.x, w.y, Gb[4 * b], Gb[4 * b + 1]);
-            Arith<Real>::box_muller(w.z, w.w, Gb[4 * b + 2], Gb[4 * b + 3]);
+            Arith<Real>::box_muller(w.x, w.y, bridge_scale, Gb[4 * b],
+                                    Gb[4 * b + 1]);
+            Arith<Real>::box_muller(w.z, w.w, bridge_scale, Gb[4 * b + 2],
+                                    Gb[4 * b + 3]);
         }
-        const Real bridge = Arith<Real>::sqrt(theta * (Real(1) - theta) * h);
         Real sgs[D], bst[D], Xt[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            Real lgb = Real(0);
+            Real lgb = Gb[0];
+            if (j > 0) {
+                lgb = L[j][0] * lgb;
 #pragma unroll
-            for (int l = 0; l <= j; ++l) lgb += L[j][l] * Gb[l];
-            sgs[j] = local_vol<Real>(prm.vol_kind, level[j], bump_a, lc, Xs[j]);
-            bst[j] = drift0[j] - Real(0.5) * sgs[j] * sgs[j];
+                for (int l = 1; l <= j; ++l) lgb += L[j][l] * Gb[l];
+            }
+            sgs[j] = local_vol<VOL>(level[j], level_a[j], lc, Xs[j]);
+            bst[j] = fma(Real(-0.5) * sgs[j], sgs[j], drift0[j]);
             Xt[j] = Xs[j] + bst[j] * theta * h +
-                    sgs[j] * (theta * sqrt_h * LGs[j] + bridge * lgb);
+                    sgs[j] * fma(theta, LGs[j], lgb);
         }
 
         // basis row at (tau, X_tau) contracted with the channel table, and
@@ -322,24 +354,83 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
             s += red[0][w];
             s2 += red[1][w];
         }
-        partial[2 * (size_t)blockIdx.x] = s;
-        partial[2 * (size_t)blockIdx.x + 1] = s2;
+        out[0] = s;
+        out[1] = s2;
+    }
+    __syncthreads(); // red[] may be reused by the next tile
+}
+
+// One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
+// writes its sums to partial[2 b].
+template <int D, int ETA, typename Real, int VOL>
+__global__ __launch_bounds__(kBlock) void path_kernel(
+    const PathParams prm, const double *__restrict__ pts,
+    const Real *__restrict__ gamma, double *__restrict__ partial)
+{
+    const int i = blockIdx.x / prm.groups;
+    const int g = blockIdx.x - i * prm.groups;
+    run_tile<D, ETA, Real, VOL>(prm, pts, gamma, i, g,
+                                partial + 2 * (size_t)blockIdx.x);
+}
+
+// Many problems of one kernel signature in one persistent launch.  Tiles
+// of problem q are tile_begin[q] .. tile_begin[q+1]-1 (problems ordered by
+// decreasing tile cost); every workgroup takes the next tile from an
+// atomic counter until none is left -- dynamic per-tile dispatch.  A tile
+// computes exactly what the one-problem kernel computes for the same
+// (i, g), so a problem's result does not depend on the batch.
+template <int D, int ETA, typename Real, int VOL>
+__global__ __launch_bounds__(kBlock) void batch_path_kernel(
+    const BatchTileDesc *__restrict__ probs, int nprob,
+    const long long *__restrict__ tile_begin, unsigned int *counter)
+{
+    __shared__ long long next;
+    const long long total = tile_begin[nprob];
+    for (;;) {
+        if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1u);
+        __syncthreads();
+        const long long t = next;
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = nprob - 1; // last q with tile_begin[q] <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_begin[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchTileDesc &q = probs[lo];
+        const long long local = t - tile_begin[lo];
+        const int i = (int)(local / q.prm.groups);
+        const int g = (int)(local - (long long)i * q.prm.groups);
+        run_tile<D, ETA, Real, VOL>(q.prm, q.pts, (const Real *)q.gamma, i, g,
+                                    q.partial + 2 * local);
     }
 }
 
 } // namespace bsde
 
-// Explicit instantiation of the FP32 and FP64 kernels for (D, E) and a
-// launcher bsde::launch_path_D<D>(eta, ...) for each instantiated D.
+// Launch of the FP32 or FP64 kernel for (D, E) with the volatility kind
+// of the parameters; used by the per-dimension launchers launch_path_dD.
+#define BSDE_PATH_LAUNCH(D, E, R, V)                                           \
+    hipLaunchKernelGGL((path_kernel<D, E, R, V>), dim3(blocks), dim3(kBlock),  \
+                       0, s, prm, pts, (const R *)gamma, partial)
+#define BSDE_BATCH_LAUNCH(D, E, R, V)                                          \
+    hipLaunchKernelGGL((batch_path_kernel<D, E, R, V>), dim3(blocks),          \
+                       dim3(kBlock), 0, s, probs, nprob, tile_begin, counter)
+#define BSDE_BATCH_CASE(D, E)                                                  \
+    if (eta == E) {                                                            \
+        if (fp32 && bump) BSDE_BATCH_LAUNCH(D, E, float, kVolBump);            \
+        else if (fp32) BSDE_BATCH_LAUNCH(D, E, float, kVolConst);              \
+        else if (bump) BSDE_BATCH_LAUNCH(D, E, double, kVolBump);              \
+        else BSDE_BATCH_LAUNCH(D, E, double, kVolConst);                       \
+        return hipGetLastError();                                              \
+    }
 #define BSDE_PATH_CASE(D, E)                                                   \
     if (eta == E) {                                                            \
-        if (fp32)                                                              \
-            hipLaunchKernelGGL((path_kernel<D, E, float>), dim3(blocks),       \
-                               dim3(kBlock), 0, s, prm, pts,                   \
-                               (const float *)gamma, partial);                 \
-        else                                                                   \
-            hipLaunchKernelGGL((path_kernel<D, E, double>), dim3(blocks),      \
-                               dim3(kBlock), 0, s, prm, pts,                   \
-                               (const double *)gamma, partial);                \
+        const bool bump = prm.vol_kind == kVolBump;                            \
+        if (fp32 && bump) BSDE_PATH_LAUNCH(D, E, float, kVolBump);             \
+        else if (fp32) BSDE_PATH_LAUNCH(D, E, float, kVolConst);               \
+        else if (bump) BSDE_PATH_LAUNCH(D, E, double, kVolBump);               \
+        else BSDE_PATH_LAUNCH(D, E, double, kVolConst);                        \
         return hipGetLastError();                                              \
     }

@@ -23,6 +23,16 @@ import oracle  # noqa: E402
 import workloads  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+MAX_STORED_POINTS = 2048
+
+
+def stored_points(n: int) -> np.ndarray:
+    """Indices of the points whose corrections are stored: all of them for
+    n <= 2048, else a fixed seeded sample of 2048 (sorted)."""
+    if n <= MAX_STORED_POINTS:
+        return np.arange(n)
+    rng = np.random.default_rng(12345)
+    return np.sort(rng.choice(n, MAX_STORED_POINTS, replace=False))
 
 # name -> (workload factory, kwargs)
 CASES = {
@@ -53,10 +63,14 @@ def main():
             pr, de = oracle.price_delta(cfg, a, [0.0], [cfg["S0"]])
             prices.append(float(pr[0]))
             deltas.append([float(x) for x in de[0]])
+        idx = stored_points(res["n"])
         out = {
             "name": name, "cfg": cfg, "seconds": time.time() - t0,
-            "price": prices, "delta": deltas,
-            "c": res["c"].tolist(), "var": res["var"].tolist(),
+            "price": prices, "delta": deltas, "n": res["n"],
+            "idx": idx.tolist(),
+            "c": res["c"][:, idx].tolist(),
+            "c_l2": [float(np.linalg.norm(c)) for c in res["c"]],
+            "c_sum": [float(np.sum(c)) for c in res["c"]],
         }
         path = os.path.join(HERE, name + ".json")
         with open(path, "w") as f:
