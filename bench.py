@@ -126,6 +126,59 @@ def cpu_baseline(cfg, seconds: float = 12.0):
                       (n_sub, n, cfg["M"], cfg["N"], steps, dt)}
 
 
+def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5)):
+    """Serving run: closed-loop saturation, then Poisson arrivals at 0.5 and
+    0.9 of the saturation rate; p50/p99 latency and throughput per phase."""
+    import torch
+
+    import paper_1102_4666_amd as bsde
+    import workloads
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    rng = np.random.default_rng(seed)
+    reqs = [workloads.serving_request(i, rng, dims) for i in range(n_requests)]
+
+    def run_phase(rate):
+        lat = []
+        with bsde.Server(budget, max_inflight=64) as S:
+            t0 = time.perf_counter()
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs))) \
+                if rate else np.zeros(len(reqs))
+            out = []
+            for cfg, ta in zip(reqs, arrivals):
+                now = time.perf_counter() - t0
+                if ta > now:
+                    time.sleep(ta - now)
+                out.append(S.submit(cfg))
+            res = []
+            for j, t in enumerate(out):
+                res.append(S.poll(t))
+                if (j + 1) % 10 == 0:
+                    print("serving: %d/%d done after %.1f s" %
+                          (j + 1, len(out), time.perf_counter() - t0),
+                          file=sys.stderr, flush=True)
+            wall = time.perf_counter() - t0
+            st = S.stats()
+        bad = [r["status"] for r in res if r["status"] != 0]
+        return {"offered_rate": rate, "requests": len(reqs), "failed": len(bad),
+                "wall_s": wall, "requests_per_s": st["requests_per_s"],
+                "path_steps_per_s": st["path_steps_per_s"],
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "engine_steps": st["engine_steps"]}
+
+    print("serving: saturation phase", file=sys.stderr, flush=True)
+    sat = run_phase(None)
+    print("serving: %.2f requests/s at saturation" % sat["requests_per_s"],
+          file=sys.stderr, flush=True)
+    x_sat = sat["requests_per_s"]
+    return {"mix": "d in %s, K U[80,120], European/American 50/50, M in "
+                   "{500,1000,2000,4000}, FP32 paths" % (list(dims),),
+            "hbm_budget_bytes": budget, "saturation": sat,
+            "load_0.5": run_phase(0.5 * x_sat),
+            "load_0.9": run_phase(0.9 * x_sat)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +189,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the error check against stored oracle results")
+    ap.add_argument("--serve", type=int, default=0, metavar="R",
+                    help="also run the request-server benchmark with R "
+                         "requests per load level")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the "
                          "HBM byte counters of the profiler)")
@@ -223,6 +279,8 @@ def main():
                                      "frac": fl / FP32_VECTOR_PEAK}
     if not args.no_accuracy:
         line["accuracy_vs_oracle"] = accuracy(args.precision, stream)
+    if args.serve:
+        line["serving"] = serve(args.serve)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(workload("fp64"), args.cpu_seconds)
     print(json.dumps(line), flush=True)

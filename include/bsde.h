@@ -39,7 +39,8 @@ typedef enum {
     BSDE_EDEVICE = 4,  /* a HIP call failed (no GPU, launch failure, ...)    */
     BSDE_ESTATE = 5,   /* call not valid in the current state (e.g. query
                           before solve)                                    */
-    BSDE_EUNSUPPORTED = 6 /* no kernel is built for this (d, eta)            */
+    BSDE_EUNSUPPORTED = 6, /* no kernel is built for this (d, eta)           */
+    BSDE_EBUSY = 7     /* request not finished yet (non-blocking poll)      */
 } bsde_status;
 
 /* Volatility sigma_j(t, S) of asset j (eq. 4 of Section 5, diagonal form:
@@ -218,6 +219,68 @@ bsde_status bsde_solve_batch(bsde_problem *problems, int count,
                              void *hip_stream, int flags, double *ms);
 
 void bsde_destroy(bsde_problem h);
+
+/* ------------------------------------------------------------------------
+ * Request server (hot-path row "serving"): continuous batching of pricing
+ * requests.  Requests are admitted while their device footprint fits the
+ * HBM budget and fewer than max_inflight are in flight; set-up threads
+ * build admitted problems while the GPU works; one engine thread advances
+ * all in-flight problems by one Picard iteration per step with the batched
+ * kernels (bsde_solve_batch), so requests arriving while others run join
+ * at the next step.  Each problem's coefficients stay resident on the
+ * device across its iterations.  A request's result is identical whether it
+ * runs alone or in a mix.  All server calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct bsde_server_s *bsde_server; /* owned by the library */
+
+/* One request: the arguments of bsde_create_problem plus a query point. */
+typedef struct {
+    int d;
+    bsde_sigma sigma;
+    double r;
+    bsde_payoff payoff;
+    bsde_grid grid;
+    int M, N, n_picard;
+    double penalty;
+    unsigned long long seed;
+    int precision;
+    double query_t;          /* time of the price/delta query              */
+    const double *query_S;   /* d prices, or NULL for the spots S0          */
+} bsde_request;
+
+typedef struct {
+    int status;              /* bsde_status of the request                  */
+    double price;            /* u(query_t, log query_S)                     */
+    double delta[10];        /* dollar deltas (first d entries)             */
+    double latency_ms;       /* submit to completion                        */
+    double queue_ms;         /* submit to admission                         */
+} bsde_result;
+
+typedef struct {
+    double p50_ms, p99_ms;     /* request latency percentiles              */
+    double requests_per_s;     /* completed / (first submit .. last done)  */
+    double path_steps_per_s;   /* sum of n M N K_it over the same span      */
+    long completed, engine_steps, in_flight, pending;
+    size_t reserved_bytes;     /* device bytes reserved by admitted requests */
+} bsde_server_stats_t;
+
+/* hbm_budget_bytes: device bytes the server may reserve for admitted
+ * problems; max_inflight: problems in set-up or on the GPU at once;
+ * setup_threads: host threads building problems (0 = 4).  Uses the HIP
+ * device current at the call.  Errors: BSDE_EINVAL, BSDE_EDEVICE. */
+bsde_status bsde_server_create(size_t hbm_budget_bytes, int max_inflight,
+                               int setup_threads, bsde_server *out);
+/* Queues a request (arrays are copied); ticket receives its id. */
+bsde_status bsde_server_submit(bsde_server s, const bsde_request *req,
+                               unsigned long long *ticket);
+/* Result of a ticket; with wait = 0 returns BSDE_EBUSY while it runs.  A
+ * ticket can be collected once. */
+bsde_status bsde_server_poll(bsde_server s, unsigned long long ticket,
+                             int wait, bsde_result *out);
+bsde_status bsde_server_stats(bsde_server s, bsde_server_stats_t *out);
+/* Stops admitting, finishes the problems already built, frees everything;
+ * requests not yet admitted are dropped. */
+void bsde_server_destroy(bsde_server s);
 const char *bsde_status_string(bsde_status s);
 /* Human-readable detail of the last error on this thread. */
 const char *bsde_last_error(void);

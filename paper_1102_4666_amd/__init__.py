@@ -27,7 +27,8 @@ GRIDS = {"tensor": 0, "random": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 STATUS = {0: "BSDE_OK", 1: "BSDE_EINVAL", 2: "BSDE_ENOMEM", 3: "BSDE_ERANK",
-          4: "BSDE_EDEVICE", 5: "BSDE_ESTATE", 6: "BSDE_EUNSUPPORTED"}
+          4: "BSDE_EDEVICE", 5: "BSDE_ESTATE", 6: "BSDE_EUNSUPPORTED",
+          7: "BSDE_EBUSY"}
 
 EXPORTS = [
     "bsde_create_problem", "bsde_solve", "bsde_query_price_delta",
@@ -35,6 +36,8 @@ EXPORTS = [
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
     "bsde_set_tiling", "bsde_last_timings", "bsde_solve_batch",
     "bsde_destroy", "bsde_status_string", "bsde_last_error",
+    "bsde_server_create", "bsde_server_submit", "bsde_server_poll",
+    "bsde_server_stats", "bsde_server_destroy",
 ]
 BSDE_BATCH_GRAPH = 1
 
@@ -61,6 +64,28 @@ class Payoff(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_t", C.c_int), ("n_x", C.c_int),
                 ("width", C.c_double), ("eta", C.c_int), ("q", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("d", C.c_int), ("sigma", Sigma), ("r", C.c_double),
+                ("payoff", Payoff), ("grid", Grid), ("M", C.c_int),
+                ("N", C.c_int), ("n_picard", C.c_int), ("penalty", C.c_double),
+                ("seed", C.c_ulonglong), ("precision", C.c_int),
+                ("query_t", C.c_double), ("query_S", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("price", C.c_double),
+                ("delta", C.c_double * 10), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("requests_per_s", C.c_double),
+                ("path_steps_per_s", C.c_double), ("completed", C.c_long),
+                ("engine_steps", C.c_long), ("in_flight", C.c_long),
+                ("pending", C.c_long), ("reserved_bytes", C.c_size_t)]
 
 
 _lib = None
@@ -93,6 +118,15 @@ def lib():
         L.bsde_last_timings.argtypes = [H, _dp]
         L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
                                        C.c_int, _dp]
+        L.bsde_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int,
+                                         C.POINTER(H)]
+        L.bsde_server_submit.argtypes = [H, C.POINTER(Request),
+                                         C.POINTER(C.c_ulonglong)]
+        L.bsde_server_poll.argtypes = [H, C.c_ulonglong, C.c_int,
+                                       C.POINTER(Result)]
+        L.bsde_server_stats.argtypes = [H, C.POINTER(ServerStats)]
+        L.bsde_server_destroy.argtypes = [H]
+        L.bsde_server_destroy.restype = None
         L.bsde_destroy.argtypes = [H]
         L.bsde_destroy.restype = None
         L.bsde_status_string.argtypes = [C.c_int]
@@ -101,7 +135,7 @@ def lib():
         L.bsde_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("bsde_destroy", "bsde_status_string",
-                            "bsde_last_error"):
+                            "bsde_last_error", "bsde_server_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -130,9 +164,8 @@ def _d(a):
 # --------------------------------------------------------------------------
 # Entry points (same names as the C ABI)
 # --------------------------------------------------------------------------
-def bsde_create_problem(cfg: dict):
-    """Marshals a problem dict into bsde_create_problem; returns the handle
-    (a c_void_p) together with the arrays that must outlive the call."""
+def _marshal(cfg: dict):
+    """The C structs of a problem dict and the arrays they point to."""
     d = int(cfg["d"])
     level = _arr(np.broadcast_to(np.asarray(cfg["vol_level"], float), (d,)))
     div = _arr(np.broadcast_to(np.asarray(cfg.get("div", 0.0), float), (d,)))
@@ -145,6 +178,13 @@ def bsde_create_problem(cfg: dict):
     grid = Grid(GRIDS[cfg.get("grid", "tensor")], int(cfg["n_t"]),
                 int(cfg["n_x"]), float(cfg.get("width", 4.0)),
                 int(cfg["eta"]), float(cfg.get("q", 1.0)))
+    return d, sig, pay, grid, (level, div, S0)
+
+
+def bsde_create_problem(cfg: dict):
+    """Marshals a problem dict into bsde_create_problem; returns the
+    handle (a c_void_p)."""
+    d, sig, pay, grid, keep = _marshal(cfg)
     h = C.c_void_p()
     st = lib().bsde_create_problem(
         d, C.byref(sig), float(cfg["r"]), C.byref(pay), C.byref(grid),
@@ -294,6 +334,61 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# --------------------------------------------------------------------------
+class Server:
+    """Continuous-batching request server (bsde_server_*)."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight=64, setup_threads=0):
+        self.h = C.c_void_p()
+        _check(lib().bsde_server_create(int(hbm_budget_bytes),
+                                        int(max_inflight), int(setup_threads),
+                                        C.byref(self.h)), "bsde_server_create")
+
+    def submit(self, cfg: dict, query_t=0.0, query_S=None) -> int:
+        d, sig, pay, grid, keep = _marshal(cfg)
+        qS = None
+        if query_S is not None:
+            qS = _arr(np.broadcast_to(np.asarray(query_S, float), (d,)))
+        req = Request(d, sig, float(cfg["r"]), pay, grid, int(cfg["M"]),
+                      int(cfg["N"]), int(cfg["K_it"]),
+                      float(cfg.get("omega", 0.0)), int(cfg.get("seed", 0)),
+                      PRECISIONS[cfg.get("precision", "fp64")],
+                      float(query_t), _d(qS) if qS is not None else None)
+        t = C.c_ulonglong()
+        _check(lib().bsde_server_submit(self.h, C.byref(req), C.byref(t)),
+               "bsde_server_submit")
+        return t.value
+
+    def poll(self, ticket: int, wait=True):
+        """dict of the result, or None if not finished (wait=False)."""
+        r = Result()
+        st = lib().bsde_server_poll(self.h, ticket, 1 if wait else 0,
+                                    C.byref(r))
+        if st == 7:
+            return None
+        _check(st, "bsde_server_poll")
+        return {"status": r.status, "price": r.price,
+                "delta": np.array(r.delta[:]), "latency_ms": r.latency_ms,
+                "queue_ms": r.queue_ms}
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().bsde_server_stats(self.h, C.byref(st)),
+               "bsde_server_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().bsde_server_destroy(self.h)
+            self.h = None
 
     def __enter__(self):
         return self

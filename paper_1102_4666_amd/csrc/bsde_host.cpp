@@ -8,8 +8,7 @@
 // Section 4.2 (eq. lspb) with polynomials centred and normalised to
 // [-1, 1]^{d+1}; the model is Section 5 (eq. 4) with the correlation of
 // Section 6.2.
-#include "../../include/bsde.h"
-#include "bsde_common.h"
+#include "bsde_internal.h"
 
 #include <hip/hip_runtime.h>
 
@@ -145,37 +144,11 @@ void event_put(hipEvent_t e)
 }
 } // namespace
 
-static bsde_status fail(bsde_status s, const std::string &msg)
+bsde_status bsde::fail(bsde_status s, const std::string &msg)
 {
     g_last_error = msg;
     return s;
 }
-
-struct bsde_problem_s {
-    // parameters
-    int d = 0, eta = 0, M = 0, N = 0, K_it = 0, precision = 0;
-    double q = 1.0, omega = 0.0;
-    PathParams base{};
-    // sizes
-    int n = 0, n_spatial = 0, p = 0, C = 0;
-    std::vector<int8_t> nu;      // p x (d+1), kernel order
-    std::vector<char> active;    // in the hyperbolic set
-    std::vector<double> pts;     // n x (d+1)
-    std::vector<double> lo, hi;
-    std::vector<double> Dfirst;  // d x p x p: d_{x_j} channel matrices
-    // device
-    double *d_pts = nullptr, *d_W = nullptr, *d_D = nullptr,
-           *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
-           *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
-    float *d_g32 = nullptr;
-    size_t partial_cap = 0;
-    // state
-    int k_done = 0;
-    bool have_alpha = false;
-    std::vector<double> alpha_hist; // (K_it + 1) x p, host mirror
-    int groups = 0, ppl = 0;       // tiling (0 = automatic)
-    double timings[5] = {0, 0, 0, 0, 0};
-};
 
 // ---------------------------------------------------------------------------
 // Set-up helpers
@@ -693,6 +666,8 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     return BSDE_OK;
 }
 
+} // extern "C"
+
 // ---------------------------------------------------------------------------
 // Batched solve: all remaining iterations of many problems.  Per iteration
 // step and kernel signature (d, eta, precision, volatility kind) one
@@ -748,8 +723,8 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
 
 // Runs `steps` iterations (at most the remaining ones) of every problem.
 // Copies the coefficient histories back when copy_back is set.
-static bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s,
-                             int steps, bool graph, bool copy_back, double *ms)
+bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
+                            int steps, bool graph, bool copy_back, double *ms)
 {
     std::vector<int> G(count), PPL(count);
     int S = 0;
@@ -908,7 +883,42 @@ static bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s,
     return BSDE_OK;
 }
 
-extern "C" bsde_status bsde_solve_batch(bsde_problem *problems, int count,
+bsde_status bsde::fetch_coefficients(bsde_problem h)
+{
+    HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
+                      sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
+    return BSDE_OK;
+}
+
+size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
+{
+    if (d < 1 || d > kMaxD || !grid) return 0;
+    const int p = index_table(d, grid->eta, nullptr, 0);
+    if (p == 0) return 0;
+    size_t ns = 1;
+    if (grid->kind == BSDE_GRID_TENSOR)
+        for (int j = 0; j < d; ++j) ns *= (size_t)grid->n_x;
+    else
+        ns = (size_t)grid->n_x;
+    const size_t n = ns * (size_t)grid->n_t;
+    const size_t C = (size_t)num_channels(d);
+    bsde_problem_s tmp;
+    tmp.n = (int)n;
+    tmp.M = M;
+    int groups, ppl;
+    auto_tiling(&tmp, groups, ppl);
+    const size_t sizes[] = {n * (d + 1) * 8, (size_t)p * n * 8, (C - 1) * p * p * 8,
+                            (size_t)(K_it + 1) * p * 8, (size_t)p * 8, (size_t)p * C * 8,
+                            (size_t)p * C * 4, (size_t)K_it * n * 8, (size_t)K_it * n * 8,
+                            n * groups * 16};
+    size_t total = 0;
+    for (size_t b : sizes) total += size_class(b == 0 ? 8 : b);
+    return total;
+}
+
+extern "C" {
+
+bsde_status bsde_solve_batch(bsde_problem *problems, int count,
                                         void *hip_stream, int flags, double *ms)
 {
     if (!problems || count < 1) return fail(BSDE_EINVAL, "no problems");

@@ -1,0 +1,52 @@
+// bsde_internal.h -- library-internal declarations shared by the C ABI
+// (bsde_host.cpp) and the request server (bsde_server.cpp).
+#pragma once
+
+#include "../../include/bsde.h"
+#include "bsde_common.h"
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+struct bsde_problem_s {
+    // parameters
+    int d = 0, eta = 0, M = 0, N = 0, K_it = 0, precision = 0;
+    double q = 1.0, omega = 0.0;
+    bsde::PathParams base{};
+    // sizes
+    int n = 0, n_spatial = 0, p = 0, C = 0;
+    std::vector<int8_t> nu;      // p x (d+1), kernel order
+    std::vector<char> active;    // in the hyperbolic set
+    std::vector<double> pts;     // n x (d+1)
+    std::vector<double> lo, hi;
+    std::vector<double> Dfirst;  // d x p x p: d_{x_j} channel matrices
+    // device
+    double *d_pts = nullptr, *d_W = nullptr, *d_D = nullptr,
+           *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
+           *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
+    float *d_g32 = nullptr;
+    size_t partial_cap = 0;
+    // state
+    int k_done = 0;
+    bool have_alpha = false;
+    std::vector<double> alpha_hist; // (K_it + 1) x p, host mirror
+    int groups = 0, ppl = 0;       // tiling (0 = automatic)
+    double timings[5] = {0, 0, 0, 0, 0};
+};
+
+
+namespace bsde {
+// records msg as the thread's last error and returns s
+bsde_status fail(bsde_status s, const std::string &msg);
+// runs `steps` Picard iterations (at most the remaining ones) of every
+// problem with the batched kernels; copies coefficient histories back
+// when copy_back is set
+bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s, int steps,
+                      bool graph, bool copy_back, double *ms);
+// copies the latest coefficients of a finished problem back to the host
+bsde_status fetch_coefficients(bsde_problem h);
+// device bytes a problem with these parameters allocates (pool size classes)
+size_t problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it);
+} // namespace bsde

@@ -139,12 +139,14 @@ __device__ __forceinline__ void cheb(Real z, Real *Tz)
 // paths m = (g * ppl + r) * kBlock + lane, r < ppl, m < M, of point i and
 // writes its FP64 sums (sum a_m, sum a_m^2) to partial[2 (i groups + g)].
 // ---------------------------------------------------------------------------
-template <int D, int ETA, typename Real, int VOL>
+// Gamma is read-only, uniform across the workgroup and read once per basis
+// function and channel per path: its loads must stay scalar (SGPR) loads,
+// so GammaPtr is a global restrict pointer or a constant-address-space one.
+template <int D, int ETA, typename Real, int VOL, typename GammaPtr>
 __device__ __forceinline__ void run_tile(const PathParams &prm,
                                          const double *__restrict__ pts,
-                                         const Real *__restrict__ gamma,
-                                         const int i, const int g,
-                                         double *__restrict__ out)
+                                         GammaPtr gamma, const int i,
+                                         const int g, double *__restrict__ out)
 {
     constexpr int DP = D + 1;
     constexpr int C = num_channels(D);
@@ -389,7 +391,14 @@ __global__ __launch_bounds__(kBlock) void batch_path_kernel(
     for (;;) {
         if (threadIdx.x == 0) next = (long long)atomicAdd(counter, 1u);
         __syncthreads();
-        const long long t = next;
+        // the tile index is the same in every lane: keep it (and the
+        // problem lookup and parameter loads that follow) scalar
+        const long long tl = next;
+        const long long t =
+            (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                             (int)(tl >> 32))
+                         << 32) |
+                        (unsigned)__builtin_amdgcn_readfirstlane((int)tl));
         __syncthreads();
         if (t >= total) break;
         int lo = 0, hi = nprob - 1; // last q with tile_begin[q] <= t
@@ -402,7 +411,8 @@ __global__ __launch_bounds__(kBlock) void batch_path_kernel(
         const long long local = t - tile_begin[lo];
         const int i = (int)(local / q.prm.groups);
         const int g = (int)(local - (long long)i * q.prm.groups);
-        run_tile<D, ETA, Real, VOL>(q.prm, q.pts, (const Real *)q.gamma, i, g,
+        using ConstReal = const __attribute__((address_space(4))) Real *;
+        run_tile<D, ETA, Real, VOL>(q.prm, q.pts, (ConstReal)q.gamma, i, g,
                                     q.partial + 2 * local);
     }
 }

@@ -101,10 +101,12 @@ def config4(omega: float = 100.0, precision: str = "fp32") -> dict:
                    K_it=10, precision=precision, seed=0)
 
 
-def serving_request(idx: int, rng: np.random.Generator) -> dict:
-    """One request of the serving mix: d in {1,2,5,10}, strike U[80,120],
-    European/American 50/50, M in {500,1000,2000,4000}, FP32 paths."""
-    d = int(rng.choice([1, 2, 5, 10]))
+def serving_request(idx: int, rng: np.random.Generator,
+                    dims=(1, 2, 5, 10)) -> dict:
+    """One request of the serving mix: d drawn from dims, strike U[80,120],
+    European/American 50/50, M in {500,1000,2000,4000}, FP32 paths; the
+    grid and Euler sizes of the benchmark workload of that dimension."""
+    d = int(rng.choice(list(dims)))
     K = float(rng.uniform(80.0, 120.0))
     american = bool(rng.integers(0, 2))
     M = int(rng.choice([500, 1000, 2000, 4000]))
