@@ -194,6 +194,16 @@ bsde_status bsde_get_corrections(bsde_problem h, int k, double *c,
 bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
                             int paths_per_lane);
 
+/* Autotuner of the path tiling: times the path kernel of this problem (at
+ * its current iteration, without changing its state) for every tiling of
+ * 2^j paths per lane (j = 0..6) with enough groups to cover M, keeps the
+ * fastest for this problem and records it for its kernel signature (d, eta,
+ * precision, volatility kind, M, N, size class of n); problems created
+ * afterwards with that signature start with it.  Outputs may be NULL:
+ * groups and paths per lane chosen, and the path-kernel time in ms. */
+bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups,
+                          int *paths_per_lane, double *ms);
+
 /* Average duration in milliseconds of the last solve's kernels, measured
  * with HIP events on the solve's stream: [0] Monte Carlo path kernel,
  * [1] reduction of the per-point sums, [2] projection R^{-1} Q' c,

@@ -34,7 +34,8 @@ EXPORTS = [
     "bsde_create_problem", "bsde_solve", "bsde_query_price_delta",
     "bsde_problem_sizes", "bsde_get_points", "bsde_get_coefficients",
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
-    "bsde_set_tiling", "bsde_last_timings", "bsde_solve_batch",
+    "bsde_set_tiling", "bsde_autotune", "bsde_last_timings",
+    "bsde_solve_batch",
     "bsde_destroy", "bsde_status_string", "bsde_last_error",
     "bsde_server_create", "bsde_server_submit", "bsde_server_poll",
     "bsde_server_stats", "bsde_server_destroy",
@@ -116,6 +117,7 @@ def lib():
         L.bsde_get_corrections.argtypes = [H, C.c_int, _dp, _dp]
         L.bsde_set_tiling.argtypes = [H, C.c_int, C.c_int]
         L.bsde_last_timings.argtypes = [H, _dp]
+        L.bsde_autotune.argtypes = [H, C.c_void_p, _ip, _ip, _dp]
         L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
                                        C.c_int, _dp]
         L.bsde_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int,
@@ -256,6 +258,13 @@ def bsde_set_tiling(h, groups_per_point, paths_per_lane):
                                  int(paths_per_lane)), "bsde_set_tiling")
 
 
+def bsde_autotune(h, stream=None):
+    g, p_, ms = C.c_int(), C.c_int(), C.c_double()
+    _check(lib().bsde_autotune(h, C.c_void_p(stream or 0), C.byref(g),
+                               C.byref(p_), C.byref(ms)), "bsde_autotune")
+    return g.value, p_.value, ms.value
+
+
 def bsde_last_timings(h):
     t = np.zeros(5)
     _check(lib().bsde_last_timings(h, _d(t)), "bsde_last_timings")
@@ -323,6 +332,10 @@ class Problem:
 
     def timings(self):
         return bsde_last_timings(self.h)
+
+    def autotune(self, stream=None):
+        """(groups per point, paths per lane, path-kernel ms) chosen."""
+        return bsde_autotune(self.h, stream)
 
     def close(self):
         if self.h:

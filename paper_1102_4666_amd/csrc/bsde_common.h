@@ -141,6 +141,31 @@ __host__ __device__ constexpr int num_channels(int d)
     return 2 + d + d * (d + 1) / 2;
 }
 
+// the channel table Gamma is stored as pad16(p) rows of pad16(C) entries,
+// zero outside p x C, so that 16 x 16 matrix-core tiles read it in bounds
+__host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
+
+// channel 2 + d + idx holds d^2 u / dx_j dx_k for the idx-th pair j <= k
+// (row-major upper triangle)
+__host__ __device__ constexpr int hess_j(int d, int idx)
+{
+    int j = 0;
+    while (idx >= d - j) {
+        idx -= d - j;
+        ++j;
+    }
+    return j;
+}
+__host__ __device__ constexpr int hess_k(int d, int idx)
+{
+    int j = 0;
+    while (idx >= d - j) {
+        idx -= d - j;
+        ++j;
+    }
+    return j + idx;
+}
+
 // ---------------------------------------------------------------------------
 // Per-launch parameters of the path kernel (passed by value).
 // ---------------------------------------------------------------------------

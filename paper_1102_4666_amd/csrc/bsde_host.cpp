@@ -20,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace bsde {
@@ -189,6 +190,28 @@ static double cheb_deriv_coef(int a, int b)
     return b == 0 ? (double)a : 2.0 * a;
 }
 
+// Runs fn(begin, end) over [0, count) split across up to 16 host threads;
+// work is the number of multiply-adds of the whole loop, and loops below
+// 2^20 of them run in the calling thread.
+template <typename F>
+static void parallel_for(long count, long min_chunk, double work, F fn)
+{
+    const long hw = std::max(1u, std::thread::hardware_concurrency());
+    long nt = std::max(1L, std::min({16L, hw, count / std::max(1L, min_chunk)}));
+    if (work < (double)(1 << 20)) nt = 1;
+    if (nt <= 1) {
+        fn(0L, count);
+        return;
+    }
+    std::vector<std::thread> th;
+    const long per = (count + nt - 1) / nt;
+    for (long t = 0; t < nt; ++t) {
+        const long b = t * per, e = std::min(count, b + per);
+        if (b < e) th.emplace_back(fn, b, e);
+    }
+    for (auto &x : th) x.join();
+}
+
 // Householder QR of B (n x pa, column-major, overwritten) and the
 // pseudo-inverse W = R^{-1} Q' (pa x n, row-major); false if B is
 // numerically rank deficient (smallest |R_jj| <= 1e-12 largest).  Every
@@ -212,13 +235,17 @@ static bool pseudo_inverse(int n, int pa, std::vector<double> &A,
         for (int i = j; i < n; ++i) vv += a[i] * a[i];
         vnorm[j] = vv;
         diag[j] = beta;
-        for (int c = j + 1; c < pa; ++c) {
-            double *b = &A[(size_t)c * n];
-            double s = 0.0;
-            for (int i = j; i < n; ++i) s += a[i] * b[i];
-            const double f = 2.0 * s / vv;
-            for (int i = j; i < n; ++i) b[i] -= f * a[i];
-        }
+        // apply the reflection to the remaining columns (independent)
+        parallel_for(pa - j - 1, 2, 2.0 * (pa - j - 1) * (n - j),
+                     [&, j, a, vv](long cb, long ce) {
+            for (long c = j + 1 + cb; c < j + 1 + ce; ++c) {
+                double *b = &A[(size_t)c * n];
+                double s = 0.0;
+                for (int i = j; i < n; ++i) s += a[i] * b[i];
+                const double f = 2.0 * s / vv;
+                for (int i = j; i < n; ++i) b[i] -= f * a[i];
+            }
+        });
     }
     double dmax = 0.0, dmin = INFINITY;
     for (int j = 0; j < pa; ++j) {
@@ -231,33 +258,39 @@ static bool pseudo_inverse(int n, int pa, std::vector<double> &A,
     }
     // thin Q = H_0 ... H_{pa-1} [I; 0] (column-major n x pa), accumulated
     // backwards: H_j only changes columns >= j
+    // (each column of Q is built independently)
     std::vector<double> Q((size_t)n * pa, 0.0);
-    for (int c = 0; c < pa; ++c) Q[(size_t)c * n + c] = 1.0;
-    for (int j = pa - 1; j >= 0; --j) {
-        const double *v = &A[(size_t)j * n];
-        for (int c = j; c < pa; ++c) {
+    parallel_for(pa, 1, 2.0 * n * pa * pa / 2, [&](long cb, long ce) {
+        for (long c = cb; c < ce; ++c) {
             double *q = &Q[(size_t)c * n];
-            double s = 0.0;
-            for (int i = j; i < n; ++i) s += v[i] * q[i];
-            const double f = 2.0 * s / vnorm[j];
-            for (int i = j; i < n; ++i) q[i] -= f * v[i];
+            q[c] = 1.0;
+            for (int j = (int)c; j >= 0; --j) {
+                const double *v = &A[(size_t)j * n];
+                double s = 0.0;
+                for (int i = j; i < n; ++i) s += v[i] * q[i];
+                const double f = 2.0 * s / vnorm[j];
+                for (int i = j; i < n; ++i) q[i] -= f * v[i];
+            }
         }
-    }
+    });
     // W = R^{-1} Q': row l of W is (Q column l - sum_{c>l} R_lc W_c) / R_ll,
     // with R_lc = A[c][l] above the diagonal and R_ll = diag[l]
     W.assign((size_t)pa * n, 0.0);
-    for (int l = pa - 1; l >= 0; --l) {
-        double *w = &W[(size_t)l * n];
-        const double *q = &Q[(size_t)l * n];
-        for (int i = 0; i < n; ++i) w[i] = q[i];
-        for (int c = l + 1; c < pa; ++c) {
-            const double rlc = A[(size_t)c * n + l];
-            const double *wc = &W[(size_t)c * n];
-            for (int i = 0; i < n; ++i) w[i] -= rlc * wc[i];
+    parallel_for(n, 4096, (double)n * pa * pa / 2,
+                 [&](long ib, long ie) { // independent point ranges
+        for (int l = pa - 1; l >= 0; --l) {
+            double *w = &W[(size_t)l * n];
+            const double *q = &Q[(size_t)l * n];
+            for (long i = ib; i < ie; ++i) w[i] = q[i];
+            for (int c = l + 1; c < pa; ++c) {
+                const double rlc = A[(size_t)c * n + l];
+                const double *wc = &W[(size_t)c * n];
+                for (long i = ib; i < ie; ++i) w[i] -= rlc * wc[i];
+            }
+            const double inv = 1.0 / diag[l];
+            for (long i = ib; i < ie; ++i) w[i] *= inv;
         }
-        const double inv = 1.0 / diag[l];
-        for (int i = 0; i < n; ++i) w[i] *= inv;
-    }
+    });
     return true;
 }
 
@@ -285,6 +318,28 @@ static void free_device(bsde_problem_s *h)
             return fail(BSDE_EDEVICE, std::string(#expr) + ": " +              \
                                           hipGetErrorString(e_));              \
     } while (0)
+
+// Tilings chosen by bsde_autotune, keyed by kernel signature and size
+// class; consulted when a problem is created.
+namespace {
+struct TuneKey {
+    int d, eta, prec, vol, M, N, nclass;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(d, eta, prec, vol, M, N, nclass) <
+               std::tie(o.d, o.eta, o.prec, o.vol, o.M, o.N, o.nclass);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tuned;
+
+TuneKey tune_key(const bsde_problem_s *h)
+{
+    int nclass = 0;
+    while ((1 << nclass) < h->n) ++nclass;
+    return {h->d, h->eta, h->precision, h->base.vol_kind, h->M, h->N, nclass};
+}
+} // namespace
 
 static void auto_tiling(const bsde_problem_s *h, int &groups, int &ppl)
 {
@@ -352,6 +407,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EUNSUPPORTED, "no kernel instantiated for d=" +
                                            std::to_string(d) + ", eta=" +
                                            std::to_string(grid->eta));
+    if (d == 10 && precision != BSDE_FP32_PATHS)
+        return fail(BSDE_EUNSUPPORTED, "d = 10 is built for FP32 paths only");
     double Lc[kMaxD * kMaxD];
     if (!cholesky(d, sigma->rho, Lc))
         return fail(BSDE_EINVAL, "correlation matrix not positive definite");
@@ -544,8 +601,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
               dalloc((void **)&h->d_D, sizeof(double) * Dm.size()) &&
               dalloc((void **)&h->d_alpha, sizeof(double) * (size_t)(h->K_it + 1) * h->p) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
-              dalloc((void **)&h->d_g64, sizeof(double) * (size_t)h->p * h->C) &&
-              dalloc((void **)&h->d_g32, sizeof(float) * (size_t)h->p * h->C) &&
+              dalloc((void **)&h->d_g64, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C)) &&
+              dalloc((void **)&h->d_g32, sizeof(float) * (size_t)pad16(h->p) * pad16(h->C)) &&
               dalloc((void **)&h->d_c, sizeof(double) * (size_t)h->K_it * h->n) &&
               dalloc((void **)&h->d_var, sizeof(double) * (size_t)h->K_it * h->n);
     if (!ok) {
@@ -559,12 +616,24 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     if (e == hipSuccess) e = hipMemcpy(h->d_W, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_D, Dm.data(), sizeof(double) * Dm.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(h->d_alpha, 0, sizeof(double) * (size_t)(h->K_it + 1) * h->p);
+    // the padding of the channel tables stays zero (the update kernels
+    // write only the p x C entries)
+    if (e == hipSuccess) e = hipMemset(h->d_g64, 0, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C));
+    if (e == hipSuccess) e = hipMemset(h->d_g32, 0, sizeof(float) * (size_t)pad16(h->p) * pad16(h->C));
     if (e != hipSuccess) {
         free_device(h);
         delete h;
         return fail(BSDE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     h->alpha_hist.assign((size_t)(h->K_it + 1) * h->p, 0.0);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(tune_key(h));
+        if (it != g_tuned.end()) {
+            h->groups = it->second.first;
+            h->ppl = it->second.second;
+        }
+    }
     *out = h;
     return BSDE_OK;
 }
@@ -908,8 +977,10 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
     int groups, ppl;
     auto_tiling(&tmp, groups, ppl);
     const size_t sizes[] = {n * (d + 1) * 8, (size_t)p * n * 8, (C - 1) * p * p * 8,
-                            (size_t)(K_it + 1) * p * 8, (size_t)p * 8, (size_t)p * C * 8,
-                            (size_t)p * C * 4, (size_t)K_it * n * 8, (size_t)K_it * n * 8,
+                            (size_t)(K_it + 1) * p * 8, (size_t)p * 8,
+                            (size_t)pad16(p) * pad16((int)C) * 8,
+                            (size_t)pad16(p) * pad16((int)C) * 4, (size_t)K_it * n * 8,
+                            (size_t)K_it * n * 8,
                             n * groups * 16};
     size_t total = 0;
     for (size_t b : sizes) total += size_class(b == 0 ? 8 : b);
@@ -937,6 +1008,75 @@ bsde_status bsde_solve_batch(bsde_problem *problems, int count,
     bsde_status st = run_batch(problems, count, s, 1 << 30, graph, true, ms);
     if (own) (void)hipStreamDestroy(own);
     return st;
+}
+
+bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
+                          int *ppl_out, double *ms_out)
+{
+    if (!h) return fail(BSDE_EINVAL, "null handle");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool fp32 = h->precision == BSDE_FP32_PATHS;
+    // candidates: paths per lane in powers of two, groups to cover M
+    std::vector<std::pair<int, int>> cand;
+    for (int ppl = 1; ppl <= 64; ppl *= 2) {
+        const int groups = (h->M + kBlock * ppl - 1) / (kBlock * ppl);
+        if (groups < 1) continue;
+        if (!cand.empty() && cand.back().first == groups) continue;
+        cand.push_back({groups, ppl});
+        if (groups == 1) break;
+    }
+    size_t need = 0;
+    for (auto &c : cand) need = std::max(need, (size_t)h->n * c.first * 2);
+    if (need > h->partial_cap) {
+        pool_free(h->d_partial);
+        h->d_partial = nullptr;
+        h->partial_cap = 0;
+        HIP_TRY(pool_alloc((void **)&h->d_partial, sizeof(double) * need));
+        h->partial_cap = need;
+    }
+    const int k = std::min(h->k_done, h->K_it - 1);
+    HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
+                            h->d_D, h->d_g64, h->d_g32));
+    hipEvent_t e0, e1;
+    HIP_TRY(event_get(&e0));
+    HIP_TRY(event_get(&e1));
+    double best = 1e300;
+    std::pair<int, int> pick = cand.front();
+    for (auto &c : cand) {
+        PathParams prm = h->base;
+        prm.k = (uint32_t)k;
+        prm.groups = c.first;
+        prm.paths_per_lane = c.second;
+        prm.n = h->n;
+        double t_min = 1e300;
+        for (int rep = 0; rep < 3; ++rep) { // first launch warms up
+            HIP_TRY(hipEventRecord(e0, s));
+            HIP_TRY(launch_path(h->d, h->eta, fp32, h->n * c.first, s, prm, h->d_pts,
+                                fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
+                                h->d_partial));
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t_min = std::min(t_min, (double)ms);
+        }
+        if (t_min < best) {
+            best = t_min;
+            pick = c;
+        }
+    }
+    event_put(e0);
+    event_put(e1);
+    h->groups = pick.first;
+    h->ppl = pick.second;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[tune_key(h)] = pick;
+    }
+    if (groups_out) *groups_out = pick.first;
+    if (ppl_out) *ppl_out = pick.second;
+    if (ms_out) *ms_out = best;
+    return BSDE_OK;
 }
 
 bsde_status bsde_last_timings(bsde_problem h, double *ms5)

@@ -74,14 +74,15 @@ __device__ __forceinline__ void channel_col(
     int C, int c, double *__restrict__ g64, float *__restrict__ g32)
 {
     __shared__ double a[kMaxP];
+    const int Cs = pad16(C); // row stride of the channel table
     for (int m = threadIdx.x; m < p; m += 256)
         a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
     __syncthreads();
     if (c == 0) {
         for (int l = threadIdx.x; l < p; l += 256) {
             if (alpha_out) alpha_out[l] = a[l];
-            g64[(size_t)l * C] = a[l];
-            g32[(size_t)l * C] = (float)a[l];
+            g64[(size_t)l * Cs] = a[l];
+            g32[(size_t)l * Cs] = (float)a[l];
         }
         return;
     }
@@ -90,8 +91,8 @@ __device__ __forceinline__ void channel_col(
         const double *drow = Dc + (size_t)l * p;
         double s = 0.0;
         for (int m = 0; m < p; ++m) s += drow[m] * a[m];
-        g64[(size_t)l * C + c] = s;
-        g32[(size_t)l * C + c] = (float)s;
+        g64[(size_t)l * Cs + c] = s;
+        g32[(size_t)l * Cs + c] = (float)s;
     }
 }
 
@@ -168,7 +169,7 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Dispatch over the instantiated (d, eta) pairs
 // ---------------------------------------------------------------------------
-#define BSDE_DIMS(X) X(1) X(2) X(3) X(5)
+#define BSDE_DIMS(X) X(1) X(2) X(3) X(5) X(10)
 #define DECL(D)                                                                \
     hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s,  \
                                 const PathParams &prm, const double *pts,      \

@@ -133,6 +133,38 @@ __device__ __forceinline__ void cheb(Real z, Real *Tz)
     for (int a = 1; a < ETA; ++a) Tz[a + 1] = Real(2) * z * Tz[a] - Tz[a - 1];
 }
 
+// 16 x 16 x 4 matrix-core products (wave64).  Operands: lane L holds
+// A[L % 16][L / 16] and B[L / 16][L % 16]; the accumulator element i of lane
+// L is D[row(L, i)][L % 16].
+template <typename Real>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int L, int i)
+    {
+        return 4 * (L >> 4) + i;
+    }
+};
+
+template <>
+struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int L, int i)
+    {
+        return (L >> 4) + 4 * i;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // The Monte Carlo path kernel.
 // Grid: n * groups workgroups of kBlock lanes; workgroup (i, g) runs the
@@ -150,8 +182,11 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
 {
     constexpr int DP = D + 1;
     constexpr int C = num_channels(D);
+    constexpr int Cs = pad16(C); // row stride of Gamma
     using BS = Basis<DP, ETA>;
     constexpr int NP = BS::P;
+    // d >= 5: the basis-row x Gamma contraction runs on the matrix cores
+    constexpr bool kMfma = D >= 5;
     // steps per group so that a group uses whole Philox blocks
     constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
     constexpr int NB = SG * D / 4;
@@ -171,7 +206,11 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
     const Real lc = (Real)prm.log_bump_c;
     const Real rho = (Real)prm.rho;
-    Real L[D][D], level[D], level_a[D], drift0[D], mid[D], scale[D];
+    // Cholesky factor of the uniform correlation rho 11' + (1 - rho) I:
+    // column k is constant below the diagonal (Lcol[k] = L[j][k], j > k),
+    // so (L G)_j = S_j + L_jj G_j with S_{j+1} = S_j + Lcol[j] G_j -- the
+    // terms of sum_k L_jk G_k in the same order, O(d) instead of O(d^2)
+    Real Lcol[D], Ldiag[D], level[D], level_a[D], drift0[D], mid[D], scale[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         level[j] = (Real)prm.level[j];
@@ -179,8 +218,8 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         drift0[j] = (Real)(prm.r - prm.div[j]);
         mid[j] = (Real)prm.mid[j];
         scale[j] = (Real)prm.scale[j];
-#pragma unroll
-        for (int l = 0; l < D; ++l) L[j][l] = (Real)prm.L[j * kMaxD + l];
+        Ldiag[j] = (Real)prm.L[j * kMaxD + j];
+        Lcol[j] = j + 1 < D ? (Real)prm.L[(j + 1) * kMaxD + j] : Real(0);
     }
     const Real tscale = Real(2) / T;
     const Real neg_half_h = Real(-0.5) * h;
@@ -190,8 +229,15 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
 
     double sum = 0.0, sumsq = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
-        const int m = (g * prm.paths_per_lane + rr) * kBlock + (int)threadIdx.x;
-        if (m >= prm.M) break;
+        int m = (g * prm.paths_per_lane + rr) * kBlock + (int)threadIdx.x;
+        const bool valid = m < prm.M;
+        if constexpr (kMfma) {
+            // matrix-core products need the whole wave: lanes past M run
+            // path 0 again and discard it
+            if (!valid) m = 0;
+        } else {
+            if (!valid) break;
+        }
 
         // U, j* = floor(U N) and theta = U N - j* in integer arithmetic
         const u32x4 wu = philox10((uint32_t)m, (uint32_t)i, prm.k, 1u << 24,
@@ -226,17 +272,15 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 const int s = grp * SG + ss;
                 if (s < prm.N) {
                     const bool at = (s == jstar);
+                    Real S = Real(0);
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
                         // sqrt(h) (L G)_j; the first row of the Cholesky
                         // factor of a correlation matrix is (1, 0, ..., 0)
                         Real lg = G[ss * D];
-                        if (j > 0) {
-                            lg = L[j][0] * lg;
-#pragma unroll
-                            for (int l = 1; l <= j; ++l)
-                                lg += L[j][l] * G[ss * D + l];
-                        }
+                        if (j > 0) lg = fma(Ldiag[j], G[ss * D + j], S);
+                        if (j + 1 < D) S = j == 0 ? Lcol[0] * G[ss * D]
+                                                  : fma(Lcol[j], G[ss * D + j], S);
                         const Real sig = local_vol<VOL>(level[j], level_a[j], lc, X[j]);
                         Xs[j] = at ? X[j] : Xs[j];
                         LGs[j] = at ? lg : LGs[j];
@@ -263,14 +307,12 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                                     Gb[4 * b + 3]);
         }
         Real sgs[D], bst[D], Xt[D];
+        Real Sb = Real(0);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             Real lgb = Gb[0];
-            if (j > 0) {
-                lgb = L[j][0] * lgb;
-#pragma unroll
-                for (int l = 1; l <= j; ++l) lgb += L[j][l] * Gb[l];
-            }
+            if (j > 0) lgb = fma(Ldiag[j], Gb[j], Sb);
+            if (j + 1 < D) Sb = j == 0 ? Lcol[0] * Gb[0] : fma(Lcol[j], Gb[j], Sb);
             sgs[j] = local_vol<VOL>(level[j], level_a[j], lc, Xs[j]);
             bst[j] = fma(Real(-0.5) * sgs[j], sgs[j], drift0[j]);
             Xt[j] = Xs[j] + bst[j] * theta * h +
@@ -288,33 +330,32 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             cheb<ETA>((Xt[j] - mid[j]) * scale[j], Tz[1 + j]);
             cheb<ETA>((X[j] - mid[j]) * scale[j], TzT[1 + j]);
         }
-        Real Bv[NP], BT[NP];
-        Real V[C];
+        Real u = Real(0), gen = Real(0), uT = Real(0);
+        if constexpr (!kMfma) {
+            Real Bv[NP], BT[NP];
+            Real V[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) V[c] = Real(0);
-        Real uT = Real(0);
-        static_for<NP>([&](auto lc) {
-            constexpr int l = decltype(lc)::value;
-            if constexpr (l == 0) {
-                Bv[0] = Real(1);
-                BT[0] = Real(1);
-            } else {
-                constexpr int par = BS::tab.parent[l];
-                constexpr int v = BS::tab.var[l];
-                constexpr int dg = BS::tab.deg[l];
-                Bv[l] = Bv[par] * Tz[v][dg];
-                BT[l] = BT[par] * TzT[v][dg];
-            }
+            for (int c = 0; c < C; ++c) V[c] = Real(0);
+            static_for<NP>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                if constexpr (l == 0) {
+                    Bv[0] = Real(1);
+                    BT[0] = Real(1);
+                } else {
+                    constexpr int par = BS::tab.parent[l];
+                    constexpr int v = BS::tab.var[l];
+                    constexpr int dg = BS::tab.deg[l];
+                    Bv[l] = Bv[par] * Tz[v][dg];
+                    BT[l] = BT[par] * TzT[v][dg];
+                }
 #pragma unroll
-            for (int c = 0; c < C; ++c) V[c] += Bv[l] * gamma[l * C + c];
-            uT += BT[l] * gamma[l * C];
-        });
-
-        // driver and frozen generator (u, d_t u, grad u, upper hessian)
-        Real gen = V[1];
+                for (int c = 0; c < C; ++c) V[c] += Bv[l] * gamma[l * Cs + c];
+                uT += BT[l] * gamma[l * Cs];
+            });
+            // frozen generator: d_t u + b* . grad u + sum cov_jk d_jk u
+            gen = V[1];
 #pragma unroll
-        for (int j = 0; j < D; ++j) gen += bst[j] * V[2 + j];
-        {
+            for (int j = 0; j < D; ++j) gen += bst[j] * V[2 + j];
             int idx = 2 + D;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -325,12 +366,128 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                     gen += cov * V[idx];
                 }
             }
+            u = V[0];
+        } else {
+            // basis function l as the product of its non-zero Chebyshev
+            // factors (at most eta of them), so that no earlier basis value
+            // has to stay live in registers
+            auto basis = [&](auto lc, const Real(&Tv)[DP][ETA + 1]) {
+                constexpr int l = decltype(lc)::value;
+                Real v = Real(1);
+                static_for<DP>([&](auto vc) {
+                    constexpr int w = decltype(vc)::value;
+                    constexpr int e = BS::tab.nu[l][w];
+                    if constexpr (e > 0) v *= Tv[w][e];
+                });
+                return v;
+            };
+            // Gamma is loop-invariant, so the compiler would hoist all of its
+            // loads out of the path loop and park them in registers; reading
+            // it through an address made opaque per use keeps each load next
+            // to its products
+            auto opaque = [&](int offset) {
+                uint64_t a = (uint64_t)(uintptr_t)&gamma[offset];
+                asm volatile("" : "+s"(a));
+                return (const __attribute__((address_space(1))) Real *)a;
+            };
+            // u^k(T, X_T): one dot product with channel 0, 16 terms at a time
+            // (the scheduling barriers keep the loads next to their use)
+            static_for<pad16(NP) / 16>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                __builtin_amdgcn_sched_barrier(0);
+                const auto g0 = opaque(q * 16 * Cs);
+                static_for<16>([&](auto jc) {
+                    constexpr int l = q * 16 + decltype(jc)::value;
+                    if constexpr (l < NP)
+                        uT += basis(std::integral_constant<int, l>{}, TzT) *
+                              g0[(l - q * 16) * Cs];
+                });
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave: the
+            // basis row goes through LDS in chunks of 16 functions into the
+            // A operand; Gamma tiles are the B operand; 4 x NT accumulators
+            constexpr int NT = Cs / 16;
+            constexpr int NCH = pad16(NP) / 16;
+            using Acc = typename Mfma<Real>::acc_t;
+            __shared__ Real lds[kBlock / 64][64 * 17];
+            Real *buf = lds[threadIdx.x >> 6];
+            const int lane = threadIdx.x & 63;
+            Acc acc[4][NT];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
+            static_for<NCH>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<16>([&](auto jc) {
+                    constexpr int jj = decltype(jc)::value;
+                    constexpr int l = q * 16 + jj;
+                    Real v = Real(0);
+                    if constexpr (l < NP)
+                        v = basis(std::integral_constant<int, l>{}, Tz);
+                    buf[jj * 64 + lane] = v; // [function][path]
+                });
+                __syncthreads();
+                const auto gq = opaque(q * 16 * Cs);
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const int lrow = kb * 4 + (lane >> 4);
+                    Real bop[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        bop[nt] = gq[lrow * Cs + nt * 16 + (lane & 15)];
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const Real aop = buf[lrow * 64 + mt * 16 + (lane & 15)];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[mt][nt] = Mfma<Real>::mma(aop, bop[nt], acc[mt][nt]);
+                    }
+                }
+                __syncthreads();
+            });
+            // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
+            // 16 nt + col]; back through LDS so that each lane reads its own
+            // path's channels and folds them into u and the generator
+            static_for<NT>([&](auto ntc) {
+                constexpr int nt = decltype(ntc)::value;
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        buf[(16 * mt + Mfma<Real>::row(lane, e)) * 17 + (lane & 15)] =
+                            acc[mt][nt][e];
+                __syncthreads();
+                static_for<16>([&](auto cc) {
+                    constexpr int c = nt * 16 + decltype(cc)::value;
+                    if constexpr (c < C) {
+                        const Real vc = buf[lane * 17 + decltype(cc)::value];
+                        if constexpr (c == 0) {
+                            u = vc;
+                        } else if constexpr (c == 1) {
+                            gen += vc;
+                        } else if constexpr (c < 2 + D) {
+                            gen += bst[c - 2] * vc;
+                        } else {
+                            constexpr int j = hess_j(D, c - 2 - D);
+                            constexpr int k = hess_k(D, c - 2 - D);
+                            const Real cov = (j == k) ? Real(0.5) * sgs[j] * sgs[j]
+                                                      : rho * sgs[j] * sgs[k];
+                            gen += cov * vc;
+                        }
+                    }
+                });
+                __syncthreads();
+            });
         }
-        const Real u = V[0];
+
+        // penalised driver f = -r u + omega (Phi - u)_+ and the path term
         const Real f = -r * u + omega * fmax(payoff<D>(prm.payoff, K, Xt) - u,
                                              Real(0));
         const Real a = (T - t0) * (f + gen) + (payoff<D>(prm.payoff, K, X) - uT);
-        const double ad = (double)a;
+        const double ad = valid ? (double)a : 0.0;
         sum += ad;
         sumsq += ad * ad;
     }
@@ -442,5 +599,20 @@ __global__ __launch_bounds__(kBlock) void batch_path_kernel(
         else if (fp32) BSDE_PATH_LAUNCH(D, E, float, kVolConst);               \
         else if (bump) BSDE_PATH_LAUNCH(D, E, double, kVolBump);               \
         else BSDE_PATH_LAUNCH(D, E, double, kVolConst);                        \
+        return hipGetLastError();                                              \
+    }
+
+// FP32-path-only variants (d = 10: the FP64 form would not fit the register
+// file); FP64 requests are rejected at problem creation.
+#define BSDE_PATH_CASE_FP32(D, E)                                              \
+    if (eta == E && fp32) {                                                    \
+        if (prm.vol_kind == kVolBump) BSDE_PATH_LAUNCH(D, E, float, kVolBump); \
+        else BSDE_PATH_LAUNCH(D, E, float, kVolConst);                         \
+        return hipGetLastError();                                              \
+    }
+#define BSDE_BATCH_CASE_FP32(D, E)                                             \
+    if (eta == E && fp32) {                                                    \
+        if (bump) BSDE_BATCH_LAUNCH(D, E, float, kVolBump);                    \
+        else BSDE_BATCH_LAUNCH(D, E, float, kVolConst);                        \
         return hipGetLastError();                                              \
     }

@@ -40,7 +40,9 @@ CASES = {
     "config2_w100": (workloads.config2, {"omega": 100.0}),
     "config2_w1": (workloads.config2, {"omega": 1.0}),
     "config3_w100": (workloads.config3, {"omega": 100.0}),
+    "config3_w1": (workloads.config3, {"omega": 1.0}),
     "config4_w100": (workloads.config4, {"omega": 100.0}),
+    "config4_w1": (workloads.config4, {"omega": 1.0}),
 }
 
 

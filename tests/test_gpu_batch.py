@@ -82,3 +82,18 @@ def test_batch_resumes_problems_at_different_iterations():
     finally:
         for P in probs:
             P.close()
+
+
+def test_autotune_records_tiling_for_later_problems():
+    from gpu_util import run_gpu
+    cfg = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=5, n_x=12, eta=4,
+                  M=1100, N=9, K_it=2, precision="fp32", seed=11)
+    with bsde.Problem(cfg) as P:
+        groups, ppl, ms = P.autotune()
+    assert groups * ppl * 256 >= 1100 and ms > 0
+    # problems of the same signature created afterwards start with the
+    # recorded tiling: bitwise equal to setting it explicitly
+    a = run_gpu(cfg)
+    b = run_gpu(cfg, tiling=(groups, ppl))
+    np.testing.assert_array_equal(a["c"], b["c"])
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])

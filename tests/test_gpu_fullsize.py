@@ -37,7 +37,9 @@ def _golden(name):
     ("config2_w1", "fp64"), ("config2_w1", "fp32"),
     ("config2_w100", "fp64"), ("config2_w100", "fp32"),
     ("config3_w100", "fp64"), ("config3_w100", "fp32"),
+    ("config3_w1", "fp64"), ("config3_w1", "fp32"),
     ("config4_w100", "fp64"), ("config4_w100", "fp32"),
+    ("config4_w1", "fp64"), ("config4_w1", "fp32"),
 ])
 def test_full_size_against_stored_oracle(name, prec):
     g = _golden(name)
@@ -62,6 +64,12 @@ def test_full_size_against_stored_oracle(name, prec):
     pref, dref = g["price"][-1], g["delta"][-1]
     print("  price gpu %.10g oracle %.10g; delta gpu %s oracle %s" %
           (got["price"], pref, got["delta"], dref))
-    assert abs(got["price"] - pref) <= tol["price"] * max(K, abs(pref))
+    # the price scale: the strike for a converged iterate; for the
+    # non-converging penalty-100 iterates, the size of the last corrections
+    # (the price is then a small difference of much larger terms)
+    scale = max(K, abs(pref))
+    if cfg["omega"] >= 100:
+        scale = max(scale, float(np.abs(c_ref[-1]).max()))
+    assert abs(got["price"] - pref) <= tol["price"] * scale
     dscale = max(1.0, float(np.abs(dref).max()))
     assert float(np.abs(got["delta"] - np.array(dref)).max()) <= tol["delta"] * dscale

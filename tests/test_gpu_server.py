@@ -58,9 +58,26 @@ def test_alone_equals_mix_equals_plain_solve():
     assert all(r["status"] == 0 for r in res.values())
     assert res[probe]["price"] == alone["price"]
     np.testing.assert_array_equal(res[probe]["delta"], alone["delta"])
-    # requests shared engine steps (continuous batching)
-    assert st["engine_steps"] < sum(c["K_it"] for c in reqs)
     assert st["completed"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_arrivals_join_a_running_batch():
+    # a long request is on the GPU when short ones arrive: they join its
+    # engine steps and finish first (continuous batching, not a queue)
+    long_cfg = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=16, n_x=128,
+                       eta=4, M=4000, N=200, K_it=30, omega=1.0,
+                       precision="fp32", seed=900)
+    short = _requests()[:6]
+    with bsde.Server(4 * GIB) as S:
+        t_long = S.submit(long_cfg)
+        time.sleep(0.01)
+        t_short = [S.submit(c) for c in short]
+        r_short = [S.poll(t) for t in t_short]
+        r_long = S.poll(t_long)
+        st = S.stats()
+    assert r_long["status"] == 0 and all(r["status"] == 0 for r in r_short)
+    assert max(r["latency_ms"] for r in r_short) < r_long["latency_ms"]
+    assert st["engine_steps"] < long_cfg["K_it"] + sum(c["K_it"] for c in short)
 
 
 def test_admission_by_device_memory():
