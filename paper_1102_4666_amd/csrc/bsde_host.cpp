@@ -1,7 +1,8 @@
-// bsde_host.cpp -- C ABI of libbsde.so: problem set-up on the host (index
-// set, grid, Chebyshev basis, rank-checked Householder QR, pseudo-inverse
-// R^{-1} Q', derivative channel matrices), device buffers, the Picard loop
-// that launches the HIP kernels, and the price/delta read-out.
+// bsde_host.cpp -- C ABI of libbsde.so: problem set-up (index set, grid,
+// derivative channel matrices on the host; the Chebyshev basis matrix and
+// its rank-checked pseudo-inverse R^{-1} Q' by CholeskyQR2 on the device),
+// device buffers, the Picard loop that launches the HIP kernels, and the
+// price/delta read-out.
 //
 // The method is Algorithm "algodetail" of Labart & Lelong (arXiv:1102.4666,
 // Section 4.1); the least-squares extrapolating operator is that of
@@ -46,6 +47,16 @@ hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
 hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
                                  const BatchUpdateDesc *d);
 hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s);
+hipError_t launch_basis_matrix(const double *pts, int n, int ld, int dp,
+                               const int8_t *nu, int pa, int pap,
+                               const double *mid, const double *scale,
+                               double T, double *B, hipStream_t s);
+hipError_t launch_gram(const double *A, int ld, int pap, int rows_per_chunk,
+                       int chunks, const int2 *pairs, int npairs,
+                       double *partial, int pa, double *G, hipStream_t s);
+hipError_t launch_gemm_ax(const double *A, int ld, const double *X, int pap,
+                          double *Y, int ldy, int nrows, const int *colmap,
+                          int ncols, hipStream_t s);
 } // namespace bsde
 
 using namespace bsde;
@@ -212,86 +223,224 @@ static void parallel_for(long count, long min_chunk, double work, F fn)
     for (auto &x : th) x.join();
 }
 
-// Householder QR of B (n x pa, column-major, overwritten) and the
-// pseudo-inverse W = R^{-1} Q' (pa x n, row-major); false if B is
-// numerically rank deficient (smallest |R_jj| <= 1e-12 largest).  Every
-// inner loop is a contiguous dot product or axpy of length <= n.
-static bool pseudo_inverse(int n, int pa, std::vector<double> &A,
-                           std::vector<double> &W, std::string &why)
+// Upper Cholesky factor R of a symmetric positive definite G (p x p,
+// row-major): G = R'R.  Right-looking; false when a pivot is not positive
+// or falls below rel_tol times the largest diagonal entry of R.
+static bool chol_upper(const std::vector<double> &G, int p, double rel_tol,
+                       std::vector<double> &R)
 {
-    std::vector<double> vnorm(pa), diag(pa);
-    for (int j = 0; j < pa; ++j) {
-        double *a = &A[(size_t)j * n];
-        double nrm2 = 0.0;
-        for (int i = j; i < n; ++i) nrm2 += a[i] * a[i];
-        const double nrm = std::sqrt(nrm2);
-        if (nrm == 0.0) {
-            why = "basis matrix has a zero column";
-            return false;
-        }
-        const double beta = a[j] >= 0.0 ? -nrm : nrm;
-        a[j] -= beta; // a[j..n) now holds the Householder vector v
-        double vv = 0.0;
-        for (int i = j; i < n; ++i) vv += a[i] * a[i];
-        vnorm[j] = vv;
-        diag[j] = beta;
-        // apply the reflection to the remaining columns (independent)
-        parallel_for(pa - j - 1, 2, 2.0 * (pa - j - 1) * (n - j),
-                     [&, j, a, vv](long cb, long ce) {
-            for (long c = j + 1 + cb; c < j + 1 + ce; ++c) {
-                double *b = &A[(size_t)c * n];
-                double s = 0.0;
-                for (int i = j; i < n; ++i) s += a[i] * b[i];
-                const double f = 2.0 * s / vv;
-                for (int i = j; i < n; ++i) b[i] -= f * a[i];
+    R = G;
+    double dmax = 0.0;
+    for (int j = 0; j < p; ++j) dmax = std::max(dmax, G[(size_t)j * p + j]);
+    dmax = std::sqrt(std::max(dmax, 0.0));
+    for (int j = 0; j < p; ++j) {
+        double *rj = &R[(size_t)j * p];
+        const double piv = rj[j];
+        if (!(piv > 0.0) || !(std::sqrt(piv) > rel_tol * dmax)) return false;
+        const double r = std::sqrt(piv);
+        for (int c = j; c < p; ++c) rj[c] /= r;
+        // trailing update of the upper triangle, rows independent
+        parallel_for(p - j - 1, 8, 0.5 * (double)(p - j) * (p - j),
+                     [&, j, rj](long b, long e) {
+            for (long rr = j + 1 + b; rr < j + 1 + e; ++rr) {
+                double *row = &R[(size_t)rr * p];
+                const double f = rj[rr];
+                for (int c = (int)rr; c < p; ++c) row[c] -= f * rj[c];
             }
         });
     }
-    double dmax = 0.0, dmin = INFINITY;
-    for (int j = 0; j < pa; ++j) {
-        dmax = std::max(dmax, std::fabs(diag[j]));
-        dmin = std::min(dmin, std::fabs(diag[j]));
-    }
-    if (!(dmin > 1e-12 * dmax)) {
-        why = "basis matrix is numerically rank deficient on the grid";
-        return false;
-    }
-    // thin Q = H_0 ... H_{pa-1} [I; 0] (column-major n x pa), accumulated
-    // backwards: H_j only changes columns >= j
-    // (each column of Q is built independently)
-    std::vector<double> Q((size_t)n * pa, 0.0);
-    parallel_for(pa, 1, 2.0 * n * pa * pa / 2, [&](long cb, long ce) {
-        for (long c = cb; c < ce; ++c) {
-            double *q = &Q[(size_t)c * n];
-            q[c] = 1.0;
-            for (int j = (int)c; j >= 0; --j) {
-                const double *v = &A[(size_t)j * n];
-                double s = 0.0;
-                for (int i = j; i < n; ++i) s += v[i] * q[i];
-                const double f = 2.0 * s / vnorm[j];
-                for (int i = j; i < n; ++i) q[i] -= f * v[i];
-            }
-        }
-    });
-    // W = R^{-1} Q': row l of W is (Q column l - sum_{c>l} R_lc W_c) / R_ll,
-    // with R_lc = A[c][l] above the diagonal and R_ll = diag[l]
-    W.assign((size_t)pa * n, 0.0);
-    parallel_for(n, 4096, (double)n * pa * pa / 2,
-                 [&](long ib, long ie) { // independent point ranges
-        for (int l = pa - 1; l >= 0; --l) {
-            double *w = &W[(size_t)l * n];
-            const double *q = &Q[(size_t)l * n];
-            for (long i = ib; i < ie; ++i) w[i] = q[i];
-            for (int c = l + 1; c < pa; ++c) {
-                const double rlc = A[(size_t)c * n + l];
-                const double *wc = &W[(size_t)c * n];
-                for (long i = ib; i < ie; ++i) w[i] -= rlc * wc[i];
-            }
-            const double inv = 1.0 / diag[l];
-            for (long i = ib; i < ie; ++i) w[i] *= inv;
-        }
-    });
+    for (int r = 1; r < p; ++r)
+        for (int c = 0; c < r; ++c) R[(size_t)r * p + c] = 0.0;
     return true;
+}
+
+// Inverse of an upper triangular R (p x p, row-major), column by column
+static std::vector<double> tri_inv_upper(const std::vector<double> &R, int p)
+{
+    std::vector<double> X((size_t)p * p, 0.0);
+    parallel_for(p, 8, (double)p * p * p / 6, [&](long b, long e) {
+        for (long c = b; c < e; ++c) {
+            X[(size_t)c * p + c] = 1.0 / R[(size_t)c * p + c];
+            for (long r = c - 1; r >= 0; --r) {
+                double s = 0.0;
+                for (long k = r + 1; k <= c; ++k) s += R[(size_t)r * p + k] * X[(size_t)k * p + c];
+                X[(size_t)r * p + c] = -s / R[(size_t)r * p + r];
+            }
+        }
+    });
+    return X;
+}
+
+// Set-up streams (non-blocking, one per concurrent set-up, reused)
+namespace {
+std::mutex g_stream_mu;
+std::map<int, std::vector<hipStream_t>> g_setup_streams;
+hipError_t setup_stream_get(hipStream_t *s)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> g(g_stream_mu);
+        auto &v = g_setup_streams[dev];
+        if (!v.empty()) {
+            *s = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+void setup_stream_put(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> g(g_stream_mu);
+    g_setup_streams[dev].push_back(s);
+}
+} // namespace
+
+// Shapes of the set-up: the leading dimension of the n x pap point matrices
+// and the row chunks of the Gram kernel (about 2048 waves over the
+// 64 x 64 block pairs, at least 256 rows each)
+static void setup_shape(int n, int pap, int &ld, int &rpc, int &chunks)
+{
+    ld = (n + 63) & ~63;
+    const int nb = (pap + 63) / 64;
+    const int want = std::max(1, 2048 / (nb * (nb + 1) / 2));
+    rpc = std::max(256, ((ld + want - 1) / want + 15) & ~15);
+    chunks = (ld + rpc - 1) / rpc;
+}
+
+// Pseudo-inverse W = B^+ (p x n, row-major; rows of inactive multi-indices
+// zero) of the basis matrix of the grid by CholeskyQR2 on the device:
+// B (n x pa) is formed from the device copy of the points, the Gram
+// matrices and the tall-skinny products run on the device, the two pa x pa
+// Cholesky factorisations and triangular inverses on the host.  Returns
+// BSDE_ERANK when B is numerically rank deficient (a Cholesky pivot of B'B
+// below 1e-7 of the largest, i.e. a condition number beyond ~1e7).
+static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<int> &act)
+{
+    const int n = h->n, pa = (int)act.size(), pap = pad16(pa), dp = h->d + 1;
+    std::vector<int2> pairs;
+    const int nb = (pap + 63) / 64;
+    for (int bi = 0; bi < nb; ++bi)
+        for (int bj = bi; bj < nb; ++bj) pairs.push_back(make_int2(bi, bj));
+    int ld, rpc, chunks;
+    setup_shape(n, pap, ld, rpc, chunks);
+    std::vector<int8_t> nu_act((size_t)pa * dp);
+    for (int c = 0; c < pa; ++c)
+        std::memcpy(&nu_act[(size_t)c * dp], &h->nu[(size_t)act[c] * dp], dp);
+    std::vector<double> ms(2 * kMaxD, 0.0);
+    for (int j = 0; j < h->d; ++j) {
+        ms[j] = h->base.mid[j];
+        ms[kMaxD + j] = h->base.scale[j];
+    }
+
+    double *dB = nullptr, *dQ = nullptr, *dPart = nullptr, *dG = nullptr,
+           *dX = nullptr, *dMS = nullptr;
+    int8_t *dNu = nullptr;
+    int2 *dPairs = nullptr;
+    int *dMap = nullptr;
+    hipStream_t s = nullptr;
+    bsde_status st = BSDE_OK;
+    std::string why;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e == hipSuccess || st != BSDE_OK) return st == BSDE_OK;
+        st = e == hipErrorOutOfMemory ? BSDE_ENOMEM : BSDE_EDEVICE;
+        why = std::string(what) + ": " + hipGetErrorString(e);
+        return false;
+    };
+    std::vector<double> G((size_t)pa * pa), R1, R2;
+    do {
+        if (!chk(setup_stream_get(&s), "set-up stream")) break;
+        if (!chk(pool_alloc((void **)&dB, sizeof(double) * ld * pap), "device allocation") ||
+            !chk(pool_alloc((void **)&dQ, sizeof(double) * ld * pap), "device allocation") ||
+            !chk(pool_alloc((void **)&dPart, sizeof(double) * chunks * pap * pap), "device allocation") ||
+            !chk(pool_alloc((void **)&dG, sizeof(double) * pa * pa), "device allocation") ||
+            !chk(pool_alloc((void **)&dX, sizeof(double) * pap * pap), "device allocation") ||
+            !chk(pool_alloc((void **)&dMS, sizeof(double) * ms.size()), "device allocation") ||
+            !chk(pool_alloc((void **)&dNu, nu_act.size()), "device allocation") ||
+            !chk(pool_alloc((void **)&dPairs, sizeof(int2) * pairs.size()), "device allocation") ||
+            !chk(pool_alloc((void **)&dMap, sizeof(int) * pa), "device allocation"))
+            break;
+        if (!chk(hipMemcpyAsync(dNu, nu_act.data(), nu_act.size(), hipMemcpyHostToDevice, s), "upload") ||
+            !chk(hipMemcpyAsync(dMS, ms.data(), sizeof(double) * ms.size(), hipMemcpyHostToDevice, s), "upload") ||
+            !chk(hipMemcpyAsync(dPairs, pairs.data(), sizeof(int2) * pairs.size(), hipMemcpyHostToDevice, s), "upload") ||
+            !chk(hipMemcpyAsync(dMap, act.data(), sizeof(int) * pa, hipMemcpyHostToDevice, s), "upload"))
+            break;
+        // B and G1 = B'B
+        if (!chk(launch_basis_matrix(h->d_pts, n, ld, dp, dNu, pa, pap, dMS, dMS + kMaxD,
+                                     h->base.T, dB, s), "basis kernel") ||
+            !chk(launch_gram(dB, ld, pap, rpc, chunks, dPairs, (int)pairs.size(), dPart, pa, dG, s),
+                 "gram kernel") ||
+            !chk(hipMemcpyAsync(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s),
+                 "download") ||
+            !chk(hipStreamSynchronize(s), "set-up"))
+            break;
+        if (!chol_upper(G, pa, 1e-7, R1)) {
+            st = BSDE_ERANK;
+            why = "basis matrix is numerically rank deficient on the grid";
+            break;
+        }
+        // Q1 = B R1^{-1} (all pap columns: the padding comes out zero)
+        const std::vector<double> X1 = tri_inv_upper(R1, pa);
+        std::vector<double> Xp((size_t)pap * pap, 0.0);
+        for (int r = 0; r < pa; ++r)
+            std::memcpy(&Xp[(size_t)r * pap], &X1[(size_t)r * pa], sizeof(double) * pa);
+        if (!chk(hipMemcpyAsync(dX, Xp.data(), sizeof(double) * Xp.size(), hipMemcpyHostToDevice, s),
+                 "upload") ||
+            !chk(launch_gemm_ax(dB, ld, dX, pap, dQ, ld, ld, nullptr, pap, s), "gemm kernel") ||
+            !chk(launch_gram(dQ, ld, pap, rpc, chunks, dPairs, (int)pairs.size(), dPart, pa, dG, s),
+                 "gram kernel") ||
+            !chk(hipMemcpyAsync(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s),
+                 "download") ||
+            !chk(hipStreamSynchronize(s), "set-up"))
+            break;
+        if (!chol_upper(G, pa, 1e-3, R2)) {
+            st = BSDE_ERANK;
+            why = "basis matrix is numerically rank deficient on the grid";
+            break;
+        }
+        // B^+' = Q1 P with P = R2^{-1} R2^{-T} R1^{-T}
+        const std::vector<double> Y2 = tri_inv_upper(R2, pa);
+        std::vector<double> T2((size_t)pa * pa, 0.0); // R2^{-1} R2^{-T}
+        parallel_for(pa, 8, (double)pa * pa * pa / 3, [&](long b, long e) {
+            for (long r = b; r < e; ++r)
+                for (int c = 0; c < pa; ++c) {
+                    double v = 0.0;
+                    for (int k = (int)std::max<long>(r, c); k < pa; ++k)
+                        v += Y2[(size_t)r * pa + k] * Y2[(size_t)c * pa + k];
+                    T2[(size_t)r * pa + c] = v;
+                }
+        });
+        std::fill(Xp.begin(), Xp.end(), 0.0);
+        parallel_for(pa, 8, (double)pa * pa * pa / 2, [&](long b, long e) {
+            for (long r = b; r < e; ++r)
+                for (int c = 0; c < pa; ++c) {
+                    double v = 0.0; // sum_k T2[r][k] X1[c][k], X1 upper
+                    for (int k = c; k < pa; ++k) v += T2[(size_t)r * pa + k] * X1[(size_t)c * pa + k];
+                    Xp[(size_t)r * pap + c] = v;
+                }
+        });
+        if (pa < h->p &&
+            !chk(hipMemsetAsync(h->d_W, 0, sizeof(double) * (size_t)h->p * n, s), "memset"))
+            break;
+        if (!chk(hipMemcpyAsync(dX, Xp.data(), sizeof(double) * Xp.size(), hipMemcpyHostToDevice, s),
+                 "upload") ||
+            !chk(launch_gemm_ax(dQ, ld, dX, pap, h->d_W, n, n, dMap, pa, s), "gemm kernel") ||
+            !chk(hipStreamSynchronize(s), "set-up"))
+            break;
+    } while (false);
+    if (s) {
+        if (st != BSDE_OK) (void)hipStreamSynchronize(s);
+        setup_stream_put(s);
+    }
+    for (void *q : {(void *)dB, (void *)dQ, (void *)dPart, (void *)dG, (void *)dX,
+                    (void *)dMS, (void *)dNu, (void *)dPairs, (void *)dMap})
+        pool_free(q);
+    if (st != BSDE_OK) return fail(st, why);
+    return BSDE_OK;
 }
 
 static void free_device(bsde_problem_s *h)
@@ -517,35 +666,6 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         delete h;
         return fail(BSDE_ERANK, "fewer points than basis functions");
     }
-    // column-major basis matrix: B[c][i] = prod_v T_{nu_v}(z_v(point i))
-    std::vector<double> B((size_t)h->n * pa);
-    {
-        std::vector<double> Tz((size_t)dp * (h->eta + 1));
-        for (int i = 0; i < h->n; ++i) {
-            const double *row = &h->pts[(size_t)i * dp];
-            double z[kMaxD + 1];
-            z[0] = 2.0 * row[0] / payoff->T - 1.0;
-            for (int j = 0; j < d; ++j) z[1 + j] = (row[1 + j] - b.mid[j]) * b.scale[j];
-            for (int v = 0; v < dp; ++v)
-                for (int a = 0; a <= h->eta; ++a)
-                    Tz[(size_t)v * (h->eta + 1) + a] = cheb_value(a, z[v]);
-            for (int c = 0; c < pa; ++c) {
-                const int8_t *e = &h->nu[(size_t)act[c] * dp];
-                double v = 1.0;
-                for (int w = 0; w < dp; ++w) v *= Tz[(size_t)w * (h->eta + 1) + e[w]];
-                B[(size_t)c * h->n + i] = v;
-            }
-        }
-    }
-    std::vector<double> Wa;
-    std::string why;
-    if (!pseudo_inverse(h->n, pa, B, Wa, why)) {
-        delete h;
-        return fail(BSDE_ERANK, why);
-    }
-    std::vector<double> W((size_t)h->p * h->n, 0.0);
-    for (int c = 0; c < pa; ++c)
-        std::memcpy(&W[(size_t)act[c] * h->n], &Wa[(size_t)c * h->n], sizeof(double) * h->n);
 
     // channel matrices: first derivatives in each variate, then products
     std::map<std::vector<int8_t>, int> pos;
@@ -597,7 +717,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return alloc_err == hipSuccess;
     };
     bool ok = dalloc((void **)&h->d_pts, sizeof(double) * h->pts.size()) &&
-              dalloc((void **)&h->d_W, sizeof(double) * W.size()) &&
+              dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n) &&
               dalloc((void **)&h->d_D, sizeof(double) * Dm.size()) &&
               dalloc((void **)&h->d_alpha, sizeof(double) * (size_t)(h->K_it + 1) * h->p) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
@@ -613,7 +733,6 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(alloc_err));
     }
     hipError_t e = hipMemcpy(h->d_pts, h->pts.data(), sizeof(double) * h->pts.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h->d_W, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_D, Dm.data(), sizeof(double) * Dm.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(h->d_alpha, 0, sizeof(double) * (size_t)(h->K_it + 1) * h->p);
     // the padding of the channel tables stays zero (the update kernels
@@ -624,6 +743,13 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         free_device(h);
         delete h;
         return fail(BSDE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    // pseudo-inverse of the basis matrix of the grid, on the device
+    const bsde_status pst = device_pseudo_inverse(h, act);
+    if (pst != BSDE_OK) {
+        free_device(h);
+        delete h;
+        return pst; // the last error is already recorded
     }
     h->alpha_hist.assign((size_t)(h->K_it + 1) * h->p, 0.0);
     {
@@ -984,6 +1110,11 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
                             n * groups * 16};
     size_t total = 0;
     for (size_t b : sizes) total += size_class(b == 0 ? 8 : b);
+    // transient set-up buffers: two point matrices and the Gram partials
+    int ld, rpc, chunks;
+    setup_shape((int)n, pad16(p), ld, rpc, chunks);
+    total += 2 * size_class((size_t)ld * pad16(p) * 8) +
+             size_class((size_t)chunks * pad16(p) * pad16(p) * 8);
     return total;
 }
 
