@@ -179,6 +179,20 @@ enum PayoffKind {
     kQuad = 5
 };
 
+// Per-asset constants of the path kernel in the path precision, rounded
+// once on the host: the kernel reads them as uniform scalar operands instead
+// of converting them into vector registers.
+template <typename Real>
+struct AssetConsts {
+    Real level[kMaxD];   // volatility level
+    Real level_a[kMaxD]; // level x bump height
+    Real drift[kMaxD];   // r - dividend
+    Real mid[kMaxD];     // domain centre
+    Real scale[kMaxD];   // 2 / (hi - lo)
+    Real Ldiag[kMaxD];   // Cholesky diagonal L_jj
+    Real Lcol[kMaxD];    // L_{j+1, j}: column j below the diagonal (constant)
+};
+
 struct PathParams {
     uint64_t seed;
     uint32_t k;          // Picard iteration (counter word 2)
@@ -195,7 +209,46 @@ struct PathParams {
     double rho;
     double mid[kMaxD];         // domain centre
     double scale[kMaxD];       // 2 / (hi - lo)
+    AssetConsts<float> cf;     // the per-asset constants in FP32
+    AssetConsts<double> cd;    // and in FP64
 };
+
+template <typename Real>
+__host__ __device__ __forceinline__ const AssetConsts<Real> &asset_consts(const PathParams &p);
+template <>
+__host__ __device__ __forceinline__ const AssetConsts<float> &asset_consts<float>(const PathParams &p)
+{
+    return p.cf;
+}
+template <>
+__host__ __device__ __forceinline__ const AssetConsts<double> &asset_consts<double>(const PathParams &p)
+{
+    return p.cd;
+}
+
+// fills cf and cd from the FP64 parameters (level, div, bump_a, mid,
+// scale, L and r must be set; d assets)
+__host__ inline void fill_asset_consts(PathParams &p, int d)
+{
+    for (int j = 0; j < kMaxD; ++j) {
+        const bool on = j < d;
+        const double v[7] = {on ? p.level[j] : 0.0,
+                             on ? p.level[j] * p.bump_a : 0.0,
+                             on ? p.r - p.div[j] : 0.0,
+                             on ? p.mid[j] : 0.0,
+                             on ? p.scale[j] : 0.0,
+                             on ? p.L[j * kMaxD + j] : 0.0,
+                             j + 1 < d ? p.L[(j + 1) * kMaxD + j] : 0.0};
+        double *dd[7] = {p.cd.level, p.cd.level_a, p.cd.drift, p.cd.mid,
+                         p.cd.scale, p.cd.Ldiag, p.cd.Lcol};
+        float *ff[7] = {p.cf.level, p.cf.level_a, p.cf.drift, p.cf.mid,
+                        p.cf.scale, p.cf.Ldiag, p.cf.Lcol};
+        for (int c = 0; c < 7; ++c) {
+            dd[c][j] = v[c];
+            ff[c][j] = (float)v[c];
+        }
+    }
+}
 
 // One problem of a batched launch (see batch_path_kernel).
 struct BatchTileDesc {

@@ -597,6 +597,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         b.mid[j] = 0.5 * (h->lo[j] + h->hi[j]);
         b.scale[j] = 2.0 / (h->hi[j] - h->lo[j]);
     }
+    fill_asset_consts(b, d);
 
     // index set in kernel order; hyperbolic subset marked active
     const int dp = d + 1;

@@ -197,35 +197,20 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     const double *row = pts + (size_t)i * DP;
     const Real T = (Real)prm.T;
     const Real t0 = (Real)row[0];
-    Real x0[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) x0[j] = (Real)row[1 + j];
     const Real h = (T - t0) / (Real)prm.N;
     // step normals come out of Box-Muller already scaled by sqrt(h)
     const Real step_scale = Arith<Real>::bm_scale(h);
     const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
     const Real lc = (Real)prm.log_bump_c;
     const Real rho = (Real)prm.rho;
-    // Cholesky factor of the uniform correlation rho 11' + (1 - rho) I:
-    // column k is constant below the diagonal (Lcol[k] = L[j][k], j > k),
+    // per-asset constants, read as uniform scalars where they are used.
+    // The Cholesky factor of the uniform correlation rho 11' + (1 - rho) I
+    // has columns constant below the diagonal (Lcol[k] = L[j][k], j > k),
     // so (L G)_j = S_j + L_jj G_j with S_{j+1} = S_j + Lcol[j] G_j -- the
     // terms of sum_k L_jk G_k in the same order, O(d) instead of O(d^2)
-    Real Lcol[D], Ldiag[D], level[D], level_a[D], drift0[D], mid[D], scale[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        level[j] = (Real)prm.level[j];
-        level_a[j] = (Real)(prm.level[j] * prm.bump_a);
-        drift0[j] = (Real)(prm.r - prm.div[j]);
-        mid[j] = (Real)prm.mid[j];
-        scale[j] = (Real)prm.scale[j];
-        Ldiag[j] = (Real)prm.L[j * kMaxD + j];
-        Lcol[j] = j + 1 < D ? (Real)prm.L[(j + 1) * kMaxD + j] : Real(0);
-    }
+    const AssetConsts<Real> &ac = asset_consts<Real>(prm);
     const Real tscale = Real(2) / T;
     const Real neg_half_h = Real(-0.5) * h;
-    Real drift_h[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) drift_h[j] = drift0[j] * h;
 
     double sum = 0.0, sumsq = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
@@ -251,8 +236,8 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         Real X[D], Xs[D], LGs[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            X[j] = x0[j];
-            Xs[j] = x0[j];
+            X[j] = (Real)row[1 + j];
+            Xs[j] = X[j];
             LGs[j] = Real(0);
         }
         const int ngroups = (prm.N + SG - 1) / SG;
@@ -278,15 +263,15 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         // sqrt(h) (L G)_j; the first row of the Cholesky
                         // factor of a correlation matrix is (1, 0, ..., 0)
                         Real lg = G[ss * D];
-                        if (j > 0) lg = fma(Ldiag[j], G[ss * D + j], S);
-                        if (j + 1 < D) S = j == 0 ? Lcol[0] * G[ss * D]
-                                                  : fma(Lcol[j], G[ss * D + j], S);
-                        const Real sig = local_vol<VOL>(level[j], level_a[j], lc, X[j]);
+                        if (j > 0) lg = fma(ac.Ldiag[j], G[ss * D + j], S);
+                        if (j + 1 < D) S = j == 0 ? ac.Lcol[0] * G[ss * D]
+                                                  : fma(ac.Lcol[j], G[ss * D + j], S);
+                        const Real sig = local_vol<VOL>(ac.level[j], ac.level_a[j], lc, X[j]);
                         Xs[j] = at ? X[j] : Xs[j];
                         LGs[j] = at ? lg : LGs[j];
                         // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
                         //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2)
-                        X[j] = fma(sig, fma(neg_half_h, sig, lg), X[j]) + drift_h[j];
+                        X[j] = fma(ac.drift[j], h, fma(sig, fma(neg_half_h, sig, lg), X[j]));
                     }
                 }
             }
@@ -311,10 +296,10 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             Real lgb = Gb[0];
-            if (j > 0) lgb = fma(Ldiag[j], Gb[j], Sb);
-            if (j + 1 < D) Sb = j == 0 ? Lcol[0] * Gb[0] : fma(Lcol[j], Gb[j], Sb);
-            sgs[j] = local_vol<VOL>(level[j], level_a[j], lc, Xs[j]);
-            bst[j] = fma(Real(-0.5) * sgs[j], sgs[j], drift0[j]);
+            if (j > 0) lgb = fma(ac.Ldiag[j], Gb[j], Sb);
+            if (j + 1 < D) Sb = j == 0 ? ac.Lcol[0] * Gb[0] : fma(ac.Lcol[j], Gb[j], Sb);
+            sgs[j] = local_vol<VOL>(ac.level[j], ac.level_a[j], lc, Xs[j]);
+            bst[j] = fma(Real(-0.5) * sgs[j], sgs[j], ac.drift[j]);
             Xt[j] = Xs[j] + bst[j] * theta * h +
                     sgs[j] * fma(theta, LGs[j], lgb);
         }
@@ -327,10 +312,13 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         for (int a = 0; a <= ETA; ++a) TzT[0][a] = Real(1);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            cheb<ETA>((Xt[j] - mid[j]) * scale[j], Tz[1 + j]);
-            cheb<ETA>((X[j] - mid[j]) * scale[j], TzT[1 + j]);
+            cheb<ETA>((Xt[j] - ac.mid[j]) * ac.scale[j], Tz[1 + j]);
+            cheb<ETA>((X[j] - ac.mid[j]) * ac.scale[j], TzT[1 + j]);
         }
-        Real u = Real(0), gen = Real(0), uT = Real(0);
+        // payoff at tau (for the penalty) and the terminal term
+        // Phi(X_T) - u^k(T, X_T)
+        Real phi_tau = payoff<D>(prm.payoff, K, Xt);
+        Real u = Real(0), gen = Real(0), uT = Real(0), terminal;
         if constexpr (!kMfma) {
             Real Bv[NP], BT[NP];
             Real V[C];
@@ -367,7 +355,9 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 }
             }
             u = V[0];
+            terminal = payoff<D>(prm.payoff, K, X) - uT;
         } else {
+            asm volatile("" : "+v"(phi_tau));
             // basis function l as the product of its non-zero Chebyshev
             // factors (at most eta of them), so that no earlier basis value
             // has to stay live in registers
@@ -385,10 +375,12 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             // loads out of the path loop and park them in registers; reading
             // it through an address made opaque per use keeps each load next
             // to its products
+            // (constant address space: Gamma does not change during the
+            // launch, so uniform reads of it are scalar loads)
             auto opaque = [&](int offset) {
                 uint64_t a = (uint64_t)(uintptr_t)&gamma[offset];
                 asm volatile("" : "+s"(a));
-                return (const __attribute__((address_space(1))) Real *)a;
+                return (const __attribute__((address_space(4))) Real *)a;
             };
             // u^k(T, X_T): one dot product with channel 0, 16 terms at a time
             // (the scheduling barriers keep the loads next to their use)
@@ -403,6 +395,10 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                               g0[(l - q * 16) * Cs];
                 });
             });
+            // the terminal term is complete here (nothing of X_T stays live
+            // through the contraction)
+            terminal = payoff<D>(prm.payoff, K, X) - uT;
+            asm volatile("" : "+v"(terminal));
             __builtin_amdgcn_sched_barrier(0);
             // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave: the
             // basis row goes through LDS in chunks of 16 functions into the
@@ -484,9 +480,8 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         }
 
         // penalised driver f = -r u + omega (Phi - u)_+ and the path term
-        const Real f = -r * u + omega * fmax(payoff<D>(prm.payoff, K, Xt) - u,
-                                             Real(0));
-        const Real a = (T - t0) * (f + gen) + (payoff<D>(prm.payoff, K, X) - uT);
+        const Real f = -r * u + omega * fmax(phi_tau - u, Real(0));
+        const Real a = (T - t0) * (f + gen) + terminal;
         const double ad = valid ? (double)a : 0.0;
         sum += ad;
         sumsq += ad * ad;
