@@ -136,6 +136,17 @@ __device__ __forceinline__ void cheb(Real z, Real *Tz)
 // 16 x 16 x 4 matrix-core products (wave64).  Operands: lane L holds
 // A[L % 16][L / 16] and B[L / 16][L % 16]; the accumulator element i of lane
 // L is D[row(L, i)][L % 16].
+// Each wave of the matrix-core contraction stages its operands in its own
+// LDS slice, so ordering its LDS writes before its reads needs no workgroup
+// barrier: a wave's LDS operations complete in issue order, and the
+// wavefront-scope fences keep the compiler from moving them across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename Real>
 struct Mfma;
 
@@ -425,7 +436,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         v = basis(std::integral_constant<int, l>{}, Tz);
                     buf[jj * 64 + lane] = v; // [function][path]
                 });
-                __syncthreads();
+                wave_lds_sync();
                 const auto gq = opaque(q * 16 * Cs);
 #pragma unroll
                 for (int kb = 0; kb < 4; ++kb) {
@@ -442,7 +453,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                             acc[mt][nt] = Mfma<Real>::mma(aop, bop[nt], acc[mt][nt]);
                     }
                 }
-                __syncthreads();
+                wave_lds_sync();
             });
             // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
             // 16 nt + col]; back through LDS so that each lane reads its own
@@ -455,7 +466,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                     for (int e = 0; e < 4; ++e)
                         buf[(16 * mt + Mfma<Real>::row(lane, e)) * 17 + (lane & 15)] =
                             acc[mt][nt][e];
-                __syncthreads();
+                wave_lds_sync();
                 static_for<16>([&](auto cc) {
                     constexpr int c = nt * 16 + decltype(cc)::value;
                     if constexpr (c < C) {
@@ -475,7 +486,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         }
                     }
                 });
-                __syncthreads();
+                wave_lds_sync();
             });
         }
 
@@ -514,10 +525,22 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     __syncthreads(); // red[] may be reused by the next tile
 }
 
+// Waves per SIMD the register allocation must allow: d = 10 in FP32 with
+// the local volatility needs about 270 registers a lane at its natural
+// schedule (one wave per SIMD, so nothing hides the matrix-core and LDS
+// latencies); two waves fit in 256 with a little rematerialisation.  The
+// constant-volatility form keeps more per-asset Euler terms live and would
+// spill at two waves, so it stays at one.
+template <int D, typename Real, int VOL>
+constexpr int min_waves()
+{
+    return (D >= 10 && sizeof(Real) == 4 && VOL == kVolBump) ? 2 : 1;
+}
+
 // One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
 // writes its sums to partial[2 b].
 template <int D, int ETA, typename Real, int VOL>
-__global__ __launch_bounds__(kBlock) void path_kernel(
+__global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void path_kernel(
     const PathParams prm, const double *__restrict__ pts,
     const Real *__restrict__ gamma, double *__restrict__ partial)
 {
@@ -534,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void path_kernel(
 // computes exactly what the one-problem kernel computes for the same
 // (i, g), so a problem's result does not depend on the batch.
 template <int D, int ETA, typename Real, int VOL>
-__global__ __launch_bounds__(kBlock) void batch_path_kernel(
+__global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void batch_path_kernel(
     const BatchTileDesc *__restrict__ probs, int nprob,
     const long long *__restrict__ tile_begin, unsigned int *counter)
 {
