@@ -32,11 +32,23 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # 3.93e13 full-rate lane-ops/s
 FP32_VECTOR_PEAK = 157.3e12                     # FLOP/s (packed FMA)
 FP64_VECTOR_PEAK = 78.6e12
-# HBM bytes per launch of the path kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (separate runs), scaled by the plain-copy calibration factors
-# (x2.0 and x1.0); None until measured for the current kernel.
-TRAFFIC = {"fp32": 173.75 * 2.0 * 1024 + 64.0 * 1024,
-           "fp64": 261.75 * 2.0 * 1024 + 64.0 * 1024}
+# HBM traffic of one path-kernel launch of the benchmark workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (separate runs, KiB per dispatch) by
+# tiling (workgroups per point), scaled by the plain-copy calibration
+# factors (x2.0 and x1.0).  The autotuner picks the tiling at run time;
+# a tiling missing here reports null.
+TRAFFIC_KIB = {"fp32": {1: (185, 64), 2: (313, 128), 4: (313, 256),
+                        8: (313, 512), 16: (315, 1024)},
+               "fp64": {1: (269, 64), 2: (397, 128), 4: (397, 256),
+                        8: (397, 512), 16: (399, 1024)}}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+
+def traffic_bytes(precision, groups):
+    fw = TRAFFIC_KIB.get(precision, {}).get(groups)
+    if fw is None:
+        return None
+    return (fw[0] * FETCH_FACTOR + fw[1] * WRITE_FACTOR) * 1024
 
 
 # Algorithmic work per Euler path-step of the path kernel for the d = 1
@@ -50,9 +62,9 @@ TRAFFIC = {"fp32": 173.75 * 2.0 * 1024 + 64.0 * 1024,
 # (FMA = 2, transcendental = 1): Box-Muller 5.5 + local vol 6 + Euler 5 +
 # per-path work 250 / N.  FP64 paths use software transcendentals with no
 # independent operation count: their figure is the measured SQ_INSTS_VALU
-# minus SQ_INSTS_VALU_TRANS_F64 per path-step (209.9 - 2.7).
+# minus SQ_INSTS_VALU_TRANS_F64 per path-step (213.3 - 2.7).
 OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.5 + 5 + 3 + 3 + 270 / 50.0 - 3.12,
-                     "fp64": 207.2}
+                     "fp64": 210.6}
 FP32_FLOP_PER_PATH_STEP = 5.5 + 6 + 5 + 250 / 50.0
 
 
@@ -104,6 +116,72 @@ def accuracy(precision: str, stream):
     return out
 
 
+def batched_vs_fp64(stream, reps: int = 2):
+    """The batched FP32-path form against the plain FP64 per-problem form on
+    the same GPU: three problems (the d = 1, 2 and 5 workloads, penalty
+    100) solved in one bsde_solve_batch call (one persistent path launch per
+    Picard step, the schedule captured as a hipGraph), against the same
+    three solved one after the other by bsde_solve in FP64.  Both are
+    checked against the stored FP64 oracle results of the same streams."""
+    import torch
+
+    import paper_1102_4666_amd as bsde
+    import workloads
+    names = ("config2", "config3", "config4")
+    gold = {}
+    for nm in names:
+        path = os.path.join(ROOT, "tests", "golden", nm + "_w100.json")
+        if os.path.exists(path):
+            with open(path) as f:
+                g = json.load(f)
+            gold[nm] = (g["price"][-1], g["delta"][-1])
+
+    def run(prec, batched):
+        probs = [bsde.Problem(getattr(workloads, nm)(precision=prec))
+                 for nm in names]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if batched:
+            bsde.solve_batch(probs, stream, graph=True)
+        else:
+            for P in probs:
+                P.solve(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = sum(P.n * P.cfg["M"] * P.cfg["N"] * P.cfg["K_it"]
+                    for P in probs)
+        err = {}
+        for nm, P in zip(names, probs):
+            price, delta = P.price_delta()
+            if nm in gold:
+                ref_p, ref_d = gold[nm]
+                # prices of the penalised problem at penalty 100 are far
+                # from K (the iteration diverges); errors relative to the
+                # oracle's own price
+                err[nm] = {"rel_price_err": abs(price[0] - ref_p) / max(1.0, abs(ref_p)),
+                           "max_rel_delta_err": float(np.max(
+                               np.abs(delta[0] - np.asarray(ref_d)) /
+                               np.maximum(1.0, np.abs(ref_d))))}
+            P.close()
+        return dt, steps, err
+
+    out = {}
+    for prec, batched, key in (("fp32", True, "batched_fp32_paths"),
+                               ("fp64", False, "per_problem_fp64")):
+        run(prec, batched)  # warm-up (kernel load, tuning table)
+        best = None
+        for _ in range(reps):
+            dt, steps, err = run(prec, batched)
+            best = dt if best is None else min(best, dt)
+        out[key] = {"seconds": best, "path_steps": steps,
+                    "path_steps_per_s": steps / best, "error_vs_oracle": err}
+    out["problems"] = "d=1 (128x16 grid, M=4000), d=2 (32^2x16, M=2000), " \
+                      "d=5 (4096x10, M=1000); N=50, penalty 100"
+    out["speedup"] = out["per_problem_fp64"]["seconds"] / \
+        out["batched_fp32_paths"]["seconds"]
+    return out
+
+
 def cpu_baseline(cfg, seconds: float = 12.0):
     """The oracle on a bounded sample: per-point corrections of iteration 1
     (coefficients present, so u^k and its derivatives are evaluated on every
@@ -126,7 +204,7 @@ def cpu_baseline(cfg, seconds: float = 12.0):
                       (n_sub, n, cfg["M"], cfg["N"], steps, dt)}
 
 
-def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5)):
+def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
     """Serving run: closed-loop saturation, then Poisson arrivals at 0.5 and
     0.9 of the saturation rate; p50/p99 latency and throughput per phase."""
     import torch
@@ -161,10 +239,18 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5)):
             wall = time.perf_counter() - t0
             st = S.stats()
         bad = [r["status"] for r in res if r["status"] != 0]
+        per_d = {}
+        for cfg, r in zip(reqs, res):
+            per_d.setdefault(cfg["d"], []).append(r["latency_ms"])
         return {"offered_rate": rate, "requests": len(reqs), "failed": len(bad),
                 "wall_s": wall, "requests_per_s": st["requests_per_s"],
                 "path_steps_per_s": st["path_steps_per_s"],
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "latency_ms_by_d": {
+                    "d=%d" % d: {"n": len(v),
+                                 "p50": float(np.percentile(v, 50)),
+                                 "max": float(np.max(v))}
+                    for d, v in sorted(per_d.items())},
                 "engine_steps": st["engine_steps"]}
 
     print("serving: saturation phase", file=sys.stderr, flush=True)
@@ -173,10 +259,34 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5)):
           file=sys.stderr, flush=True)
     x_sat = sat["requests_per_s"]
     return {"mix": "d in %s, K U[80,120], European/American 50/50, M in "
-                   "{500,1000,2000,4000}, FP32 paths" % (list(dims),),
+                   "{500,1000,2000,4000} (d=10: 8192x10 random points, "
+                   "eta=3, every other request at M=500), FP32 paths"
+                   % (list(dims),),
             "hbm_budget_bytes": budget, "saturation": sat,
             "load_0.5": run_phase(0.5 * x_sat),
             "load_0.9": run_phase(0.9 * x_sat)}
+
+
+def single_launches(names):
+    """One Picard iteration (one path-kernel launch) of each named workload,
+    FP32 paths, default tiling: the runs behind the profiles of the
+    matrix-core kernels.  Names: config2, config3, config4, d10-serving (the
+    d=10 request shape of the serving mix at M=500)."""
+    import paper_1102_4666_amd as bsde
+    import workloads
+    out = {}
+    for nm in names:
+        if nm == "d10-serving":
+            cfg = workloads.serving_request(1, np.random.default_rng(0), dims=(10,))
+            cfg.update(M=500, K=100.0, omega=1.0)
+        else:
+            cfg = getattr(workloads, nm)(precision="fp32")
+        cfg.update(K_it=1)
+        with bsde.Problem(cfg) as P:
+            P.solve()
+            out[nm] = {"path_kernel_ms": P.timings()[0],
+                       "path_steps": P.n * cfg["M"] * cfg["N"]}
+    return out
 
 
 def main():
@@ -189,12 +299,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the error check against stored oracle results")
-    ap.add_argument("--serve", type=int, default=0, metavar="R",
-                    help="also run the request-server benchmark with R "
-                         "requests per load level")
+    ap.add_argument("--serve", type=int, default=24, metavar="R",
+                    help="requests per load level of the request-server "
+                         "benchmark (0 = skip it)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-FP32 vs per-problem-FP64 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the "
                          "HBM byte counters of the profiler)")
+    ap.add_argument("--single-launch", default="", metavar="NAMES",
+                    help="comma-separated workloads (config2, config3, "
+                         "config4, d10-serving): run one path-kernel launch "
+                         "of each and print its time, nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU "
@@ -214,6 +330,9 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4,
                           "copy_bytes_written": dst.numel() * 4,
                           "copies": 3}))
+        return
+    if args.single_launch:
+        print(json.dumps(single_launches(args.single_launch.split(","))))
         return
     stream = torch.cuda.current_stream().cuda_stream
     cfg = workload(args.precision)
@@ -276,7 +395,7 @@ def main():
                      "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "T VALU lane-ops/s (transcendentals excluded)",
                      "frac": achieved / VALU_PEAK_LANE_OPS,
-                     "traffic": TRAFFIC.get(args.precision)},
+                     "traffic": traffic_bytes(args.precision, tiling[0])},
     }
     if args.precision == "fp32":
         fl = FP32_FLOP_PER_PATH_STEP * launch_steps / t_path
@@ -285,8 +404,10 @@ def main():
                                      "frac": fl / FP32_VECTOR_PEAK}
     if not args.no_accuracy:
         line["accuracy_vs_oracle"] = accuracy(args.precision, stream)
+    if not args.no_batched:
+        line["batched_vs_fp64_per_problem"] = batched_vs_fp64(stream)
     if args.serve:
-        line["serving"] = serve(args.serve)
+        line["serving"] = serve(args.serve, dims=(1, 2, 5, 10))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(workload("fp64"), args.cpu_seconds)
     print(json.dumps(line), flush=True)

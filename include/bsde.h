@@ -196,8 +196,10 @@ bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
 
 /* Autotuner of the path tiling: times the path kernel of this problem (at
  * its current iteration, without changing its state) for every tiling of
- * 2^j paths per lane (j = 0..6) with enough groups to cover M, keeps the
- * fastest for this problem and records it for its kernel signature (d, eta,
+ * 2^j paths per lane (j = 0..6) with enough groups to cover M (best of 4
+ * timed launches each; a tiling with fewer groups replaces the current
+ * choice only when more than 2% faster), keeps the choice for this problem
+ * and records it for its kernel signature (d, eta,
  * precision, volatility kind, M, N, size class of n); problems created
  * afterwards with that signature start with it.  Outputs may be NULL:
  * groups and paths per lane chosen, and the path-kernel time in ms. */
@@ -235,9 +237,10 @@ void bsde_destroy(bsde_problem h);
  * requests.  Requests are admitted while their device footprint fits the
  * HBM budget and fewer than max_inflight are in flight; set-up threads
  * build admitted problems while the GPU works; one engine thread advances
- * all in-flight problems by one Picard iteration per step with the batched
- * kernels (bsde_solve_batch), so requests arriving while others run join
- * at the next step.  Each problem's coefficients stay resident on the
+ * all in-flight problems with the batched kernels (bsde_solve_batch) step
+ * by step, so requests arriving while others run join at the next step.
+ * A step lasts about one Picard iteration of its most expensive problem;
+ * cheaper problems run several of their iterations in it (at most 16).  Each problem's coefficients stay resident on the
  * device across its iterations.  A request's result is identical whether it
  * runs alone or in a mix.  All server calls are thread-safe.
  * ------------------------------------------------------------------------ */
@@ -264,6 +267,7 @@ typedef struct {
     double delta[10];        /* dollar deltas (first d entries)             */
     double latency_ms;       /* submit to completion                        */
     double queue_ms;         /* submit to admission                         */
+    int engine_steps;        /* engine steps the request took part in       */
 } bsde_result;
 
 typedef struct {

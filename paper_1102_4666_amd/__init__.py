@@ -78,7 +78,7 @@ class Request(C.Structure):
 class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("price", C.c_double),
                 ("delta", C.c_double * 10), ("latency_ms", C.c_double),
-                ("queue_ms", C.c_double)]
+                ("queue_ms", C.c_double), ("engine_steps", C.c_int)]
 
 
 class ServerStats(C.Structure):
@@ -390,7 +390,7 @@ class Server:
         _check(st, "bsde_server_poll")
         return {"status": r.status, "price": r.price,
                 "delta": np.array(r.delta[:]), "latency_ms": r.latency_ms,
-                "queue_ms": r.queue_ms}
+                "queue_ms": r.queue_ms, "engine_steps": r.engine_steps}
 
     def stats(self):
         st = ServerStats()

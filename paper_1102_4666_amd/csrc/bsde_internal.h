@@ -40,11 +40,12 @@ struct bsde_problem_s {
 namespace bsde {
 // records msg as the thread's last error and returns s
 bsde_status fail(bsde_status s, const std::string &msg);
-// runs `steps` Picard iterations (at most the remaining ones) of every
-// problem with the batched kernels; copies coefficient histories back
-// when copy_back is set
+// runs `steps` Picard iterations (steps_each[q] for problem q when given;
+// at most the remaining ones) of every problem with the batched kernels;
+// copies coefficient histories back when copy_back is set
 bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s, int steps,
-                      bool graph, bool copy_back, double *ms);
+                      bool graph, bool copy_back, double *ms,
+                      const int *steps_each = nullptr);
 // copies the latest coefficients of a finished problem back to the host
 bsde_status fetch_coefficients(bsde_problem h);
 // device bytes a problem with these parameters allocates (pool size classes)

@@ -115,3 +115,27 @@ def test_unsupported_and_concurrent_clients():
         assert r is None or r["status"] == 0
         if r is None:
             assert S.poll(t)["status"] == 0
+
+
+def test_cheap_requests_chain_iterations_beside_a_heavy_one():
+    # an engine step lasts about one iteration of the heaviest problem, so
+    # a cheap request in flight beside it runs several of its iterations
+    # per step -- and its result is still the one it gets alone
+    heavy = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=16, n_x=128,
+                    eta=4, M=4000, N=200, K_it=40, omega=1.0,
+                    precision="fp32", seed=901)   # ~2 ms per iteration
+    cheap = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=6, n_x=20, eta=4,
+                    M=256, N=10, K_it=8, omega=1.0, precision="fp32",
+                    seed=902)
+    with bsde.Server(4 * GIB) as S:
+        alone = S.poll(S.submit(cheap))
+    with bsde.Server(4 * GIB) as S:
+        th = S.submit(heavy)
+        time.sleep(0.02)        # the heavy request is on the GPU by now
+        tc = S.submit(cheap)
+        rc, rh = S.poll(tc), S.poll(th)
+    assert rh["status"] == 0 and rc["status"] == 0
+    assert rh["engine_steps"] == heavy["K_it"]
+    assert rc["engine_steps"] <= 2, rc["engine_steps"]
+    assert rc["price"] == alone["price"]
+    np.testing.assert_array_equal(rc["delta"], alone["delta"])
