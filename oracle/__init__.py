@@ -61,6 +61,7 @@ class Problem(C.Structure):
         ("K_it", C.c_int),
         ("omega", C.c_double),
         ("seed", C.c_uint64),
+        ("redraw", C.c_int),
     ]
 
 
@@ -101,6 +102,7 @@ def lib():
         L.oracle_num_basis.argtypes = [P]
         L.oracle_domain.argtypes = [P, _dp, _dp]
         L.oracle_points.argtypes = [P, _dp]
+        L.oracle_points_k.argtypes = [P, C.c_uint32, _dp]
         L.oracle_cholesky.argtypes = [C.c_int, C.c_double, _dp]
         L.oracle_lstsq.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
         L.oracle_payoff.argtypes = [P, _dp]
@@ -120,6 +122,7 @@ def lib():
                                    _dp]
         L.oracle_fit.argtypes = [P, _dp, _dp]
         L.oracle_basis_matrix.argtypes = [P, _dp]
+        L.oracle_basis_matrix_k.argtypes = [P, C.c_uint32, _dp]
         L.oracle_price_delta.argtypes = [P, _dp, C.c_int, _dp, _dp, _dp,
                                          _dp]
         _lib = L
@@ -166,6 +169,7 @@ def make_problem(cfg: dict) -> Problem:
     p.K_it = int(cfg["K_it"])
     p.omega = float(cfg.get("omega", 0.0))
     p.seed = int(cfg.get("seed", 0))
+    p.redraw = int(bool(cfg.get("redraw", 0)))
     return p
 
 
@@ -206,11 +210,12 @@ def domain(cfg):
     return lo, hi
 
 
-def points(cfg):
+def points(cfg, k=0):
+    """The points of Picard iteration k (the fixed grid unless redraw)."""
     pb = make_problem(cfg)
     n = lib().oracle_num_points(C.byref(pb))
     pts = np.zeros((n, pb.d + 1))
-    lib().oracle_points(C.byref(pb), _d(pts))
+    lib().oracle_points_k(C.byref(pb), k, _d(pts))
     return pts
 
 
@@ -318,12 +323,12 @@ def solve(cfg, k_start=0, alpha_start=None, k_end=None):
     return {"alpha": ah, "c": ch, "var": vh, "u": uh, "n": n, "p": p}
 
 
-def basis_matrix(cfg):
+def basis_matrix(cfg, k=0):
     pb = make_problem(cfg)
     n = lib().oracle_num_points(C.byref(pb))
     p = lib().oracle_num_basis(C.byref(pb))
     B = np.zeros((n, p))
-    lib().oracle_basis_matrix(C.byref(pb), _d(B))
+    lib().oracle_basis_matrix_k(C.byref(pb), k, _d(B))
     return B
 
 
@@ -345,7 +350,10 @@ def solve_parallel(cfg, workers=8, chunk=64, k_start=0, alpha_start=None,
     ranges = [(i, min(i + chunk, n)) for i in range(0, n, chunk)]
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
+        redraw = bool(cfg.get("redraw", 0)) and cfg.get("grid") == "random"
         for k in range(k_start, k_end):
+            if redraw:
+                B = basis_matrix(cfg, k)
             args = [(cfg, alpha if have else None, k, a, b) for a, b in ranges]
             parts = pool.starmap(corrections, args)
             c = np.concatenate([x[0] for x in parts])

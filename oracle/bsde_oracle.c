@@ -183,7 +183,16 @@ int oracle_num_points(const oracle_problem *pb)
 
 int oracle_points(const oracle_problem *pb, double *pts)
 {
+    return oracle_points_k(pb, 0, pts);
+}
+
+/* Algorithm 1 draws the n points uniformly at every iteration; with the
+ * fixed time nodes of the grid reading only the spatial coordinates are
+ * redrawn, from the counter (b, 0, k, substream 2 | block). */
+int oracle_points_k(const oracle_problem *pb, uint32_t k, double *pts)
+{
     int d = pb->d;
+    uint32_t kdraw = (pb->redraw && pb->grid == ORACLE_GRID_RANDOM) ? k : 0;
     long ns = n_spatial(pb);
     double lo[ORACLE_DMAX], hi[ORACLE_DMAX];
     oracle_domain(pb, lo, hi);
@@ -203,7 +212,7 @@ int oracle_points(const oracle_problem *pb, double *pts)
                             : 0.0;
                 } else {
                     uint32_t w[4];
-                    philox_block(pb->seed, (uint32_t)b, 0, 0, 2,
+                    philox_block(pb->seed, (uint32_t)b, 0, kdraw, 2,
                                  (uint32_t)(j / 4), w);
                     z = 2.0 * u01(w[j % 4]) - 1.0;
                 }
@@ -521,7 +530,7 @@ void oracle_corrections(const oracle_problem *pb, const double *alpha,
     double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
     double *a = (double *)malloc(sizeof(double) * (size_t)pb->M);
     oracle_index_set(d + 1, pb->eta, pb->q, nu, p);
-    oracle_points(pb, pts);
+    oracle_points_k(pb, k, pts);
     for (int i = i_begin; i < i_end; ++i)
         correction_at_point(pb, nu, p, alpha, pts + (size_t)i * (d + 1),
                             (uint32_t)i, k, a, &c[i - i_begin],
@@ -555,11 +564,16 @@ static void basis_matrix(const oracle_problem *pb, const int *nu, int p,
 
 void oracle_basis_matrix(const oracle_problem *pb, double *B)
 {
+    oracle_basis_matrix_k(pb, 0, B);
+}
+
+void oracle_basis_matrix_k(const oracle_problem *pb, uint32_t k, double *B)
+{
     int d = pb->d, n = oracle_num_points(pb), p = oracle_num_basis(pb);
     int *nu = (int *)malloc(sizeof(int) * (size_t)p * (d + 1));
     double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
     oracle_index_set(d + 1, pb->eta, pb->q, nu, p);
-    oracle_points(pb, pts);
+    oracle_points_k(pb, k, pts);
     basis_matrix(pb, nu, p, pts, n, B);
     free(nu); free(pts);
 }
@@ -610,7 +624,14 @@ int oracle_solve(const oracle_problem *pb, int k_start,
 
     int status = ORACLE_OK;
     int have_alpha = alpha_start != NULL;
+    int redraw = pb->redraw && pb->grid == ORACLE_GRID_RANDOM;
     for (int k = k_start; k < k_end; ++k) {
+        /* the points of this iteration (Algorithm 1: new uniform points at
+         * every iteration) and their basis matrix */
+        if (redraw) {
+            oracle_points_k(pb, (uint32_t)k, pts);
+            basis_matrix(pb, nu, p, pts, n, B);
+        }
         /* c_i for every point (eq. chat) */
         for (int i = 0; i < n; ++i)
             correction_at_point(pb, nu, p, have_alpha ? alpha : NULL,

@@ -93,6 +93,8 @@ typedef struct {
     int M, N, K_it;
     double omega;                   /* penalisation weight (0 = European)   */
     uint64_t seed;
+    int redraw;                     /* random grid: new points every        */
+                                    /* Picard iteration (Algorithm 1)       */
 } oracle_problem;
 
 /* --- randomness ------------------------------------------------------- */
@@ -112,6 +114,10 @@ int oracle_num_basis(const oracle_problem *pb);
 void oracle_domain(const oracle_problem *pb, double *lo, double *hi);
 /* points as n rows of (t, x_1..x_d); point i = a * n_spatial + b. */
 int oracle_points(const oracle_problem *pb, double *pts);
+/* the points used at Picard iteration k: with redraw on a random grid the
+ * spatial points are drawn afresh for every k (counter word 2 = k), else
+ * the fixed grid of oracle_points (which is iteration 0's). */
+int oracle_points_k(const oracle_problem *pb, uint32_t k, double *pts);
 /* Cholesky factor (row-major d x d, lower) of rho 11' + (1 - rho) I. */
 int oracle_cholesky(int d, double rho, double *L);
 /* Least squares argmin ||y - B alpha|| by Householder QR, B row-major n x p. */
@@ -157,6 +163,8 @@ int oracle_solve(const oracle_problem *pb, int k_start,
                  double *c_hist, double *var_hist, double *u_hist);
 /* B_{il} = B_l(t_i, x_i), row-major n x p (the least-squares design matrix). */
 void oracle_basis_matrix(const oracle_problem *pb, double *B);
+/* the basis matrix of the points of Picard iteration k */
+void oracle_basis_matrix_k(const oracle_problem *pb, uint32_t k, double *B);
 /* alpha = B^+ y for values y at the grid points (fit of a known function). */
 int oracle_fit(const oracle_problem *pb, const double *y, double *alpha);
 /* price u(t, log S) and dollar delta e^{-x_j} d_{x_j} u for nq queries. */

@@ -233,7 +233,10 @@ def exact_picard_const_vol(cfg, pts, K_it, n_leg=16, n_herm=24):
     put payoff, whose conditional expectation is closed form.  Tensor
     Gauss-Hermite over the correlated Gaussian increment and Gauss-Legendre
     in time make E[int f(u^k)] exact for the polynomial u^k.  Returns the
-    prices u^k(0, log S0) for k = 0..K_it."""
+    prices u^k(0, log S0) for k = 0..K_it.  pts is the (n, d+1) array of
+    points, or a function of the iteration k returning the points of that
+    iteration (points redrawn every iteration)."""
+    pts_of = pts if callable(pts) else (lambda k: pts)
     d = cfg["d"]
     T, r, K = cfg["T"], cfg["r"], cfg["K"]
     sig = np.asarray(cfg["vol_level"], float)
@@ -243,7 +246,6 @@ def exact_picard_const_vol(cfg, pts, K_it, n_leg=16, n_herm=24):
     lo = np.log(S0) - w * sig * math.sqrt(T)
     hi = np.log(S0) + w * sig * math.sqrt(T)
     nu = total_degree_set(d + 1, cfg["eta"])
-    B = monomial_design(pts, T, lo, hi, nu)
     C = np.full((d, d), cfg.get("rho", 0.0))
     np.fill_diagonal(C, 1.0)
     L = np.linalg.cholesky(C)
@@ -274,7 +276,9 @@ def exact_picard_const_vol(cfg, pts, K_it, n_leg=16, n_herm=24):
 
     alpha = np.zeros(len(nu))
     prices = [0.0]
-    for _ in range(K_it):
+    for k in range(K_it):
+        pts = pts_of(k)
+        B = monomial_design(pts, T, lo, hi, nu)
         y = np.empty(len(pts))
         for i, row in enumerate(pts):
             t0, x0 = row[0], row[1:]

@@ -109,3 +109,43 @@ def test_penalty_term_matches_exact_expectation_and_bracket():
     # American (CRR) one
     crr = refs.crr_american_put(100, 100, 0.05, 0.2, 1.0, steps=2000)
     assert exact_eur[-1] + 0.05 < got < crr + 0.1
+
+
+def test_redrawn_points_follow_the_exact_expectation_map():
+    # Algorithm 1 with new random points at every iteration: the projection
+    # of iteration k uses the points of iteration k.  With only 240 points
+    # for 20 basis functions the exact-expectation iterates themselves move
+    # by +-1 from one point set to the next; the Monte Carlo oracle tracks
+    # the exact map on the same point sets (tolerances: 4.5 x the standard
+    # deviation of the difference over 8 seeds).
+    cfg = problem(d=2, rho=0.3, vol_level=[0.2, 0.3], S0=[100.0, 100.0],
+                  payoff="put_geom", grid="random", redraw=1, n_t=6,
+                  n_x=40, eta=3, M=1000, N=1, K_it=3)
+    assert not np.array_equal(oracle.points(cfg, 0), oracle.points(cfg, 1))
+    exact = refs.exact_picard_const_vol(cfg, lambda k: oracle.points(cfg, k), 3)
+    fixed = refs.exact_picard_const_vol(cfg, oracle.points(cfg, 0), 3)
+    res = oracle.solve(cfg)
+    got = [_price(cfg, a)[0] for a in res["alpha"]]
+    for k, tol in zip([1, 2, 3], [0.35, 0.19, 0.06]):
+        assert abs(got[k] - exact[k]) < tol, (k, got[k], exact[k])
+    # the redrawn point sets matter: the fixed-grid map is far away
+    assert max(abs(a - b) for a, b in zip(exact[2:], fixed[2:])) > 5 * 0.19
+
+
+def test_redraw_keeps_an_exact_solution_fixed():
+    # the solution of the zero-variance problem lies in the span, so every
+    # redrawn projection returns the same coefficients: alpha^k = alpha^0
+    sig = np.array([0.2, 0.3])
+    cfg = problem(d=2, r=0.0, vol_level=list(sig), rho=0.3, payoff="quad",
+                  eta=3, grid="random", redraw=1, n_t=5, n_x=30, M=16, N=7,
+                  S0=[100.0, 100.0], K_it=3)
+    pts = oracle.points(cfg)
+    C = np.array([[1, 0.3], [0.3, 1]])
+    tau = 1.0 - pts[:, 0]
+    y = (pts[:, 1:] - 0.5 * sig ** 2 * tau[:, None]).sum(1) ** 2 + \
+        tau * float(sig @ C @ sig)
+    a0 = oracle.fit(cfg, y)
+    res = oracle.solve(cfg, 0, a0)
+    for k in range(1, 4):
+        np.testing.assert_allclose(res["alpha"][k], a0, rtol=0, atol=1e-8)
+    assert np.abs(res["c"]).max() < 1e-10

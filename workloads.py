@@ -34,6 +34,7 @@ def problem(**kw) -> dict:
         "T": 1.0,
         "S0": [100.0],
         "grid": "tensor",      # tensor | random
+        "redraw": 0,           # random grid: new points every iteration
         "n_t": 8,
         "n_x": 16,
         "width": 4.0,
