@@ -90,8 +90,9 @@ typedef enum {
     BSDE_GRID_TENSOR = 0, /* n_x equispaced nodes per asset (endpoints
                              included); spatial point b has base-n_x digits
                              b_j, asset 1 least significant               */
-    BSDE_GRID_RANDOM = 1  /* n_x points uniform in D, drawn once from the
-                             counter-based generator (substream 2)        */
+    BSDE_GRID_RANDOM = 1  /* n_x points uniform in D from the counter-based
+                             generator (substream 2): drawn once, or at
+                             every Picard iteration with redraw            */
 } bsde_grid_kind;
 
 typedef struct {
@@ -102,6 +103,13 @@ typedef struct {
     int eta;       /* maximal total degree of the polynomial basis          */
     double q;      /* hyperbolic index set parameter in (0, 1]; 1 = total
                       degree                                               */
+    int redraw;    /* 1: random grid only -- new spatial points at every
+                      Picard iteration k (Algorithm 1 draws new points each
+                      iteration; counter word 2 = k, iteration 0 = the
+                      fixed grid), the least-squares factorisation redone
+                      on the device for each; bsde_solve only (the batched
+                      entry points and the server return
+                      BSDE_EUNSUPPORTED).  0: one fixed grid.             */
 } bsde_grid;
 
 typedef enum {
@@ -142,7 +150,10 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
  * update, eq. alpha) on the given HIP stream (hipStream_t, NULL = the
  * default stream) and returns once they are complete.  Starting
  * coefficients are u^0 = 0 unless set with bsde_set_coefficients or
- * bsde_fit_values.  Errors: BSDE_EDEVICE. */
+ * bsde_fit_values.  With redraw, each iteration first draws its points
+ * and factorises their basis matrix on the device (waiting for the
+ * previous iteration).  Errors: BSDE_EDEVICE, BSDE_ERANK (redrawn points
+ * with a rank-deficient basis matrix). */
 bsde_status bsde_solve(bsde_problem h, void *hip_stream);
 
 /* Price u(t, log S) and dollar deltas Delta_j = e^{-x_j} d_{x_j} u (the
@@ -162,7 +173,8 @@ bsde_status bsde_query_price_delta(bsde_problem h, int nq, const double *t,
  * derivative channels (u, d_t u, grad u, upper-triangular hessian). */
 bsde_status bsde_problem_sizes(bsde_problem h, int *n, int *p, int *C);
 
-/* The n * (d+1) grid points (t_i, x_i), row-major. */
+/* The n * (d+1) grid points (t_i, x_i), row-major: with redraw, the
+ * points of the last iteration run (iteration 0's before any solve). */
 bsde_status bsde_get_points(bsde_problem h, double *pts);
 
 /* Coefficients alpha^k (Chebyshev basis, p doubles) after k iterations,
@@ -178,8 +190,8 @@ bsde_status bsde_set_coefficients(bsde_problem h, const double *alpha,
                                   int k_done);
 
 /* Sets alpha = argmin ||y - B alpha|| for values y (n doubles) at the grid
- * points (least-squares fit of a known function) and declares k_done
- * iterations done. */
+ * points -- those bsde_get_points returns -- (least-squares fit of a known
+ * function) and declares k_done iterations done. */
 bsde_status bsde_fit_values(bsde_problem h, const double *y, int k_done);
 
 /* Per-point correction c^k_i (eq. chat) and the sample variance of the
@@ -284,7 +296,10 @@ typedef struct {
  * device current at the call.  Errors: BSDE_EINVAL, BSDE_EDEVICE. */
 bsde_status bsde_server_create(size_t hbm_budget_bytes, int max_inflight,
                                int setup_threads, bsde_server *out);
-/* Queues a request (arrays are copied); ticket receives its id. */
+/* Queues a request (arrays are copied); ticket receives its id.  Errors:
+ * BSDE_EINVAL, BSDE_EUNSUPPORTED (a grid with redraw: such problems need
+ * a host-side factorisation between iterations and run through bsde_solve
+ * only); errors of the problem itself arrive through bsde_server_poll. */
 bsde_status bsde_server_submit(bsde_server s, const bsde_request *req,
                                unsigned long long *ticket);
 /* Result of a ticket; with wait = 0 returns BSDE_EBUSY while it runs.  A

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <tuple>
 #include <cstdio>
@@ -300,6 +301,41 @@ void setup_stream_put(hipStream_t s)
 }
 } // namespace
 
+// The points of Picard iteration k, time-major (point i = a n_spatial + b):
+// time nodes a T / (n_t - 1); tensor grid digits equispaced in [-1, 1]; or
+// Philox-uniform spatial points from the counter (b, 0, k', 2 << 24 |
+// block) with k' = k when the points are redrawn every iteration, else 0.
+static void make_points(const bsde_problem_s *h, int k, std::vector<double> &pts)
+{
+    const int d = h->d, dp = d + 1;
+    const long ns = h->n_spatial;
+    const uint64_t seed = h->base.seed;
+    const uint32_t kdraw = (h->redraw && h->grid_kind == BSDE_GRID_RANDOM) ? (uint32_t)k : 0u;
+    pts.resize((size_t)h->n * dp);
+    for (int a = 0; a < h->n_t; ++a) {
+        double t = a * h->base.T / (h->n_t - 1);
+        for (long s = 0; s < ns; ++s) {
+            double *row = &pts[(size_t)(a * ns + s) * dp];
+            row[0] = t;
+            long rest = s;
+            for (int j = 0; j < d; ++j) {
+                double z;
+                if (h->grid_kind == BSDE_GRID_TENSOR) {
+                    long digit = rest % h->n_x;
+                    rest /= h->n_x;
+                    z = h->n_x > 1 ? -1.0 + 2.0 * digit / (h->n_x - 1) : 0.0;
+                } else {
+                    u32x4 w = philox10((uint32_t)s, 0, kdraw, (2u << 24) | (uint32_t)(j / 4),
+                                       (uint32_t)seed, (uint32_t)(seed >> 32));
+                    uint32_t word = j % 4 == 0 ? w.x : j % 4 == 1 ? w.y : j % 4 == 2 ? w.z : w.w;
+                    z = 2.0 * (((double)word + 0.5) * 0x1p-32) - 1.0;
+                }
+                row[1 + j] = h->lo[j] + 0.5 * (z + 1.0) * (h->hi[j] - h->lo[j]);
+            }
+        }
+    }
+}
+
 // Shapes of the set-up: the leading dimension of the n x pap point matrices
 // and the row chunks of the Gram kernel (about 2048 waves over the
 // 64 x 64 block pairs, at least 256 rows each)
@@ -543,6 +579,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EINVAL, "bump centre must be > 0");
     if (grid->kind != BSDE_GRID_TENSOR && grid->kind != BSDE_GRID_RANDOM)
         return fail(BSDE_EINVAL, "bad grid kind");
+    if (grid->redraw != 0 && (grid->redraw != 1 || grid->kind != BSDE_GRID_RANDOM))
+        return fail(BSDE_EINVAL, "redraw needs a random grid");
     if (grid->n_t < 2 || grid->n_x < 1 || !(grid->width > 0.0) ||
         grid->eta < 1 || !(grid->q > 0.0 && grid->q <= 1.0))
         return fail(BSDE_EINVAL, "bad grid (n_t >= 2, n_x >= 1, width > 0, "
@@ -634,32 +672,15 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     }
     h->n_spatial = (int)ns;
     h->n = (int)(ns * grid->n_t);
-    h->pts.resize((size_t)h->n * dp);
-    for (int a = 0; a < grid->n_t; ++a) {
-        double t = a * payoff->T / (grid->n_t - 1);
-        for (long s = 0; s < ns; ++s) {
-            double *row = &h->pts[(size_t)(a * ns + s) * dp];
-            row[0] = t;
-            long rest = s;
-            for (int j = 0; j < d; ++j) {
-                double z;
-                if (grid->kind == BSDE_GRID_TENSOR) {
-                    long digit = rest % grid->n_x;
-                    rest /= grid->n_x;
-                    z = grid->n_x > 1 ? -1.0 + 2.0 * digit / (grid->n_x - 1) : 0.0;
-                } else {
-                    u32x4 w = philox10((uint32_t)s, 0, 0, (2u << 24) | (uint32_t)(j / 4),
-                                       (uint32_t)seed, (uint32_t)(seed >> 32));
-                    uint32_t word = j % 4 == 0 ? w.x : j % 4 == 1 ? w.y : j % 4 == 2 ? w.z : w.w;
-                    z = 2.0 * (((double)word + 0.5) * 0x1p-32) - 1.0;
-                }
-                row[1 + j] = h->lo[j] + 0.5 * (z + 1.0) * (h->hi[j] - h->lo[j]);
-            }
-        }
-    }
+    h->grid_kind = grid->kind;
+    h->n_t = grid->n_t;
+    h->n_x = grid->n_x;
+    h->redraw = grid->redraw;
+    h->pts_k = 0;
+    make_points(h, 0, h->pts);
 
     // basis matrix over the active multi-indices and its pseudo-inverse
-    std::vector<int> act;
+    std::vector<int> &act = h->act;
     for (int l = 0; l < h->p; ++l)
         if (h->active[l]) act.push_back(l);
     const int pa = (int)act.size();
@@ -806,18 +827,37 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     if (st != BSDE_OK) return st;
     const bool fp32 = h->precision == BSDE_FP32_PATHS;
     const int iters = h->K_it - h->k_done;
-    // events: start, end, and 4 per iteration (before path, after path,
-    // after reduction, after projection; the next iteration's first event
-    // closes the channel update)
-    std::vector<hipEvent_t> ev(2 + 4 * (size_t)iters + 1);
+    // events: start, end, and 5 per iteration (before path, after path,
+    // after reduction, after projection, after the channel update)
+    std::vector<hipEvent_t> ev(2 + 5 * (size_t)iters);
     for (auto &x : ev) HIP_TRY(event_get(&x));
+    struct Release {
+        std::vector<hipEvent_t> &v;
+        ~Release() { for (auto &x : v) event_put(x); }
+    } release_events{ev};
+    double t_setup = 0.0;
     HIP_TRY(hipEventRecord(ev[0], s));
     // channel table of the starting coefficients
     HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
                             h->d_D, h->d_g64, h->d_g32));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
-        hipEvent_t *e = &ev[2 + 4 * (size_t)it];
+        hipEvent_t *e = &ev[2 + 5 * (size_t)it];
+        if (h->redraw && h->pts_k != k) {
+            // Algorithm 1: new points for this iteration, and the
+            // pseudo-inverse of their basis matrix (after the previous
+            // iteration is done with the old ones)
+            HIP_TRY(hipStreamSynchronize(s));
+            const auto t0 = std::chrono::steady_clock::now();
+            make_points(h, k, h->pts);
+            HIP_TRY(hipMemcpy(h->d_pts, h->pts.data(), sizeof(double) * h->pts.size(),
+                              hipMemcpyHostToDevice));
+            const bsde_status pst = device_pseudo_inverse(h, h->act);
+            if (pst != BSDE_OK) return pst;
+            h->pts_k = k;
+            t_setup += std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t0).count();
+        }
         PathParams prm = h->base;
         prm.k = (uint32_t)k;
         prm.groups = groups;
@@ -832,22 +872,22 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
                               h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
-                              h->d_g32, e + 2));
+                              h->d_g32, e + 2)); // records e[2], e[3], e[4]
     }
     HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipEventSynchronize(ev[1]));
     double t_path = 0, t_fin = 0, t_proj = 0, t_chan = 0;
     for (int it = 0; it < iters; ++it) {
-        hipEvent_t *e = &ev[2 + 4 * (size_t)it];
+        hipEvent_t *e = &ev[2 + 5 * (size_t)it];
         float ms;
         hipEventElapsedTime(&ms, e[0], e[1]); t_path += ms;
         hipEventElapsedTime(&ms, e[1], e[2]); t_fin += ms;
         hipEventElapsedTime(&ms, e[2], e[3]); t_proj += ms;
-        hipEventElapsedTime(&ms, e[3], it + 1 < iters ? e[4] : ev[1]); t_chan += ms;
+        hipEventElapsedTime(&ms, e[3], e[4]); t_chan += ms;
     }
     float tot;
     hipEventElapsedTime(&tot, ev[0], ev[1]);
-    for (auto &x : ev) event_put(x);
+    (void)t_setup; // included in the total (host-side set-up between launches)
     HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
                       sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
     if (iters > 0) {
@@ -1133,6 +1173,8 @@ bsde_status bsde_solve_batch(bsde_problem *problems, int count,
         if (!problems[q]) return fail(BSDE_EINVAL, "null handle in batch");
         for (int r = 0; r < q; ++r)
             if (problems[r] == problems[q]) return fail(BSDE_EINVAL, "duplicate handle in batch");
+        if (problems[q]->redraw)
+            return fail(BSDE_EUNSUPPORTED, "points redrawn every iteration: use bsde_solve");
     }
     hipStream_t s = (hipStream_t)hip_stream;
     hipStream_t own = nullptr;

@@ -17,6 +17,10 @@ struct bsde_problem_s {
     bsde::PathParams base{};
     // sizes
     int n = 0, n_spatial = 0, p = 0, C = 0;
+    // grid: kind, nodes, redraw flag and the iteration whose points are on
+    // the device (with redraw)
+    int grid_kind = 0, n_t = 0, n_x = 0, redraw = 0, pts_k = 0;
+    std::vector<int> act;        // active multi-indices (hyperbolic set)
     std::vector<int8_t> nu;      // p x (d+1), kernel order
     std::vector<char> active;    // in the hyperbolic set
     std::vector<double> pts;     // n x (d+1)

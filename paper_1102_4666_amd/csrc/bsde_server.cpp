@@ -255,6 +255,8 @@ bsde_status bsde_server_submit(bsde_server S, const bsde_request *req,
         return fail(BSDE_EINVAL, "null argument");
     const int d = req->d;
     if (d < 1 || d > kMaxD) return fail(BSDE_EINVAL, "d must be in [1, 10]");
+    if (req->grid.redraw)
+        return fail(BSDE_EUNSUPPORTED, "points redrawn every iteration are not served");
     auto *q = new (std::nothrow) Request();
     if (!q) return fail(BSDE_ENOMEM, "host allocation");
     q->d = d;

@@ -51,6 +51,17 @@ CASES = {
     "d10_eta3": problem(d=10, vol_level=0.2, rho=0.3, payoff="call_geom",
                         S0=100.0, grid="random", n_t=4, n_x=300, eta=3,
                         M=16, N=3, K_it=2),
+    # random points redrawn at every Picard iteration (Algorithm 1), the
+    # least-squares factorisation redone on the device each time
+    "d2_redraw": problem(d=2, vol_kind="bump", vol_level=[0.2, 0.3],
+                         bump_a=0.25, rho=0.3, S0=[100.0, 100.0],
+                         grid="random", redraw=1, n_t=4, n_x=40, eta=3,
+                         M=260, N=6, K_it=3, omega=1.0),
+    "d5_redraw": problem(d=5, vol_kind="bump",
+                         vol_level=[0.15, 0.2, 0.25, 0.3, 0.35], bump_a=0.25,
+                         rho=0.2, payoff="put_geom", S0=100.0, grid="random",
+                         redraw=1, n_t=3, n_x=60, eta=2, M=100, N=4, K_it=3,
+                         omega=1.0),
 }
 FP32_ONLY = {"d10_eta2", "d10_eta3"}
 
@@ -67,7 +78,8 @@ def _oracle(cache, name):
         pr, de = oracle.price_delta(cfg, res["alpha"][-1], [0.0], [cfg["S0"]])
         res["price"] = pr[0]
         res["delta"] = de[0]
-        res["pts"] = oracle.points(cfg)
+        # the points of the last iteration (the grid when they are fixed)
+        res["pts"] = oracle.points(cfg, cfg["K_it"] - 1 if cfg.get("redraw") else 0)
         cache[name] = res
     return cache[name]
 
@@ -210,3 +222,27 @@ def test_rank_deficient_grids_are_rejected():
     with pytest.raises(BsdeError) as e:
         Problem(problem(d=2, n_t=2, n_x=2, eta=3))
     assert e.value.status == 3, str(e.value)
+
+
+def test_redraw_resumes_and_is_solve_only():
+    from paper_1102_4666_amd import BsdeError, Problem, Server, solve_batch
+    cfg = dict(CASES["d2_redraw"], precision="fp64", K_it=4)
+    a = run_gpu(cfg)
+    with Problem(cfg) as P:
+        np.testing.assert_allclose(P.points(), oracle.points(cfg, 0), rtol=1e-15)
+        P.set_coefficients(a["alpha"][2], 2)
+        P.solve()
+        np.testing.assert_array_equal(P.coefficients(4), a["alpha"][4])
+        np.testing.assert_array_equal(P.corrections(3)[0], a["c"][3])
+        np.testing.assert_allclose(P.points(), oracle.points(cfg, 3), rtol=1e-15)
+    with Problem(cfg) as P:
+        with pytest.raises(BsdeError) as e:
+            solve_batch([P])
+        assert e.value.status == 6
+    with Server(1 << 30) as S:
+        with pytest.raises(BsdeError) as e:
+            S.submit(cfg)
+        assert e.value.status == 6
+    with pytest.raises(BsdeError) as e:   # redraw needs a random grid
+        Problem(dict(cfg, grid="tensor", n_x=6))
+    assert e.value.status == 1
