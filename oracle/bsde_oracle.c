@@ -326,10 +326,16 @@ double oracle_payoff(const oracle_problem *pb, const double *x)
 
 double oracle_vol(const oracle_problem *pb, int j, double t, double x_j)
 {
-    (void)t; /* both volatility kinds are time-homogeneous */
     if (pb->vol_kind == ORACLE_VOL_BUMP) {
         double dx = x_j - log(pb->bump_c);
         return pb->vol_level[j] * (1.0 + pb->bump_a * exp(-dx * dx));
+    }
+    if (pb->vol_kind == ORACLE_VOL_DUPIRE) {
+        /* eq. vol_locale with the price S = e^{x_j} and s the spot S0_j */
+        double S = exp(x_j);
+        double dev = S * exp(pb->r * t) - pb->S0[j];
+        return 0.6 * (1.2 - exp(-0.1 * t) * exp(-0.001 * dev * dev)) *
+               exp(-0.05 * sqrt(t));
     }
     return pb->vol_level[j];
 }

@@ -56,7 +56,11 @@ extern "C" {
 
 #define ORACLE_DMAX 16
 
-enum { ORACLE_VOL_CONST = 0, ORACLE_VOL_BUMP = 1 };
+/* volatility kinds: constant l_j; bump l_j (1 + a e^{-(x_j - log c)^2});
+ * Dupire-type of eq. vol_locale, sigma(t, S) = 0.6 (1.2 - e^{-0.1 t}
+ * e^{-0.001 (S e^{r t} - s)^2}) e^{-0.05 sqrt t} with s = S0_j (the smile
+ * bottom at the forward); for it, l_j only sets the domain width. */
+enum { ORACLE_VOL_CONST = 0, ORACLE_VOL_BUMP = 1, ORACLE_VOL_DUPIRE = 2 };
 enum {
     ORACLE_PUT_ARITH = 0,  /* (K - mean_j e^{x_j})_+          eq. put_payoff  */
     ORACLE_CALL_ARITH = 1, /* (mean_j e^{x_j} - K)_+          eq. call_payoff */

@@ -43,6 +43,7 @@ CASES = {
     "config3_w1": (workloads.config3, {"omega": 1.0}),
     "config4_w100": (workloads.config4, {"omega": 100.0}),
     "config4_w1": (workloads.config4, {"omega": 1.0}),
+    "config4_redraw_w1": (workloads.config4, {"omega": 1.0, "redraw": 1}),
 }
 
 

@@ -80,14 +80,15 @@ def crr_american_put(S, K, r, sigma, T, steps=4000):
 
 # --------------------------------------------------------------------------
 def penalised_pde_1d(S0, K, r, vol, T, omega, payoff="put", nx=1601,
-                     nt=2000, half_width=3.0, source=None):
+                     nt=2000, half_width=3.0, source=None, vol_t=None):
     """Fully implicit FD for d_t u + 1/2 s(x)^2 u_xx + (r - s^2/2) u_x - r u
     + omega (Phi - u)_+ + source(t, x) = 0, u(T) = Phi, on x = log S in
     [log S0 - half_width, log S0 + half_width] with Dirichlet data from the
     payoff (put: K e^{-r(T-t)} - S at the left, 0 at the right).  The
     penalty is solved by policy iteration at every time step.  vol(x) is a
-    callable of the log-price.  Returns (x grid, list of u at t_n,
-    t grid)."""
+    callable of the log-price; vol_t(t, x), if given, a time-dependent one
+    (evaluated at the time of each implicit step).  Returns (x grid, list
+    of u at t_n, t grid)."""
     x = np.linspace(math.log(S0) - half_width, math.log(S0) + half_width, nx)
     dx = x[1] - x[0]
     dt = T / nt
@@ -106,6 +107,11 @@ def penalised_pde_1d(S0, K, r, vol, T, omega, payoff="put", nx=1601,
     us = [u.copy()]
     for n in range(nt - 1, -1, -1):
         t = n * dt
+        if vol_t is not None:
+            s2 = vol_t(t, x) ** 2
+            a = 0.5 * s2 / dx ** 2
+            b = (r - 0.5 * s2) / (2 * dx)
+            lower, diag, upper = a - b, -2 * a - r, a + b
         rhs = u.copy()
         if source is not None:
             rhs = rhs + dt * source(t, x)

@@ -40,6 +40,8 @@ def _golden(name):
     ("config3_w1", "fp64"), ("config3_w1", "fp32"),
     ("config4_w100", "fp64"), ("config4_w100", "fp32"),
     ("config4_w1", "fp64"), ("config4_w1", "fp32"),
+    # points redrawn at every iteration (Algorithm 1)
+    ("config4_redraw_w1", "fp64"), ("config4_redraw_w1", "fp32"),
 ])
 def test_full_size_against_stored_oracle(name, prec):
     g = _golden(name)

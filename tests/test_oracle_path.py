@@ -114,3 +114,46 @@ def test_zero_variance_when_uk_is_the_solution(d, rho):
     assert v.max() < 1e-20
     for m in range(4):
         assert abs(oracle.path_term(cfg, alpha, pts[7, 0], pts[7, 1:], 7, m, 0)) < 1e-10
+
+
+def test_dupire_volatility_has_the_stated_smile():
+    # eq. vol_locale: at t = 0 and the spot s the volatility is
+    # 0.6 (1.2 - 1) = 0.12; at every t the bottom of the smile sits at the
+    # price S with S e^{rt} = s (the forward of the text), with value
+    # 0.6 (1.2 - e^{-0.1 t}) e^{-0.05 sqrt t}; far from it the smile
+    # flattens at 0.72 e^{-0.05 sqrt t}
+    cfg = problem(d=1, vol_kind="dupire", r=0.05, S0=100.0)
+    assert abs(oracle.vol(cfg, 0, 0.0, math.log(100.0)) - 0.12) < 1e-15
+    for t in (0.0, 0.3, 1.0, 2.5):
+        S = np.linspace(40.0, 160.0, 24001)
+        v = np.array([oracle.vol(cfg, 0, t, math.log(s)) for s in S])
+        assert abs(S[np.argmin(v)] - 100.0 * math.exp(-0.05 * t)) < 0.01
+        damp = math.exp(-0.05 * math.sqrt(t))
+        assert abs(v.min() - 0.6 * (1.2 - math.exp(-0.1 * t)) * damp) < 1e-8
+        far = oracle.vol(cfg, 0, t, math.log(1000.0))
+        assert abs(far - 0.72 * damp) < 1e-12
+
+
+def test_time_dependent_local_vol_euler_matches_pde_price():
+    # the Euler scheme evaluates sigma at the time of each step: the
+    # Dupire-type European put against an implicit finite-difference
+    # solution with the volatility at each step's time
+    cfg = problem(d=1, vol_kind="dupire", vol_level=0.3, r=0.05, N=50,
+                  M=60000, n_t=2, n_x=1, eta=1)
+    c, v = oracle.corrections(cfg, None, 0, 0, 1)   # point (t=0, x=log S0)
+    mc = math.exp(-0.05) * c[0]
+    se = math.exp(-0.05) * math.sqrt(v[0] / cfg["M"])
+
+    def vol_t(t, x):
+        dev = np.exp(x) * math.exp(0.05 * t) - 100.0
+        return 0.6 * (1.2 - math.exp(-0.1 * t) * np.exp(-0.001 * dev ** 2)) * \
+            math.exp(-0.05 * math.sqrt(t))
+    x, us, _ = refs.penalised_pde_1d(100.0, 100.0, 0.05, lambda x: x * 0, 1.0,
+                                     0.0, nx=1201, nt=1000, vol_t=vol_t)
+    fd = refs.interp_value_delta(x, us[0], 100.0)[0]
+    assert abs(mc - fd) < 4.5 * se + 0.01
+    # freezing the volatility at t = 0 would be a different model
+    x0, us0, _ = refs.penalised_pde_1d(100.0, 100.0, 0.05,
+                                       lambda x: vol_t(0.0, x), 1.0, 0.0,
+                                       nx=1201, nt=1000)
+    assert abs(refs.interp_value_delta(x0, us0[0], 100.0)[0] - fd) > 5 * (4.5 * se + 0.01)

@@ -22,7 +22,7 @@ def problem(**kw) -> dict:
     """A d=1 Black-Scholes European put with small sizes, overridden by kw."""
     cfg = {
         "d": 1,
-        "vol_kind": "const",   # "const" | "bump"
+        "vol_kind": "const",   # "const" | "bump" | "dupire"
         "vol_level": [0.2],
         "bump_a": 0.0,
         "bump_c": 100.0,
@@ -91,15 +91,16 @@ def config3(omega: float = 100.0, precision: str = "fp32") -> dict:
                    eta=5, M=2000, N=50, K_it=8, precision=precision, seed=0)
 
 
-def config4(omega: float = 100.0, precision: str = "fp32") -> dict:
+def config4(omega: float = 100.0, precision: str = "fp32",
+            redraw: int = 0) -> dict:
     """d=5 American geometric-basket put, per-asset levels U[0.15, 0.35]
     (seeded), rho=0.2, 4096 random spatial points x 10 times, M=1000,
-    N=50, 10 iterations."""
+    N=50, 10 iterations (redraw=1: new spatial points every iteration)."""
     return problem(d=5, vol_kind="bump", vol_level=vol_levels(5, seed=0),
                    bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, K=100.0,
                    S0=100.0, T=1.0, payoff="put_geom", omega=omega,
-                   grid="random", n_t=10, n_x=4096, eta=3, M=1000, N=50,
-                   K_it=10, precision=precision, seed=0)
+                   grid="random", redraw=redraw, n_t=10, n_x=4096, eta=3,
+                   M=1000, N=50, K_it=10, precision=precision, seed=0)
 
 
 def serving_request(idx: int, rng: np.random.Generator,
