@@ -39,7 +39,9 @@ typedef enum {
     BSDE_EDEVICE = 4,  /* a HIP call failed (no GPU, launch failure, ...)    */
     BSDE_ESTATE = 5,   /* call not valid in the current state (e.g. query
                           before solve)                                    */
-    BSDE_EUNSUPPORTED = 6, /* no kernel is built for this (d, eta)           */
+    BSDE_EUNSUPPORTED = 6, /* no kernel is built for this (d, eta, precision,
+                              volatility kind), or a feature the entry point
+                              does not serve                                */
     BSDE_EBUSY = 7     /* request not finished yet (non-blocking poll)      */
 } bsde_status;
 
@@ -48,7 +50,12 @@ typedef enum {
  * correlation matrix). */
 typedef enum {
     BSDE_VOL_CONST = 0, /* sigma_j = level_j                               */
-    BSDE_VOL_BUMP = 1   /* sigma_j = level_j (1 + bump_a e^{-(log(S/bump_c))^2}) */
+    BSDE_VOL_BUMP = 1,  /* sigma_j = level_j (1 + bump_a e^{-(log(S/bump_c))^2}) */
+    BSDE_VOL_DUPIRE = 2 /* eq. vol_locale: sigma(t, S) = 0.6 (1.2 -
+                           e^{-0.1 t} e^{-0.001 (S e^{r t} - s)^2})
+                           e^{-0.05 sqrt t}, s = S0_j (smile bottom at the
+                           forward); level_j then only sets the width of D.
+                           Kernels: d=1 eta=4, d=2 eta=3, d=5 eta=2,3.      */
 } bsde_vol_kind;
 
 typedef struct {

@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsde.so")
 
-VOL_KINDS = {"const": 0, "bump": 1}
+VOL_KINDS = {"const": 0, "bump": 1, "dupire": 2}
 PAYOFFS = {"put": 0, "call": 1, "put_geom": 2, "call_geom": 3, "fwd": 4,
            "quad": 5}
 GRIDS = {"tensor": 0, "random": 1}

@@ -169,7 +169,7 @@ __host__ __device__ constexpr int hess_k(int d, int idx)
 // ---------------------------------------------------------------------------
 // Per-launch parameters of the path kernel (passed by value).
 // ---------------------------------------------------------------------------
-enum VolKind { kVolConst = 0, kVolBump = 1 };
+enum VolKind { kVolConst = 0, kVolBump = 1, kVolDupire = 2 };
 enum PayoffKind {
     kPutArith = 0,
     kCallArith = 1,
@@ -191,6 +191,7 @@ struct AssetConsts {
     Real scale[kMaxD];   // 2 / (hi - lo)
     Real Ldiag[kMaxD];   // Cholesky diagonal L_jj
     Real Lcol[kMaxD];    // L_{j+1, j}: column j below the diagonal (constant)
+    Real spot[kMaxD];    // S0_j: the smile centre of the Dupire-type volatility
 };
 
 struct PathParams {
@@ -209,6 +210,7 @@ struct PathParams {
     double rho;
     double mid[kMaxD];         // domain centre
     double scale[kMaxD];       // 2 / (hi - lo)
+    double spot[kMaxD];        // S0_j
     AssetConsts<float> cf;     // the per-asset constants in FP32
     AssetConsts<double> cd;    // and in FP64
 };
@@ -227,23 +229,24 @@ __host__ __device__ __forceinline__ const AssetConsts<double> &asset_consts<doub
 }
 
 // fills cf and cd from the FP64 parameters (level, div, bump_a, mid,
-// scale, L and r must be set; d assets)
+// scale, L, spot and r must be set; d assets)
 __host__ inline void fill_asset_consts(PathParams &p, int d)
 {
     for (int j = 0; j < kMaxD; ++j) {
         const bool on = j < d;
-        const double v[7] = {on ? p.level[j] : 0.0,
+        const double v[8] = {on ? p.level[j] : 0.0,
                              on ? p.level[j] * p.bump_a : 0.0,
                              on ? p.r - p.div[j] : 0.0,
                              on ? p.mid[j] : 0.0,
                              on ? p.scale[j] : 0.0,
                              on ? p.L[j * kMaxD + j] : 0.0,
-                             j + 1 < d ? p.L[(j + 1) * kMaxD + j] : 0.0};
-        double *dd[7] = {p.cd.level, p.cd.level_a, p.cd.drift, p.cd.mid,
-                         p.cd.scale, p.cd.Ldiag, p.cd.Lcol};
-        float *ff[7] = {p.cf.level, p.cf.level_a, p.cf.drift, p.cf.mid,
-                        p.cf.scale, p.cf.Ldiag, p.cf.Lcol};
-        for (int c = 0; c < 7; ++c) {
+                             j + 1 < d ? p.L[(j + 1) * kMaxD + j] : 0.0,
+                             on ? p.spot[j] : 0.0};
+        double *dd[8] = {p.cd.level, p.cd.level_a, p.cd.drift, p.cd.mid,
+                         p.cd.scale, p.cd.Ldiag, p.cd.Lcol, p.cd.spot};
+        float *ff[8] = {p.cf.level, p.cf.level_a, p.cf.drift, p.cf.mid,
+                        p.cf.scale, p.cf.Ldiag, p.cf.Lcol, p.cf.spot};
+        for (int c = 0; c < 8; ++c) {
             dd[c][j] = v[c];
             ff[c][j] = (float)v[c];
         }

@@ -39,10 +39,11 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          hipEvent_t *ev);
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
                            const double *Dmat, double *g64, float *g32);
-hipError_t launch_batch(int d, int eta, bool fp32, bool bump, int blocks,
+hipError_t launch_batch(int d, int eta, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter);
-int batch_occupancy(int d, int eta, bool fp32, bool bump);
+int batch_occupancy(int d, int eta, bool fp32, int vol);
+bool variant_exists(int d, int eta, bool fp32, int vol);
 hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
                                hipStream_t s, const BatchUpdateDesc *d);
 hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
@@ -573,7 +574,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EINVAL, "penalty must be >= 0 and r finite");
     if (!(payoff->T > 0.0) || payoff->kind < 0 || payoff->kind > 5)
         return fail(BSDE_EINVAL, "bad payoff");
-    if (sigma->kind != BSDE_VOL_CONST && sigma->kind != BSDE_VOL_BUMP)
+    if (sigma->kind != BSDE_VOL_CONST && sigma->kind != BSDE_VOL_BUMP &&
+        sigma->kind != BSDE_VOL_DUPIRE)
         return fail(BSDE_EINVAL, "bad volatility kind");
     if (sigma->kind == BSDE_VOL_BUMP && !(sigma->bump_c > 0.0))
         return fail(BSDE_EINVAL, "bump centre must be > 0");
@@ -594,8 +596,13 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EUNSUPPORTED, "no kernel instantiated for d=" +
                                            std::to_string(d) + ", eta=" +
                                            std::to_string(grid->eta));
-    if (d == 10 && precision != BSDE_FP32_PATHS)
-        return fail(BSDE_EUNSUPPORTED, "d = 10 is built for FP32 paths only");
+    if (!variant_exists(d, grid->eta, precision == BSDE_FP32_PATHS, sigma->kind))
+        return fail(BSDE_EUNSUPPORTED,
+                    "no kernel instantiated for d=" + std::to_string(d) + ", eta=" +
+                        std::to_string(grid->eta) + " with this precision and "
+                        "volatility kind (d = 10: FP32 paths only; the "
+                        "Dupire-type volatility: d=1 eta=4, d=2 eta=3, d=5 "
+                        "eta=2,3)");
     double Lc[kMaxD * kMaxD];
     if (!cholesky(d, sigma->rho, Lc))
         return fail(BSDE_EINVAL, "correlation matrix not positive definite");
@@ -628,6 +635,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     h->hi.resize(d);
     for (int j = 0; j < d; ++j) {
         b.level[j] = sigma->level[j];
+        b.spot[j] = payoff->S0[j];
         b.div[j] = sigma->dividend ? sigma->dividend[j] : 0.0;
         double half = grid->width * sigma->level[j] * std::sqrt(payoff->T);
         h->lo[j] = std::log(payoff->S0[j]) - half;
@@ -915,10 +923,11 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
 namespace {
 struct Sig {
     int d, eta;
-    bool fp32, bump;
+    bool fp32;
+    int vol;
     bool operator<(const Sig &o) const
     {
-        return std::tie(d, eta, fp32, bump) < std::tie(o.d, o.eta, o.fp32, o.bump);
+        return std::tie(d, eta, fp32, vol) < std::tie(o.d, o.eta, o.fp32, o.vol);
     }
 };
 
@@ -977,7 +986,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     for (int q = 0; q < count; ++q) {
         bsde_problem h = probs[q];
         sigs[{h->d, h->eta, h->precision == BSDE_FP32_PATHS,
-              h->base.vol_kind == kVolBump}].push_back(q);
+              h->base.vol_kind}].push_back(q);
     }
     // host-side descriptor tables, laid out in one byte buffer
     std::vector<char> blob;
@@ -1063,10 +1072,10 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         for (int step = 0; step < S; ++step) {
             for (const PathLaunch &pl : plan[step].paths) {
                 const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta,
-                                                            pl.sig.fp32, pl.sig.bump));
+                                                            pl.sig.fp32, pl.sig.vol));
                 const long long cap = (long long)occ * num_cus();
                 const int blocks = (int)std::max(1LL, std::min(pl.tiles, cap));
-                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.fp32, pl.sig.bump, blocks, s,
+                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.fp32, pl.sig.vol, blocks, s,
                                  (const BatchTileDesc *)(dblob + pl.desc_off), pl.nprob,
                                  (const long long *)(dblob + pl.begin_off),
                                  counters + pl.counter);

@@ -1,134 +1,10 @@
-// bsde_inst_d1.hip -- path kernels for d = 1 (eta in {2, 3, 4, 5, 6, 8}).
+// bsde_inst_d1.hip -- path kernels for d = 1: eta in {2, 3, 4, 5, 6, 8},
+// FP32 and FP64 paths; the Dupire-type volatility at eta = 4.
 #include "bsde_path.h"
 
 namespace bsde {
-
-hipError_t launch_path_d1(int eta, bool fp32, int blocks, hipStream_t s,
-                           const PathParams &prm, const double *pts,
-                           const void *gamma, double *partial)
-{
-    BSDE_PATH_CASE(1, 2)
-    BSDE_PATH_CASE(1, 3)
-    BSDE_PATH_CASE(1, 4)
-    BSDE_PATH_CASE(1, 5)
-    BSDE_PATH_CASE(1, 6)
-    BSDE_PATH_CASE(1, 8)
-    return hipErrorInvalidValue;
-}
-
-// multi-indices of the kernels' basis, in the kernels' order
-int index_table_d1(int eta, int8_t *nu, int cap)
-{
-    if (eta == 2) {
-        constexpr auto &t = Basis<2, 2>::tab;
-        constexpr int P = Basis<2, 2>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 3) {
-        constexpr auto &t = Basis<2, 3>::tab;
-        constexpr int P = Basis<2, 3>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 4) {
-        constexpr auto &t = Basis<2, 4>::tab;
-        constexpr int P = Basis<2, 4>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 5) {
-        constexpr auto &t = Basis<2, 5>::tab;
-        constexpr int P = Basis<2, 5>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 6) {
-        constexpr auto &t = Basis<2, 6>::tab;
-        constexpr int P = Basis<2, 6>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 8) {
-        constexpr auto &t = Basis<2, 8>::tab;
-        constexpr int P = Basis<2, 8>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 2; ++v) nu[l * 2 + v] = t.nu[l][v];
-        return P;
-    }
-    return 0;
-}
-
-hipError_t launch_batch_d1(int eta, bool fp32, bool bump, int blocks,
-                            hipStream_t s, const BatchTileDesc *probs,
-                            int nprob, const long long *tile_begin,
-                            unsigned int *counter)
-{
-    BSDE_BATCH_CASE(1, 2)
-    BSDE_BATCH_CASE(1, 3)
-    BSDE_BATCH_CASE(1, 4)
-    BSDE_BATCH_CASE(1, 5)
-    BSDE_BATCH_CASE(1, 6)
-    BSDE_BATCH_CASE(1, 8)
-    return hipErrorInvalidValue;
-}
-
-// blocks of the batched kernel resident per CU
-int batch_occupancy_d1(int eta, bool fp32, bool bump)
-{
-    int nb = 0;
-#define OCC(E, R, V)                                                           \
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(                        \
-        &nb, batch_path_kernel<1, E, R, V>, kBlock, 0)
-    if (eta == 2) {
-        if (fp32 && bump) OCC(2, float, kVolBump);
-        else if (fp32) OCC(2, float, kVolConst);
-        else if (bump) OCC(2, double, kVolBump);
-        else OCC(2, double, kVolConst);
-    }
-    if (eta == 3) {
-        if (fp32 && bump) OCC(3, float, kVolBump);
-        else if (fp32) OCC(3, float, kVolConst);
-        else if (bump) OCC(3, double, kVolBump);
-        else OCC(3, double, kVolConst);
-    }
-    if (eta == 4) {
-        if (fp32 && bump) OCC(4, float, kVolBump);
-        else if (fp32) OCC(4, float, kVolConst);
-        else if (bump) OCC(4, double, kVolBump);
-        else OCC(4, double, kVolConst);
-    }
-    if (eta == 5) {
-        if (fp32 && bump) OCC(5, float, kVolBump);
-        else if (fp32) OCC(5, float, kVolConst);
-        else if (bump) OCC(5, double, kVolBump);
-        else OCC(5, double, kVolConst);
-    }
-    if (eta == 6) {
-        if (fp32 && bump) OCC(6, float, kVolBump);
-        else if (fp32) OCC(6, float, kVolConst);
-        else if (bump) OCC(6, double, kVolBump);
-        else OCC(6, double, kVolConst);
-    }
-    if (eta == 8) {
-        if (fp32 && bump) OCC(8, float, kVolBump);
-        else if (fp32) OCC(8, float, kVolConst);
-        else if (bump) OCC(8, double, kVolBump);
-        else OCC(8, double, kVolConst);
-    }
-#undef OCC
-    return nb;
-}
-
+#define SETS_D1(X)                                                             \
+    X(2, true, false) X(3, true, false) X(4, true, true) X(5, true, false)     \
+    X(6, true, false) X(8, true, false)
+BSDE_DEFINE_DIMENSION(1, SETS_D1)
 } // namespace bsde

@@ -1,70 +1,9 @@
-// bsde_inst_d5.hip -- path kernels for d = 5 (eta in {2, 3}).
+// bsde_inst_d5.hip -- path kernels for d = 5: eta in {2, 3}, FP32 and FP64
+// paths, all volatility kinds (the Dupire-type one for the paper's d = 5
+// runs of Section 6).
 #include "bsde_path.h"
 
 namespace bsde {
-
-hipError_t launch_path_d5(int eta, bool fp32, int blocks, hipStream_t s,
-                           const PathParams &prm, const double *pts,
-                           const void *gamma, double *partial)
-{
-    BSDE_PATH_CASE(5, 2)
-    BSDE_PATH_CASE(5, 3)
-    return hipErrorInvalidValue;
-}
-
-// multi-indices of the kernels' basis, in the kernels' order
-int index_table_d5(int eta, int8_t *nu, int cap)
-{
-    if (eta == 2) {
-        constexpr auto &t = Basis<6, 2>::tab;
-        constexpr int P = Basis<6, 2>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 6; ++v) nu[l * 6 + v] = t.nu[l][v];
-        return P;
-    }
-    if (eta == 3) {
-        constexpr auto &t = Basis<6, 3>::tab;
-        constexpr int P = Basis<6, 3>::P;
-        if (nu && cap >= P)
-            for (int l = 0; l < P; ++l)
-                for (int v = 0; v < 6; ++v) nu[l * 6 + v] = t.nu[l][v];
-        return P;
-    }
-    return 0;
-}
-
-hipError_t launch_batch_d5(int eta, bool fp32, bool bump, int blocks,
-                            hipStream_t s, const BatchTileDesc *probs,
-                            int nprob, const long long *tile_begin,
-                            unsigned int *counter)
-{
-    BSDE_BATCH_CASE(5, 2)
-    BSDE_BATCH_CASE(5, 3)
-    return hipErrorInvalidValue;
-}
-
-// blocks of the batched kernel resident per CU
-int batch_occupancy_d5(int eta, bool fp32, bool bump)
-{
-    int nb = 0;
-#define OCC(E, R, V)                                                           \
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(                        \
-        &nb, batch_path_kernel<5, E, R, V>, kBlock, 0)
-    if (eta == 2) {
-        if (fp32 && bump) OCC(2, float, kVolBump);
-        else if (fp32) OCC(2, float, kVolConst);
-        else if (bump) OCC(2, double, kVolBump);
-        else OCC(2, double, kVolConst);
-    }
-    if (eta == 3) {
-        if (fp32 && bump) OCC(3, float, kVolBump);
-        else if (fp32) OCC(3, float, kVolConst);
-        else if (bump) OCC(3, double, kVolBump);
-        else OCC(3, double, kVolConst);
-    }
-#undef OCC
-    return nb;
-}
-
+#define SETS_D5(X) X(2, true, true) X(3, true, true)
+BSDE_DEFINE_DIMENSION(5, SETS_D5)
 } // namespace bsde

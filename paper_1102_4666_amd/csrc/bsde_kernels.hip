@@ -175,11 +175,12 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial);           \
     int index_table_d##D(int eta, int8_t *nu, int cap);                        \
-    hipError_t launch_batch_d##D(int eta, bool fp32, bool bump, int blocks,     \
+    hipError_t launch_batch_d##D(int eta, bool fp32, int vol, int blocks,      \
                                  hipStream_t s, const BatchTileDesc *probs,    \
                                  int nprob, const long long *tile_begin,       \
                                  unsigned int *counter);                       \
-    int batch_occupancy_d##D(int eta, bool fp32, bool bump);
+    int batch_occupancy_d##D(int eta, bool fp32, int vol);                     \
+    bool has_variant_d##D(int eta, bool fp32, int vol);
 BSDE_DIMS(DECL)
 #undef DECL
 
@@ -194,6 +195,15 @@ int index_table(int d, int eta, int8_t *nu, int cap)
 
 bool kernel_exists(int d, int eta) { return index_table(d, eta, nullptr, 0) > 0; }
 
+bool variant_exists(int d, int eta, bool fp32, int vol)
+{
+#define X(D)                                                                   \
+    if (d == D) return has_variant_d##D(eta, fp32, vol);
+    BSDE_DIMS(X)
+#undef X
+    return false;
+}
+
 hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
                        const PathParams &prm, const double *pts,
                        const void *gamma, double *partial)
@@ -206,23 +216,23 @@ hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(int d, int eta, bool fp32, bool bump, int blocks,
+hipError_t launch_batch(int d, int eta, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter)
 {
 #define X(D)                                                                   \
     if (d == D)                                                                \
-        return launch_batch_d##D(eta, fp32, bump, blocks, s, probs, nprob,     \
+        return launch_batch_d##D(eta, fp32, vol, blocks, s, probs, nprob,      \
                                  tile_begin, counter);
     BSDE_DIMS(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-int batch_occupancy(int d, int eta, bool fp32, bool bump)
+int batch_occupancy(int d, int eta, bool fp32, int vol)
 {
 #define X(D)                                                                   \
-    if (d == D) return batch_occupancy_d##D(eta, fp32, bump);
+    if (d == D) return batch_occupancy_d##D(eta, fp32, vol);
     BSDE_DIMS(X)
 #undef X
     return 0;

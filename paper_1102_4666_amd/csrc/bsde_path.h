@@ -88,14 +88,40 @@ struct Arith<double> {
     }
 };
 
-// sigma_j = level (1 + a e^{-(x - log c)^2}) = level + (level a) e^{...}
+// Time factors of the Dupire-type volatility of eq. vol_locale, uniform
+// across the paths of a point at one Euler step: with S = e^x,
+// sigma(t, S) = A(t) - B(t) e^{-0.001 (S e^{r t} - s)^2}, A = 0.72 e^{-0.05
+// sqrt t}, B = 0.6 e^{-0.1 t} e^{-0.05 sqrt t}, rt = r t.
+template <typename Real>
+struct VolTime {
+    Real A, B, rt;
+};
+template <int VOL, typename Real>
+__device__ __forceinline__ VolTime<Real> vol_time(Real t, Real r)
+{
+    VolTime<Real> v{Real(0), Real(0), Real(0)};
+    if constexpr (VOL == kVolDupire) {
+        const Real damp = Arith<Real>::exp(Real(-0.05) * Arith<Real>::sqrt(t));
+        v.A = Real(0.72) * damp;
+        v.B = Real(0.6) * damp * Arith<Real>::exp(Real(-0.1) * t);
+        v.rt = r * t;
+    }
+    return v;
+}
+
+// sigma_j of log-price x: constant; bump level (1 + a e^{-(x - log c)^2})
+// = level + (level a) e^{...}; or the Dupire-type form above
 template <int VOL, typename Real>
 __device__ __forceinline__ Real local_vol(Real level, Real level_a, Real lc,
+                                          Real spot, const VolTime<Real> &vt,
                                           Real x)
 {
     if constexpr (VOL == kVolBump) {
         Real dx = x - lc;
         return fma(level_a, Arith<Real>::exp(-dx * dx), level);
+    } else if constexpr (VOL == kVolDupire) {
+        const Real dev = Arith<Real>::exp(x + vt.rt) - spot;
+        return fma(-vt.B, Arith<Real>::exp(Real(-0.001) * dev * dev), vt.A);
     }
     return level;
 }
@@ -268,6 +294,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 const int s = grp * SG + ss;
                 if (s < prm.N) {
                     const bool at = (s == jstar);
+                    const VolTime<Real> vt = vol_time<VOL>(t0 + Real(s) * h, r);
                     Real S = Real(0);
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
@@ -277,7 +304,8 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         if (j > 0) lg = fma(ac.Ldiag[j], G[ss * D + j], S);
                         if (j + 1 < D) S = j == 0 ? ac.Lcol[0] * G[ss * D]
                                                   : fma(ac.Lcol[j], G[ss * D + j], S);
-                        const Real sig = local_vol<VOL>(ac.level[j], ac.level_a[j], lc, X[j]);
+                        const Real sig = local_vol<VOL>(ac.level[j], ac.level_a[j], lc,
+                                                        ac.spot[j], vt, X[j]);
                         Xs[j] = at ? X[j] : Xs[j];
                         LGs[j] = at ? lg : LGs[j];
                         // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
@@ -304,12 +332,14 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         }
         Real sgs[D], bst[D], Xt[D];
         Real Sb = Real(0);
+        const VolTime<Real> vts = vol_time<VOL>(t0 + Real(jstar) * h, r);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             Real lgb = Gb[0];
             if (j > 0) lgb = fma(ac.Ldiag[j], Gb[j], Sb);
             if (j + 1 < D) Sb = j == 0 ? ac.Lcol[0] * Gb[0] : fma(ac.Lcol[j], Gb[j], Sb);
-            sgs[j] = local_vol<VOL>(ac.level[j], ac.level_a[j], lc, Xs[j]);
+            sgs[j] = local_vol<VOL>(ac.level[j], ac.level_a[j], lc, ac.spot[j], vts,
+                                    Xs[j]);
             bst[j] = fma(Real(-0.5) * sgs[j], sgs[j], ac.drift[j]);
             Xt[j] = Xs[j] + bst[j] * theta * h +
                     sgs[j] * fma(theta, LGs[j], lgb);
@@ -592,45 +622,123 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void batch_pat
     }
 }
 
+// ---------------------------------------------------------------------------
+// Instantiation and dispatch.  For one (d, eta) the kernels exist for FP32
+// paths and, when FP64 is set, FP64 paths; for the constant and bump
+// volatilities and, when DUP is set, the Dupire-type one.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TypeTag {
+    using type = T;
+};
+
+// calls f(TypeTag<Real>, integral_constant<VOL>) for the variant at hand;
+// hipErrorInvalidValue when it is not instantiated
+template <int D, int E, bool FP64, bool DUP, typename F>
+hipError_t dispatch_variant(bool fp32, int vol, F &&f)
+{
+    auto by_vol = [&](auto rt) -> hipError_t {
+        if (vol == kVolConst) return f(rt, std::integral_constant<int, kVolConst>{});
+        if (vol == kVolBump) return f(rt, std::integral_constant<int, kVolBump>{});
+        if constexpr (DUP) {
+            if (vol == kVolDupire) return f(rt, std::integral_constant<int, kVolDupire>{});
+        }
+        return hipErrorInvalidValue;
+    };
+    if (fp32) return by_vol(TypeTag<float>{});
+    if constexpr (FP64) return by_vol(TypeTag<double>{});
+    return hipErrorInvalidValue;
+}
+
+template <int D, int E>
+int copy_index_table(int8_t *nu, int cap)
+{
+    constexpr int DP = D + 1;
+    constexpr auto &t = Basis<DP, E>::tab;
+    constexpr int P = Basis<DP, E>::P;
+    if (nu && cap >= P)
+        for (int l = 0; l < P; ++l)
+            for (int v = 0; v < DP; ++v) nu[l * DP + v] = t.nu[l][v];
+    return P;
+}
+
 } // namespace bsde
 
-// Launch of the FP32 or FP64 kernel for (D, E) with the volatility kind
-// of the parameters; used by the per-dimension launchers launch_path_dD.
-#define BSDE_PATH_LAUNCH(D, E, R, V)                                           \
-    hipLaunchKernelGGL((path_kernel<D, E, R, V>), dim3(blocks), dim3(kBlock),  \
-                       0, s, prm, pts, (const R *)gamma, partial)
-#define BSDE_BATCH_LAUNCH(D, E, R, V)                                          \
-    hipLaunchKernelGGL((batch_path_kernel<D, E, R, V>), dim3(blocks),          \
-                       dim3(kBlock), 0, s, probs, nprob, tile_begin, counter)
-#define BSDE_BATCH_CASE(D, E)                                                  \
-    if (eta == E) {                                                            \
-        if (fp32 && bump) BSDE_BATCH_LAUNCH(D, E, float, kVolBump);            \
-        else if (fp32) BSDE_BATCH_LAUNCH(D, E, float, kVolConst);              \
-        else if (bump) BSDE_BATCH_LAUNCH(D, E, double, kVolBump);              \
-        else BSDE_BATCH_LAUNCH(D, E, double, kVolConst);                       \
-        return hipGetLastError();                                              \
-    }
-#define BSDE_PATH_CASE(D, E)                                                   \
-    if (eta == E) {                                                            \
-        const bool bump = prm.vol_kind == kVolBump;                            \
-        if (fp32 && bump) BSDE_PATH_LAUNCH(D, E, float, kVolBump);             \
-        else if (fp32) BSDE_PATH_LAUNCH(D, E, float, kVolConst);               \
-        else if (bump) BSDE_PATH_LAUNCH(D, E, double, kVolBump);               \
-        else BSDE_PATH_LAUNCH(D, E, double, kVolConst);                        \
-        return hipGetLastError();                                              \
+// Defines launch_path_dD, index_table_dD, launch_batch_dD,
+// batch_occupancy_dD and has_variant_dD for the (eta, FP64, Dupire) sets
+// listed by SETS(X) as X(E, FP64, DUP).
+#define BSDE_DEFINE_DIMENSION(D, SETS)                                         \
+    hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s, \
+                                const PathParams &prm, const double *pts,      \
+                                const void *gamma, double *partial)            \
+    {                                                                          \
+        constexpr int D_ = D;                                                  \
+        SETS(BSDE_PATH_SET)                                                    \
+        return hipErrorInvalidValue;                                           \
+    }                                                                          \
+    int index_table_d##D(int eta, int8_t *nu, int cap)                         \
+    {                                                                          \
+        constexpr int D_ = D;                                                  \
+        SETS(BSDE_TABLE_SET)                                                   \
+        return 0;                                                              \
+    }                                                                          \
+    hipError_t launch_batch_d##D(int eta, bool fp32, int vol, int blocks,      \
+                                 hipStream_t s, const BatchTileDesc *probs,    \
+                                 int nprob, const long long *tile_begin,       \
+                                 unsigned int *counter)                        \
+    {                                                                          \
+        constexpr int D_ = D;                                                  \
+        SETS(BSDE_BATCH_SET)                                                   \
+        return hipErrorInvalidValue;                                           \
+    }                                                                          \
+    int batch_occupancy_d##D(int eta, bool fp32, int vol)                      \
+    {                                                                          \
+        constexpr int D_ = D;                                                  \
+        int nb = 0;                                                            \
+        SETS(BSDE_OCC_SET)                                                     \
+        return nb;                                                             \
+    }                                                                          \
+    bool has_variant_d##D(int eta, bool fp32, int vol)                         \
+    {                                                                          \
+        constexpr int D_ = D;                                                  \
+        SETS(BSDE_HAS_SET)                                                     \
+        return false;                                                          \
     }
 
-// FP32-path-only variants (d = 10: the FP64 form would not fit the register
-// file); FP64 requests are rejected at problem creation.
-#define BSDE_PATH_CASE_FP32(D, E)                                              \
-    if (eta == E && fp32) {                                                    \
-        if (prm.vol_kind == kVolBump) BSDE_PATH_LAUNCH(D, E, float, kVolBump); \
-        else BSDE_PATH_LAUNCH(D, E, float, kVolConst);                         \
-        return hipGetLastError();                                              \
-    }
-#define BSDE_BATCH_CASE_FP32(D, E)                                             \
-    if (eta == E && fp32) {                                                    \
-        if (bump) BSDE_BATCH_LAUNCH(D, E, float, kVolBump);                    \
-        else BSDE_BATCH_LAUNCH(D, E, float, kVolConst);                        \
-        return hipGetLastError();                                              \
-    }
+#define BSDE_PATH_SET(E, F64, DUP)                                             \
+    if (eta == E)                                                              \
+        return dispatch_variant<D_, E, F64, DUP>(                              \
+            fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
+                using R = typename decltype(rt)::type;                         \
+                hipLaunchKernelGGL((path_kernel<D_, E, R, decltype(vt)::value>),\
+                                   dim3(blocks), dim3(kBlock), 0, s, prm, pts, \
+                                   (const R *)gamma, partial);                 \
+                return hipGetLastError();                                      \
+            });
+#define BSDE_TABLE_SET(E, F64, DUP)                                            \
+    if (eta == E) return copy_index_table<D_, E>(nu, cap);
+#define BSDE_BATCH_SET(E, F64, DUP)                                            \
+    if (eta == E)                                                              \
+        return dispatch_variant<D_, E, F64, DUP>(                              \
+            fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
+                using R = typename decltype(rt)::type;                         \
+                hipLaunchKernelGGL(                                            \
+                    (batch_path_kernel<D_, E, R, decltype(vt)::value>),        \
+                    dim3(blocks), dim3(kBlock), 0, s, probs, nprob,            \
+                    tile_begin, counter);                                      \
+                return hipGetLastError();                                      \
+            });
+#define BSDE_OCC_SET(E, F64, DUP)                                              \
+    if (eta == E)                                                              \
+        (void)dispatch_variant<D_, E, F64, DUP>(                               \
+            fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
+                using R = typename decltype(rt)::type;                         \
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(           \
+                    &nb, batch_path_kernel<D_, E, R, decltype(vt)::value>,     \
+                    kBlock, 0);                                                \
+            });
+#define BSDE_HAS_SET(E, F64, DUP)                                              \
+    if (eta == E)                                                              \
+        return dispatch_variant<D_, E, F64, DUP>(                              \
+                   fp32, vol, [](auto, auto) { return hipSuccess; }) ==        \
+               hipSuccess;

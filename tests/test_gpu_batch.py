@@ -25,6 +25,10 @@ def _mix():
                 omega=100.0, precision="fp32", seed=6),
         problem(d=1, vol_kind="bump", bump_a=0.25, n_t=6, n_x=20, eta=4,
                 M=1500, N=9, K_it=3, omega=1.0, precision="fp32", seed=7),
+        # the Dupire-type volatility: a kernel signature of its own
+        problem(d=5, vol_kind="dupire", vol_level=0.3, div=0.1, S0=100.0,
+                grid="random", n_t=3, n_x=40, eta=2, M=100, N=4, K_it=2,
+                omega=1.0, precision="fp32", seed=8),
     ]
 
 

@@ -51,6 +51,15 @@ CASES = {
     "d10_eta3": problem(d=10, vol_level=0.2, rho=0.3, payoff="call_geom",
                         S0=100.0, grid="random", n_t=4, n_x=300, eta=3,
                         M=16, N=3, K_it=2),
+    # the Dupire-type local volatility of eq. vol_locale (time-dependent)
+    "d1_dupire": problem(d=1, vol_kind="dupire", vol_level=0.3, n_t=6,
+                         n_x=20, eta=4, M=300, N=10, K_it=3, omega=1.0),
+    "d2_dupire": problem(d=2, vol_kind="dupire", vol_level=0.3, rho=0.2,
+                         S0=[100.0, 110.0], n_t=4, n_x=6, eta=3, M=260, N=6,
+                         K_it=2, omega=1.0),
+    "d5_dupire": problem(d=5, vol_kind="dupire", vol_level=0.3, div=0.1,
+                         S0=100.0, grid="random", n_t=4, n_x=60, eta=3,
+                         M=100, N=4, K_it=2, omega=1.0),
     # random points redrawn at every Picard iteration (Algorithm 1), the
     # least-squares factorisation redone on the device each time
     "d2_redraw": problem(d=2, vol_kind="bump", vol_level=[0.2, 0.3],
