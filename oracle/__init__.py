@@ -23,7 +23,7 @@ DMAX = 16
 VOL_KINDS = {"const": 0, "bump": 1, "dupire": 2}
 PAYOFFS = {"put": 0, "call": 1, "put_geom": 2, "call_geom": 3, "fwd": 4,
            "quad": 5}
-GRIDS = {"tensor": 0, "random": 1}
+GRIDS = {"tensor": 0, "random": 1, "uniform": 2}
 
 
 def build() -> str:
@@ -350,7 +350,7 @@ def solve_parallel(cfg, workers=8, chunk=64, k_start=0, alpha_start=None,
     ranges = [(i, min(i + chunk, n)) for i in range(0, n, chunk)]
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
-        redraw = bool(cfg.get("redraw", 0)) and cfg.get("grid") == "random"
+        redraw = bool(cfg.get("redraw", 0)) and cfg.get("grid") in ("random", "uniform")
         for k in range(k_start, k_end):
             if redraw:
                 B = basis_matrix(cfg, k)

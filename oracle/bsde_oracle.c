@@ -178,6 +178,7 @@ static long n_spatial(const oracle_problem *pb)
 
 int oracle_num_points(const oracle_problem *pb)
 {
+    if (pb->grid == ORACLE_GRID_UNIFORM) return pb->n_x;
     return (int)(n_spatial(pb) * pb->n_t);
 }
 
@@ -192,7 +193,23 @@ int oracle_points(const oracle_problem *pb, double *pts)
 int oracle_points_k(const oracle_problem *pb, uint32_t k, double *pts)
 {
     int d = pb->d;
-    uint32_t kdraw = (pb->redraw && pb->grid == ORACLE_GRID_RANDOM) ? k : 0;
+    uint32_t kdraw = (pb->redraw && pb->grid != ORACLE_GRID_TENSOR) ? k : 0;
+    if (pb->grid == ORACLE_GRID_UNIFORM) {
+        /* point i: word q of the counter (i, 0, k, substream 3 | q / 4) is
+         * t for q = 0 and x_j for q = 1 + j, each uniform on its range */
+        double lo[ORACLE_DMAX], hi[ORACLE_DMAX];
+        oracle_domain(pb, lo, hi);
+        for (int i = 0; i < pb->n_x; ++i) {
+            double *row = pts + (size_t)i * (d + 1);
+            for (int q = 0; q <= d; ++q) {
+                uint32_t w[4];
+                philox_block(pb->seed, (uint32_t)i, 0, kdraw, 3, (uint32_t)(q / 4), w);
+                double u = u01(w[q % 4]);
+                row[q] = q == 0 ? pb->T * u : lo[q - 1] + u * (hi[q - 1] - lo[q - 1]);
+            }
+        }
+        return pb->n_x;
+    }
     long ns = n_spatial(pb);
     double lo[ORACLE_DMAX], hi[ORACLE_DMAX];
     oracle_domain(pb, lo, hi);
@@ -603,7 +620,8 @@ int oracle_solve(const oracle_problem *pb, int k_start,
                  double *c_hist, double *var_hist, double *u_hist)
 {
     int d = pb->d;
-    if (d < 1 || d > ORACLE_DMAX || pb->N < 1 || pb->M < 1 || pb->n_t < 2 ||
+    if (d < 1 || d > ORACLE_DMAX || pb->N < 1 || pb->M < 1 ||
+        (pb->grid != ORACLE_GRID_UNIFORM && pb->n_t < 2) ||
         pb->n_x < 1 || k_start < 0 || k_end < k_start)
         return ORACLE_EINVAL;
     double Ltest[ORACLE_DMAX * ORACLE_DMAX];
@@ -630,7 +648,7 @@ int oracle_solve(const oracle_problem *pb, int k_start,
 
     int status = ORACLE_OK;
     int have_alpha = alpha_start != NULL;
-    int redraw = pb->redraw && pb->grid == ORACLE_GRID_RANDOM;
+    int redraw = pb->redraw && pb->grid != ORACLE_GRID_TENSOR;
     for (int k = k_start; k < k_end; ++k) {
         /* the points of this iteration (Algorithm 1: new uniform points at
          * every iteration) and their basis matrix */

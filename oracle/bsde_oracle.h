@@ -69,7 +69,9 @@ enum {
     ORACLE_FWD_ARITH = 4,  /* mean_j e^{x_j} - K   (call minus put)            */
     ORACLE_QUAD = 5        /* (sum_j x_j)^2        (test payoff)               */
 };
-enum { ORACLE_GRID_TENSOR = 0, ORACLE_GRID_RANDOM = 1 };
+/* points: tensor grid x time nodes; random spatial points x time nodes;
+ * or n_x points uniform in [0, T] x D (Algorithm 1's literal draw) */
+enum { ORACLE_GRID_TENSOR = 0, ORACLE_GRID_RANDOM = 1, ORACLE_GRID_UNIFORM = 2 };
 
 enum {
     ORACLE_OK = 0,
@@ -97,8 +99,8 @@ typedef struct {
     int M, N, K_it;
     double omega;                   /* penalisation weight (0 = European)   */
     uint64_t seed;
-    int redraw;                     /* random grid: new points every        */
-                                    /* Picard iteration (Algorithm 1)       */
+    int redraw;                     /* random/uniform points: new points    */
+                                    /* every Picard iteration (Algorithm 1) */
 } oracle_problem;
 
 /* --- randomness ------------------------------------------------------- */

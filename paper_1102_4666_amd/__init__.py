@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libbsde.so")
 VOL_KINDS = {"const": 0, "bump": 1, "dupire": 2}
 PAYOFFS = {"put": 0, "call": 1, "put_geom": 2, "call_geom": 3, "fwd": 4,
            "quad": 5}
-GRIDS = {"tensor": 0, "random": 1}
+GRIDS = {"tensor": 0, "random": 1, "uniform": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 STATUS = {0: "BSDE_OK", 1: "BSDE_EINVAL", 2: "BSDE_ENOMEM", 3: "BSDE_ERANK",

@@ -59,10 +59,13 @@ __host__ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1,
 }
 
 // ---------------------------------------------------------------------------
-// Total-degree index set {nu in N^{DP} : |nu| <= ETA}, graded, and within a
-// degree lexicographically decreasing.  For every multi-index the table
-// gives the "parent" obtained by zeroing its last non-zero entry, the
-// variate of that entry and its degree: B_nu = B_parent * T_deg(z_var).
+// Index set of the basis (Section 4.2, the hyperbolic sets of eq.
+// hyper_set): {nu in N^{DP} : (sum_j nu_j^q)^{1/q} <= ETA} with q = Q / 10
+// (Q = 10: the total-degree set |nu| <= ETA), graded, and within a degree
+// lexicographically decreasing.  For every multi-index the table gives the
+// "parent" obtained by zeroing its last non-zero entry (the sets are
+// downward closed, so it is in the set), the variate of that entry and its
+// degree: B_nu = B_parent * T_deg(z_var).
 // ---------------------------------------------------------------------------
 constexpr int binom(int n, int k)
 {
@@ -71,27 +74,65 @@ constexpr int binom(int n, int k)
     return (int)r;
 }
 
-template <int DP, int ETA>
-struct IndexTable {
-    static constexpr int P = binom(DP + ETA, ETA);
-    int8_t nu[P][DP];
-    int16_t parent[P];
-    int8_t var[P];
-    int8_t deg[P];
-};
-
-template <int DP, int ETA>
-constexpr IndexTable<DP, ETA> make_index_table()
+// compile-time exp and log (series, to double rounding) for the q-norms
+constexpr double c_exp(double x)
 {
-    IndexTable<DP, ETA> t{};
-    int count = 0;
+    int k = 0;
+    while (x > 0.5 || x < -0.5) {
+        x *= 0.5;
+        ++k;
+    }
+    double term = 1.0, sum = 1.0;
+    for (int i = 1; i < 30; ++i) {
+        term *= x / i;
+        sum += term;
+    }
+    for (int i = 0; i < k; ++i) sum *= sum;
+    return sum;
+}
+constexpr double c_log(double x)
+{
+    int e = 0;
+    while (x > 1.5) {
+        x *= 0.5;
+        ++e;
+    }
+    while (x < 0.75) {
+        x *= 2.0;
+        --e;
+    }
+    const double y = (x - 1.0) / (x + 1.0), y2 = y * y;
+    double term = y, sum = 0.0;
+    for (int i = 1; i < 80; i += 2) {
+        sum += term / i;
+        term *= y2;
+    }
+    return 2.0 * sum + e * 0.693147180559945309417232121458;
+}
+// n^(Q/10) for a non-negative integer n
+constexpr double qpow(int n, int Q)
+{
+    return n == 0 ? 0.0 : Q == 10 ? (double)n : c_exp(Q / 10.0 * c_log((double)n));
+}
+template <int DP>
+constexpr bool in_index_set(const int *nu, int eta, int Q)
+{
+    if (Q == 10) return true; // the total degree is bounded by the enumeration
+    double s = 0.0;
+    for (int v = 0; v < DP; ++v) s += qpow(nu[v], Q);
+    return s <= qpow(eta, Q) * (1.0 + 1e-12);
+}
+
+// visits the multi-indices of total degree <= ETA in table order
+template <int DP, int ETA, typename F>
+constexpr void for_each_total_degree(F &&f)
+{
     for (int g = 0; g <= ETA; ++g) {
         // odometer over compositions of g into DP parts, first part largest
         int cur[DP] = {};
         cur[0] = g;
         while (true) {
-            for (int v = 0; v < DP; ++v) t.nu[count][v] = (int8_t)cur[v];
-            ++count;
+            f(cur);
             // next composition in lexicographically decreasing order
             int j = DP - 2;
             while (j >= 0 && cur[j] == 0) --j;
@@ -103,6 +144,37 @@ constexpr IndexTable<DP, ETA> make_index_table()
             cur[j + 1] = rest + 1;
         }
     }
+}
+
+template <int DP, int ETA, int Q>
+constexpr int index_set_size()
+{
+    int count = 0;
+    for_each_total_degree<DP, ETA>([&](const int *nu) {
+        if (in_index_set<DP>(nu, ETA, Q)) ++count;
+    });
+    return count;
+}
+
+template <int DP, int ETA, int Q>
+struct IndexTable {
+    static constexpr int P = index_set_size<DP, ETA, Q>();
+    int8_t nu[P][DP];
+    int16_t parent[P];
+    int8_t var[P];
+    int8_t deg[P];
+};
+
+template <int DP, int ETA, int Q>
+constexpr IndexTable<DP, ETA, Q> make_index_table()
+{
+    IndexTable<DP, ETA, Q> t{};
+    int count = 0;
+    for_each_total_degree<DP, ETA>([&](const int *cur) {
+        if (!in_index_set<DP>(cur, ETA, Q)) return;
+        for (int v = 0; v < DP; ++v) t.nu[count][v] = (int8_t)cur[v];
+        ++count;
+    });
     for (int l = 0; l < t.P; ++l) {
         int last = -1;
         for (int v = 0; v < DP; ++v)
@@ -129,10 +201,10 @@ constexpr IndexTable<DP, ETA> make_index_table()
     return t;
 }
 
-template <int DP, int ETA>
+template <int DP, int ETA, int Q = 10>
 struct Basis {
-    static constexpr int P = binom(DP + ETA, ETA);
-    static constexpr IndexTable<DP, ETA> tab = make_index_table<DP, ETA>();
+    static constexpr int P = IndexTable<DP, ETA, Q>::P;
+    static constexpr IndexTable<DP, ETA, Q> tab = make_index_table<DP, ETA, Q>();
 };
 
 // number of derivative channels: u, d_t u, d d_x u, d(d+1)/2 d_xx u

@@ -26,9 +26,9 @@
 #include <vector>
 
 namespace bsde {
-bool kernel_exists(int d, int eta);
-int index_table(int d, int eta, int8_t *nu, int cap);
-hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
+bool kernel_exists(int d, int eta, int q10);
+int index_table(int d, int eta, int q10, int8_t *nu, int cap);
+hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream_t s,
                        const PathParams &prm, const double *pts,
                        const void *gamma, double *partial);
 hipError_t launch_update(int n, int groups, int M, int p, int C,
@@ -39,11 +39,11 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          hipEvent_t *ev);
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
                            const double *Dmat, double *g64, float *g32);
-hipError_t launch_batch(int d, int eta, bool fp32, int vol, int blocks,
+hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter);
-int batch_occupancy(int d, int eta, bool fp32, int vol);
-bool variant_exists(int d, int eta, bool fp32, int vol);
+int batch_occupancy(int d, int eta, int q10, bool fp32, int vol);
+bool variant_exists(int d, int eta, int q10, bool fp32, int vol);
 hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
                                hipStream_t s, const BatchUpdateDesc *d);
 hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
@@ -223,6 +223,16 @@ static void parallel_for(long count, long min_chunk, double work, F fn)
         if (b < e) th.emplace_back(fn, b, e);
     }
     for (auto &x : th) x.join();
+}
+
+// q in tenths when a kernel of that hyperbolic set is built for (d, eta),
+// else 10 (the total-degree kernel, used with a mask for q < 1)
+static int kernel_q10(int d, int eta, double q)
+{
+    const double q10 = q * 10.0;
+    const int r = (int)std::lround(q10);
+    if (r >= 1 && r < 10 && std::fabs(q10 - r) < 1e-9 && kernel_exists(d, eta, r)) return r;
+    return 10;
 }
 
 // Upper Cholesky factor R of a symmetric positive definite G (p x p,
@@ -509,11 +519,11 @@ static void free_device(bsde_problem_s *h)
 // class; consulted when a problem is created.
 namespace {
 struct TuneKey {
-    int d, eta, prec, vol, M, N, nclass;
+    int d, eta, q10, prec, vol, M, N, nclass;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(d, eta, prec, vol, M, N, nclass) <
-               std::tie(o.d, o.eta, o.prec, o.vol, o.M, o.N, o.nclass);
+        return std::tie(d, eta, q10, prec, vol, M, N, nclass) <
+               std::tie(o.d, o.eta, o.q10, o.prec, o.vol, o.M, o.N, o.nclass);
     }
 };
 std::mutex g_tune_mu;
@@ -523,7 +533,7 @@ TuneKey tune_key(const bsde_problem_s *h)
 {
     int nclass = 0;
     while ((1 << nclass) < h->n) ++nclass;
-    return {h->d, h->eta, h->precision, h->base.vol_kind, h->M, h->N, nclass};
+    return {h->d, h->eta, h->q10, h->precision, h->base.vol_kind, h->M, h->N, nclass};
 }
 } // namespace
 
@@ -592,11 +602,14 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     for (int j = 0; j < d; ++j)
         if (!(sigma->level[j] > 0.0) || !(payoff->S0[j] > 0.0))
             return fail(BSDE_EINVAL, "levels and spots must be > 0");
-    if (!kernel_exists(d, grid->eta))
+    // a kernel of the hyperbolic set itself when one is built, else the
+    // total-degree kernel with the entries outside the set kept at zero
+    const int q10 = kernel_q10(d, grid->eta, grid->q);
+    if (!kernel_exists(d, grid->eta, q10))
         return fail(BSDE_EUNSUPPORTED, "no kernel instantiated for d=" +
                                            std::to_string(d) + ", eta=" +
                                            std::to_string(grid->eta));
-    if (!variant_exists(d, grid->eta, precision == BSDE_FP32_PATHS, sigma->kind))
+    if (!variant_exists(d, grid->eta, q10, precision == BSDE_FP32_PATHS, sigma->kind))
         return fail(BSDE_EUNSUPPORTED,
                     "no kernel instantiated for d=" + std::to_string(d) + ", eta=" +
                         std::to_string(grid->eta) + " with this precision and "
@@ -647,9 +660,10 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
 
     // index set in kernel order; hyperbolic subset marked active
     const int dp = d + 1;
-    h->p = index_table(d, grid->eta, nullptr, 0);
+    h->q10 = q10;
+    h->p = index_table(d, grid->eta, q10, nullptr, 0);
     h->nu.resize((size_t)h->p * dp);
-    index_table(d, grid->eta, h->nu.data(), h->p);
+    index_table(d, grid->eta, q10, h->nu.data(), h->p);
     h->active.assign(h->p, 1);
     if (grid->q < 1.0) {
         for (int l = 0; l < h->p; ++l) {
@@ -872,7 +886,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
         prm.paths_per_lane = ppl;
         prm.n = h->n;
         HIP_TRY(hipEventRecord(e[0], s));
-        HIP_TRY(launch_path(h->d, h->eta, fp32, h->n * groups, s, prm, h->d_pts,
+        HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * groups, s, prm, h->d_pts,
                             fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
                             h->d_partial));
         HIP_TRY(hipEventRecord(e[1], s));
@@ -922,12 +936,12 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
 // ---------------------------------------------------------------------------
 namespace {
 struct Sig {
-    int d, eta;
+    int d, eta, q10;
     bool fp32;
     int vol;
     bool operator<(const Sig &o) const
     {
-        return std::tie(d, eta, fp32, vol) < std::tie(o.d, o.eta, o.fp32, o.vol);
+        return std::tie(d, eta, q10, fp32, vol) < std::tie(o.d, o.eta, o.q10, o.fp32, o.vol);
     }
 };
 
@@ -985,7 +999,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     std::map<Sig, std::vector<int>> sigs;
     for (int q = 0; q < count; ++q) {
         bsde_problem h = probs[q];
-        sigs[{h->d, h->eta, h->precision == BSDE_FP32_PATHS,
+        sigs[{h->d, h->eta, h->q10, h->precision == BSDE_FP32_PATHS,
               h->base.vol_kind}].push_back(q);
     }
     // host-side descriptor tables, laid out in one byte buffer
@@ -1071,11 +1085,11 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         if (e != hipSuccess) return e;
         for (int step = 0; step < S; ++step) {
             for (const PathLaunch &pl : plan[step].paths) {
-                const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta,
+                const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta, pl.sig.q10,
                                                             pl.sig.fp32, pl.sig.vol));
                 const long long cap = (long long)occ * num_cus();
                 const int blocks = (int)std::max(1LL, std::min(pl.tiles, cap));
-                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.fp32, pl.sig.vol, blocks, s,
+                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.q10, pl.sig.fp32, pl.sig.vol, blocks, s,
                                  (const BatchTileDesc *)(dblob + pl.desc_off), pl.nprob,
                                  (const long long *)(dblob + pl.begin_off),
                                  counters + pl.counter);
@@ -1142,7 +1156,7 @@ bsde_status bsde::fetch_coefficients(bsde_problem h)
 size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
 {
     if (d < 1 || d > kMaxD || !grid) return 0;
-    const int p = index_table(d, grid->eta, nullptr, 0);
+    const int p = index_table(d, grid->eta, kernel_q10(d, grid->eta, grid->q), nullptr, 0);
     if (p == 0) return 0;
     size_t ns = 1;
     if (grid->kind == BSDE_GRID_TENSOR)
@@ -1238,7 +1252,7 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
         double t_min = 1e300;
         for (int rep = 0; rep < 5; ++rep) { // first launch warms up
             HIP_TRY(hipEventRecord(e0, s));
-            HIP_TRY(launch_path(h->d, h->eta, fp32, h->n * c.first, s, prm, h->d_pts,
+            HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * c.first, s, prm, h->d_pts,
                                 fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
                                 h->d_partial));
             HIP_TRY(hipEventRecord(e1, s));

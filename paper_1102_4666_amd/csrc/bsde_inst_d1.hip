@@ -4,7 +4,7 @@
 
 namespace bsde {
 #define SETS_D1(X)                                                             \
-    X(2, true, false) X(3, true, false) X(4, true, true) X(5, true, false)     \
-    X(6, true, false) X(8, true, false)
+    X(2, 10, true, false) X(3, 10, true, false) X(4, 10, true, true)           \
+    X(5, 10, true, false) X(6, 10, true, false) X(8, 10, true, false)
 BSDE_DEFINE_DIMENSION(1, SETS_D1)
 } // namespace bsde

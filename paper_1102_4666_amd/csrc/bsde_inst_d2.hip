@@ -3,6 +3,8 @@
 #include "bsde_path.h"
 
 namespace bsde {
-#define SETS_D2(X) X(2, true, false) X(3, true, true) X(4, true, false) X(5, true, false)
+#define SETS_D2(X)                                                             \
+    X(2, 10, true, false) X(3, 10, true, true) X(4, 10, true, false)           \
+    X(5, 10, true, false)
 BSDE_DEFINE_DIMENSION(2, SETS_D2)
 } // namespace bsde

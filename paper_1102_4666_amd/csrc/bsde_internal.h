@@ -20,6 +20,7 @@ struct bsde_problem_s {
     // grid: kind, nodes, redraw flag and the iteration whose points are on
     // the device (with redraw)
     int grid_kind = 0, n_t = 0, n_x = 0, redraw = 0, pts_k = 0;
+    int q10 = 10;                // index-set kernel: q in tenths (10 = total degree)
     std::vector<int> act;        // active multi-indices (hyperbolic set)
     std::vector<int8_t> nu;      // p x (d+1), kernel order
     std::vector<char> active;    // in the hyperbolic set

@@ -171,68 +171,74 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
 // ---------------------------------------------------------------------------
 #define BSDE_DIMS(X) X(1) X(2) X(3) X(5) X(10)
 #define DECL(D)                                                                \
-    hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s,  \
+    hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,        \
+                                hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial);           \
-    int index_table_d##D(int eta, int8_t *nu, int cap);                        \
-    hipError_t launch_batch_d##D(int eta, bool fp32, int vol, int blocks,      \
+    int index_table_d##D(int eta, int q10, int8_t *nu, int cap);               \
+    hipError_t launch_batch_d##D(int eta, int q10, bool fp32, int vol,         \
+                                 int blocks,                                   \
                                  hipStream_t s, const BatchTileDesc *probs,    \
                                  int nprob, const long long *tile_begin,       \
                                  unsigned int *counter);                       \
-    int batch_occupancy_d##D(int eta, bool fp32, int vol);                     \
-    bool has_variant_d##D(int eta, bool fp32, int vol);
+    int batch_occupancy_d##D(int eta, int q10, bool fp32, int vol);            \
+    bool has_variant_d##D(int eta, int q10, bool fp32, int vol);
 BSDE_DIMS(DECL)
 #undef DECL
 
-int index_table(int d, int eta, int8_t *nu, int cap)
+int index_table(int d, int eta, int q10, int8_t *nu, int cap)
 {
 #define X(D)                                                                   \
-    if (d == D) return index_table_d##D(eta, nu, cap);
+    if (d == D) return index_table_d##D(eta, q10, nu, cap);
     BSDE_DIMS(X)
 #undef X
     return 0;
 }
 
-bool kernel_exists(int d, int eta) { return index_table(d, eta, nullptr, 0) > 0; }
+bool kernel_exists(int d, int eta, int q10)
+{
+    return index_table(d, eta, q10, nullptr, 0) > 0;
+}
 
-bool variant_exists(int d, int eta, bool fp32, int vol)
+bool variant_exists(int d, int eta, int q10, bool fp32, int vol)
 {
 #define X(D)                                                                   \
-    if (d == D) return has_variant_d##D(eta, fp32, vol);
+    if (d == D) return has_variant_d##D(eta, q10, fp32, vol);
     BSDE_DIMS(X)
 #undef X
     return false;
 }
 
-hipError_t launch_path(int d, int eta, bool fp32, int blocks, hipStream_t s,
+hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream_t s,
                        const PathParams &prm, const double *pts,
                        const void *gamma, double *partial)
 {
 #define X(D)                                                                   \
     if (d == D)                                                                \
-        return launch_path_d##D(eta, fp32, blocks, s, prm, pts, gamma, partial);
+        return launch_path_d##D(eta, q10, fp32, blocks, s, prm, pts, gamma,    \
+                                partial);
     BSDE_DIMS(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(int d, int eta, bool fp32, int vol, int blocks,
+hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter)
 {
 #define X(D)                                                                   \
     if (d == D)                                                                \
-        return launch_batch_d##D(eta, fp32, vol, blocks, s, probs, nprob,      \
+        return launch_batch_d##D(eta, q10, fp32, vol, blocks, s, probs, nprob, \
                                  tile_begin, counter);
     BSDE_DIMS(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-int batch_occupancy(int d, int eta, bool fp32, int vol)
+int batch_occupancy(int d, int eta, int q10, bool fp32, int vol)
 {
 #define X(D)                                                                   \
-    if (d == D) return batch_occupancy_d##D(eta, fp32, vol);
+    if (d == D) return batch_occupancy_d##D(eta, q10, fp32, vol);
     BSDE_DIMS(X)
 #undef X
     return 0;

@@ -211,7 +211,7 @@ struct Mfma<double> {
 // Gamma is read-only, uniform across the workgroup and read once per basis
 // function and channel per path: its loads must stay scalar (SGPR) loads,
 // so GammaPtr is a global restrict pointer or a constant-address-space one.
-template <int D, int ETA, typename Real, int VOL, typename GammaPtr>
+template <int D, int ETA, typename Real, int VOL, int Q, typename GammaPtr>
 __device__ __forceinline__ void run_tile(const PathParams &prm,
                                          const double *__restrict__ pts,
                                          GammaPtr gamma, const int i,
@@ -220,7 +220,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     constexpr int DP = D + 1;
     constexpr int C = num_channels(D);
     constexpr int Cs = pad16(C); // row stride of Gamma
-    using BS = Basis<DP, ETA>;
+    using BS = Basis<DP, ETA, Q>;
     constexpr int NP = BS::P;
     // d >= 5: the basis-row x Gamma contraction runs on the matrix cores
     constexpr bool kMfma = D >= 5;
@@ -569,14 +569,14 @@ constexpr int min_waves()
 
 // One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
 // writes its sums to partial[2 b].
-template <int D, int ETA, typename Real, int VOL>
+template <int D, int ETA, typename Real, int VOL, int Q>
 __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void path_kernel(
     const PathParams prm, const double *__restrict__ pts,
     const Real *__restrict__ gamma, double *__restrict__ partial)
 {
     const int i = blockIdx.x / prm.groups;
     const int g = blockIdx.x - i * prm.groups;
-    run_tile<D, ETA, Real, VOL>(prm, pts, gamma, i, g,
+    run_tile<D, ETA, Real, VOL, Q>(prm, pts, gamma, i, g,
                                 partial + 2 * (size_t)blockIdx.x);
 }
 
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void path_kern
 // atomic counter until none is left -- dynamic per-tile dispatch.  A tile
 // computes exactly what the one-problem kernel computes for the same
 // (i, g), so a problem's result does not depend on the batch.
-template <int D, int ETA, typename Real, int VOL>
+template <int D, int ETA, typename Real, int VOL, int Q>
 __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void batch_path_kernel(
     const BatchTileDesc *__restrict__ probs, int nprob,
     const long long *__restrict__ tile_begin, unsigned int *counter)
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void batch_pat
         const int i = (int)(local / q.prm.groups);
         const int g = (int)(local - (long long)i * q.prm.groups);
         using ConstReal = const __attribute__((address_space(4))) Real *;
-        run_tile<D, ETA, Real, VOL>(q.prm, q.pts, (ConstReal)q.gamma, i, g,
+        run_tile<D, ETA, Real, VOL, Q>(q.prm, q.pts, (ConstReal)q.gamma, i, g,
                                     q.partial + 2 * local);
     }
 }
@@ -650,12 +650,12 @@ hipError_t dispatch_variant(bool fp32, int vol, F &&f)
     return hipErrorInvalidValue;
 }
 
-template <int D, int E>
+template <int D, int E, int Q>
 int copy_index_table(int8_t *nu, int cap)
 {
     constexpr int DP = D + 1;
-    constexpr auto &t = Basis<DP, E>::tab;
-    constexpr int P = Basis<DP, E>::P;
+    constexpr auto &t = Basis<DP, E, Q>::tab;
+    constexpr int P = Basis<DP, E, Q>::P;
     if (nu && cap >= P)
         for (int l = 0; l < P; ++l)
             for (int v = 0; v < DP; ++v) nu[l * DP + v] = t.nu[l][v];
@@ -665,10 +665,11 @@ int copy_index_table(int8_t *nu, int cap)
 } // namespace bsde
 
 // Defines launch_path_dD, index_table_dD, launch_batch_dD,
-// batch_occupancy_dD and has_variant_dD for the (eta, FP64, Dupire) sets
-// listed by SETS(X) as X(E, FP64, DUP).
+// batch_occupancy_dD and has_variant_dD for the (eta, q-norm, FP64, Dupire)
+// sets listed by SETS(X) as X(E, Q, FP64, DUP), with q = Q / 10.
 #define BSDE_DEFINE_DIMENSION(D, SETS)                                         \
-    hipError_t launch_path_d##D(int eta, bool fp32, int blocks, hipStream_t s, \
+    hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,       \
+                                hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial)            \
     {                                                                          \
@@ -676,13 +677,14 @@ int copy_index_table(int8_t *nu, int cap)
         SETS(BSDE_PATH_SET)                                                    \
         return hipErrorInvalidValue;                                           \
     }                                                                          \
-    int index_table_d##D(int eta, int8_t *nu, int cap)                         \
+    int index_table_d##D(int eta, int q10, int8_t *nu, int cap)                \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         SETS(BSDE_TABLE_SET)                                                   \
         return 0;                                                              \
     }                                                                          \
-    hipError_t launch_batch_d##D(int eta, bool fp32, int vol, int blocks,      \
+    hipError_t launch_batch_d##D(int eta, int q10, bool fp32, int vol,         \
+                                 int blocks,                                   \
                                  hipStream_t s, const BatchTileDesc *probs,    \
                                  int nprob, const long long *tile_begin,       \
                                  unsigned int *counter)                        \
@@ -691,54 +693,55 @@ int copy_index_table(int8_t *nu, int cap)
         SETS(BSDE_BATCH_SET)                                                   \
         return hipErrorInvalidValue;                                           \
     }                                                                          \
-    int batch_occupancy_d##D(int eta, bool fp32, int vol)                      \
+    int batch_occupancy_d##D(int eta, int q10, bool fp32, int vol)             \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         int nb = 0;                                                            \
         SETS(BSDE_OCC_SET)                                                     \
         return nb;                                                             \
     }                                                                          \
-    bool has_variant_d##D(int eta, bool fp32, int vol)                         \
+    bool has_variant_d##D(int eta, int q10, bool fp32, int vol)                \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         SETS(BSDE_HAS_SET)                                                     \
         return false;                                                          \
     }
 
-#define BSDE_PATH_SET(E, F64, DUP)                                             \
-    if (eta == E)                                                              \
+#define BSDE_PATH_SET(E, Q, F64, DUP)                                          \
+    if (eta == E && q10 == Q)                                                  \
         return dispatch_variant<D_, E, F64, DUP>(                              \
             fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
                 using R = typename decltype(rt)::type;                         \
-                hipLaunchKernelGGL((path_kernel<D_, E, R, decltype(vt)::value>),\
+                hipLaunchKernelGGL(                                            \
+                    (path_kernel<D_, E, R, decltype(vt)::value, Q>),           \
                                    dim3(blocks), dim3(kBlock), 0, s, prm, pts, \
                                    (const R *)gamma, partial);                 \
                 return hipGetLastError();                                      \
             });
-#define BSDE_TABLE_SET(E, F64, DUP)                                            \
-    if (eta == E) return copy_index_table<D_, E>(nu, cap);
-#define BSDE_BATCH_SET(E, F64, DUP)                                            \
-    if (eta == E)                                                              \
+#define BSDE_TABLE_SET(E, Q, F64, DUP)                                         \
+    if (eta == E && q10 == Q) return copy_index_table<D_, E, Q>(nu, cap);
+#define BSDE_BATCH_SET(E, Q, F64, DUP)                                         \
+    if (eta == E && q10 == Q)                                                  \
         return dispatch_variant<D_, E, F64, DUP>(                              \
             fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
                 using R = typename decltype(rt)::type;                         \
                 hipLaunchKernelGGL(                                            \
-                    (batch_path_kernel<D_, E, R, decltype(vt)::value>),        \
+                    (batch_path_kernel<D_, E, R, decltype(vt)::value, Q>),     \
                     dim3(blocks), dim3(kBlock), 0, s, probs, nprob,            \
                     tile_begin, counter);                                      \
                 return hipGetLastError();                                      \
             });
-#define BSDE_OCC_SET(E, F64, DUP)                                              \
-    if (eta == E)                                                              \
+#define BSDE_OCC_SET(E, Q, F64, DUP)                                           \
+    if (eta == E && q10 == Q)                                                  \
         (void)dispatch_variant<D_, E, F64, DUP>(                               \
             fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
                 using R = typename decltype(rt)::type;                         \
                 return hipOccupancyMaxActiveBlocksPerMultiprocessor(           \
-                    &nb, batch_path_kernel<D_, E, R, decltype(vt)::value>,     \
+                    &nb, batch_path_kernel<D_, E, R, decltype(vt)::value, Q>,  \
                     kBlock, 0);                                                \
             });
-#define BSDE_HAS_SET(E, F64, DUP)                                              \
-    if (eta == E)                                                              \
+#define BSDE_HAS_SET(E, Q, F64, DUP)                                           \
+    if (eta == E && q10 == Q)                                                  \
         return dispatch_variant<D_, E, F64, DUP>(                              \
                    fp32, vol, [](auto, auto) { return hipSuccess; }) ==        \
                hipSuccess;

@@ -81,3 +81,14 @@ def test_black_scholes_american_put_basket_delta_d5():
     print("BS American put d=5: price %.4f; mean delta %.4f vs printed mean %.4f"
           % (m, dl.mean(), printed.mean()))
     assert abs(dl.mean() - printed.mean()) < 0.01
+
+
+def test_black_scholes_european_call_basket_d10():
+    # Section 6.2.1, European call basket d = 10 (Figure fig:call_euro_10):
+    # M = 30,000, eta = 5, q = 0.6; benchmark 7.0207, CI (7.0125, 7.0288)
+    cfg = problem(d=10, vol_level=0.2, rho=0.2, T=1.0, r=0.05, K=100.0,
+                  S0=100.0, payoff="call", omega=0.0, M=30000,
+                  **dict(BASE, eta=5, q=0.6))
+    m, s, _ = _mean_over_seeds(cfg)
+    print("BS European call d=10: %.4f (seed std %.4f) vs 7.0207" % (m, s))
+    assert abs(m - 7.0207) < 0.35

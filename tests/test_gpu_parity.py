@@ -71,8 +71,15 @@ CASES = {
                          rho=0.2, payoff="put_geom", S0=100.0, grid="random",
                          redraw=1, n_t=3, n_x=60, eta=2, M=100, N=4, K_it=3,
                          omega=1.0),
+    # the hyperbolic index set eta = 5, q = 0.6 (p = 221) of the paper's
+    # d = 10 runs, with a kernel of its own
+    "d10_hyperbolic": problem(d=10, vol_kind="bump",
+                              vol_level=[0.15 + 0.02 * j for j in range(10)],
+                              bump_a=0.25, rho=0.2, payoff="call", S0=100.0,
+                              grid="random", n_t=6, n_x=300, eta=5, q=0.6,
+                              M=16, N=3, K_it=2, omega=1.0),
 }
-FP32_ONLY = {"d10_eta2", "d10_eta3"}
+FP32_ONLY = {"d10_eta2", "d10_eta3", "d10_hyperbolic"}
 
 
 @pytest.fixture(scope="module")
@@ -255,3 +262,18 @@ def test_redraw_resumes_and_is_solve_only():
     with pytest.raises(BsdeError) as e:   # redraw needs a random grid
         Problem(dict(cfg, grid="tensor", n_x=6))
     assert e.value.status == 1
+
+
+def test_hyperbolic_index_set_kernel():
+    # q = 0.6 at d = 10, eta = 5 runs on a kernel of the hyperbolic set
+    # itself (p = 221, eq. hyper_set); d = 2, eta = 4, q = 0.6 has none and
+    # runs the total-degree kernel with the other coefficients held at zero
+    from paper_1102_4666_amd import Problem
+    with Problem(dict(CASES["d10_hyperbolic"], precision="fp32")) as P:
+        assert P.p == len(oracle.index_set(11, 5, 0.6)) == 221
+    cfg = problem(d=2, n_t=6, n_x=8, eta=4, q=0.6, M=64, N=4, K_it=2)
+    with Problem(cfg) as P:
+        assert P.p == 35                      # binom(3 + 4, 4)
+        P.solve()
+        alpha = P.coefficients()
+    assert np.count_nonzero(alpha) == len(oracle.index_set(3, 4, 0.6))

@@ -152,3 +152,23 @@ def test_fit_reproduces_polynomial_and_its_derivatives():
     assert ut == pytest.approx(-0.6 * s + x[0], rel=1e-9)
     np.testing.assert_allclose(ux, [2 * s + t, 4 * s], rtol=1e-9)
     np.testing.assert_allclose(uxx, [[2, 4], [4, 8]], rtol=1e-8)
+
+
+def test_uniform_points_cover_time_and_domain():
+    # Algorithm 1: n points uniform over [0, T] x D, redrawn per iteration
+    from scipy import stats
+    cfg = problem(d=3, vol_level=[0.2, 0.3, 0.25], grid="uniform", n_x=20000,
+                  T=2.0, redraw=1)
+    lo, hi = oracle.domain(cfg)
+    p0 = oracle.points(cfg, 0)
+    assert p0.shape == (20000, 4)
+    assert stats.kstest(p0[:, 0] / 2.0, "uniform").pvalue > 1e-3
+    for j in range(3):
+        u = (p0[:, 1 + j] - lo[j]) / (hi[j] - lo[j])
+        assert u.min() > 0 and u.max() < 1
+        assert stats.kstest(u, "uniform").pvalue > 1e-3
+    # coordinates of one point are independent draws
+    assert abs(np.corrcoef(p0[:, 0], p0[:, 1])[0, 1]) < 0.03
+    p1 = oracle.points(cfg, 1)
+    assert not np.array_equal(p0, p1)
+    np.testing.assert_array_equal(p0, oracle.points(dict(cfg, redraw=0), 5))

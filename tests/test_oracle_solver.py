@@ -149,3 +149,18 @@ def test_redraw_keeps_an_exact_solution_fixed():
     for k in range(1, 4):
         np.testing.assert_allclose(res["alpha"][k], a0, rtol=0, atol=1e-8)
     assert np.abs(res["c"]).max() < 1e-10
+
+
+def test_uniform_redrawn_points_follow_the_exact_expectation_map():
+    # the literal point draw of Algorithm 1: (t, x) uniform over [0, T] x D,
+    # new at every iteration; the Monte Carlo oracle tracks the exact
+    # projected map on the same point sets (4.5 x the standard deviation of
+    # the difference over 8 seeds)
+    cfg = problem(d=2, rho=0.3, vol_level=[0.2, 0.3], S0=[100.0, 100.0],
+                  payoff="put_geom", grid="uniform", redraw=1, n_x=240,
+                  eta=3, M=1000, N=1, K_it=3)
+    exact = refs.exact_picard_const_vol(cfg, lambda k: oracle.points(cfg, k), 3)
+    res = oracle.solve(cfg)
+    got = [_price(cfg, a)[0] for a in res["alpha"]]
+    for k, tol in zip([1, 2, 3], [0.28, 0.25, 0.11]):
+        assert abs(got[k] - exact[k]) < tol, (k, got[k], exact[k])
