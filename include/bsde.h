@@ -97,23 +97,27 @@ typedef enum {
     BSDE_GRID_TENSOR = 0, /* n_x equispaced nodes per asset (endpoints
                              included); spatial point b has base-n_x digits
                              b_j, asset 1 least significant               */
-    BSDE_GRID_RANDOM = 1  /* n_x points uniform in D from the counter-based
+    BSDE_GRID_RANDOM = 1, /* n_x points uniform in D from the counter-based
                              generator (substream 2): drawn once, or at
                              every Picard iteration with redraw            */
+    BSDE_GRID_UNIFORM = 2 /* n = n_x points (t, x) uniform over [0, T] x D,
+                             Algorithm 1's draw (substream 3; n_t unused),
+                             once or at every iteration with redraw        */
 } bsde_grid_kind;
 
 typedef struct {
     int kind;      /* bsde_grid_kind                                        */
-    int n_t;       /* time nodes, >= 2                                      */
-    int n_x;       /* tensor: nodes per asset; random: spatial points       */
+    int n_t;       /* time nodes, >= 2 (tensor and random kinds)            */
+    int n_x;       /* tensor: nodes per asset; random: spatial points;
+                      uniform: points                                      */
     double width;  /* half-width of D in units of level_j sqrt(T), > 0      */
     int eta;       /* maximal total degree of the polynomial basis          */
     double q;      /* hyperbolic index set parameter in (0, 1]; 1 = total
                       degree                                               */
-    int redraw;    /* 1: random grid only -- new spatial points at every
-                      Picard iteration k (Algorithm 1 draws new points each
-                      iteration; counter word 2 = k, iteration 0 = the
-                      fixed grid), the least-squares factorisation redone
+    int redraw;    /* 1: random or uniform points only -- new points at
+                      every Picard iteration k (Algorithm 1 draws new points
+                      each iteration; counter word 2 = k, iteration 0 = the
+                      fixed set), the least-squares factorisation redone
                       on the device for each; bsde_solve only (the batched
                       entry points and the server return
                       BSDE_EUNSUPPORTED).  0: one fixed grid.             */

@@ -312,7 +312,8 @@ void setup_stream_put(hipStream_t s)
 }
 } // namespace
 
-// The points of Picard iteration k, time-major (point i = a n_spatial + b):
+// The points of Picard iteration k.  Uniform kind: n points uniform over
+// [0, T] x D.  Otherwise time-major (point i = a n_spatial + b):
 // time nodes a T / (n_t - 1); tensor grid digits equispaced in [-1, 1]; or
 // Philox-uniform spatial points from the counter (b, 0, k', 2 << 24 |
 // block) with k' = k when the points are redrawn every iteration, else 0.
@@ -321,8 +322,23 @@ static void make_points(const bsde_problem_s *h, int k, std::vector<double> &pts
     const int d = h->d, dp = d + 1;
     const long ns = h->n_spatial;
     const uint64_t seed = h->base.seed;
-    const uint32_t kdraw = (h->redraw && h->grid_kind == BSDE_GRID_RANDOM) ? (uint32_t)k : 0u;
+    const uint32_t kdraw = (h->redraw && h->grid_kind != BSDE_GRID_TENSOR) ? (uint32_t)k : 0u;
     pts.resize((size_t)h->n * dp);
+    if (h->grid_kind == BSDE_GRID_UNIFORM) {
+        // point i: word q of the counter (i, 0, k', 3 << 24 | q / 4) gives
+        // t (q = 0) and x_j (q = 1 + j), uniform on [0, T] and [lo_j, hi_j]
+        for (int i = 0; i < h->n; ++i) {
+            double *row = &pts[(size_t)i * dp];
+            for (int q = 0; q <= d; ++q) {
+                u32x4 w = philox10((uint32_t)i, 0, kdraw, (3u << 24) | (uint32_t)(q / 4),
+                                   (uint32_t)seed, (uint32_t)(seed >> 32));
+                uint32_t word = q % 4 == 0 ? w.x : q % 4 == 1 ? w.y : q % 4 == 2 ? w.z : w.w;
+                const double u = ((double)word + 0.5) * 0x1p-32;
+                row[q] = q == 0 ? h->base.T * u : h->lo[q - 1] + u * (h->hi[q - 1] - h->lo[q - 1]);
+            }
+        }
+        return;
+    }
     for (int a = 0; a < h->n_t; ++a) {
         double t = a * h->base.T / (h->n_t - 1);
         for (long s = 0; s < ns; ++s) {
@@ -589,11 +605,13 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EINVAL, "bad volatility kind");
     if (sigma->kind == BSDE_VOL_BUMP && !(sigma->bump_c > 0.0))
         return fail(BSDE_EINVAL, "bump centre must be > 0");
-    if (grid->kind != BSDE_GRID_TENSOR && grid->kind != BSDE_GRID_RANDOM)
+    if (grid->kind != BSDE_GRID_TENSOR && grid->kind != BSDE_GRID_RANDOM &&
+        grid->kind != BSDE_GRID_UNIFORM)
         return fail(BSDE_EINVAL, "bad grid kind");
-    if (grid->redraw != 0 && (grid->redraw != 1 || grid->kind != BSDE_GRID_RANDOM))
-        return fail(BSDE_EINVAL, "redraw needs a random grid");
-    if (grid->n_t < 2 || grid->n_x < 1 || !(grid->width > 0.0) ||
+    if (grid->redraw != 0 && (grid->redraw != 1 || grid->kind == BSDE_GRID_TENSOR))
+        return fail(BSDE_EINVAL, "redraw needs random or uniform points");
+    if ((grid->kind != BSDE_GRID_UNIFORM && grid->n_t < 2) || grid->n_x < 1 ||
+        !(grid->width > 0.0) ||
         grid->eta < 1 || !(grid->q > 0.0 && grid->q <= 1.0))
         return fail(BSDE_EINVAL, "bad grid (n_t >= 2, n_x >= 1, width > 0, "
                                  "eta >= 1, 0 < q <= 1)");
@@ -688,14 +706,16 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     } else {
         ns = grid->n_x;
     }
-    if ((long)ns * grid->n_t > (1L << 26)) {
+    // uniform points: n_x of them, no time nodes
+    const int n_t = grid->kind == BSDE_GRID_UNIFORM ? 1 : grid->n_t;
+    if ((long)ns * n_t > (1L << 26)) {
         delete h;
         return fail(BSDE_EINVAL, "too many points");
     }
     h->n_spatial = (int)ns;
-    h->n = (int)(ns * grid->n_t);
+    h->n = (int)(ns * n_t);
     h->grid_kind = grid->kind;
-    h->n_t = grid->n_t;
+    h->n_t = n_t;
     h->n_x = grid->n_x;
     h->redraw = grid->redraw;
     h->pts_k = 0;
@@ -1163,7 +1183,7 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
         for (int j = 0; j < d; ++j) ns *= (size_t)grid->n_x;
     else
         ns = (size_t)grid->n_x;
-    const size_t n = ns * (size_t)grid->n_t;
+    const size_t n = ns * (size_t)(grid->kind == BSDE_GRID_UNIFORM ? 1 : grid->n_t);
     const size_t C = (size_t)num_channels(d);
     bsde_problem_s tmp;
     tmp.n = (int)n;

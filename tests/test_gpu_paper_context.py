@@ -3,8 +3,8 @@ as context checks of the method at the paper's scale -- not parity: the
 paper's benchmarks come from other Monte Carlo methods, and its figures
 carry their own noise.
 
-Set-up as printed in Section 6: n = 1000 points redrawn at every
-iteration (Algorithm 1; here 10 time nodes x 100 uniform spatial points),
+Set-up as printed in Section 6: n = 1000 points (t, x) uniform over
+[0, T] x D, redrawn at every iteration (Algorithm 1),
 eta = 3, q = 1, M = 50,000 (Black-Scholes European put basket, T = 3),
 M = 30,000 and N = 10 (Dupire-type volatility of eq. vol_locale), M = 5000
 (Black-Scholes American put basket, 5 iterations).  The domain half-width
@@ -23,7 +23,7 @@ from workloads import problem
 
 pytestmark = pytest.mark.gpu
 
-BASE = dict(grid="random", redraw=1, n_t=10, n_x=100, eta=3, N=10, K_it=10,
+BASE = dict(grid="uniform", redraw=1, n_x=1000, eta=3, N=10, K_it=10,
             width=1.0, precision="fp32")
 
 

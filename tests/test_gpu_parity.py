@@ -51,6 +51,17 @@ CASES = {
     "d10_eta3": problem(d=10, vol_level=0.2, rho=0.3, payoff="call_geom",
                         S0=100.0, grid="random", n_t=4, n_x=300, eta=3,
                         M=16, N=3, K_it=2),
+    # points (t, x) uniform over [0, T] x D, fixed and redrawn
+    "d2_uniform": problem(d=2, vol_kind="bump", vol_level=[0.2, 0.3],
+                          bump_a=0.25, rho=0.3, S0=[100.0, 100.0],
+                          grid="uniform", n_x=150, eta=3, M=260, N=6,
+                          K_it=2, omega=1.0),
+    "d5_uniform_redraw": problem(d=5, vol_kind="bump",
+                                 vol_level=[0.15, 0.2, 0.25, 0.3, 0.35],
+                                 bump_a=0.25, rho=0.2, payoff="put",
+                                 S0=100.0, grid="uniform", redraw=1,
+                                 n_x=300, eta=3, M=100, N=4, K_it=3,
+                                 omega=1.0),
     # the Dupire-type local volatility of eq. vol_locale (time-dependent)
     "d1_dupire": problem(d=1, vol_kind="dupire", vol_level=0.3, n_t=6,
                          n_x=20, eta=4, M=300, N=10, K_it=3, omega=1.0),
