@@ -217,6 +217,35 @@ __host__ __device__ constexpr int num_channels(int d)
 // zero outside p x C, so that 16 x 16 matrix-core tiles read it in bounds
 __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 
+__host__ __device__ constexpr int pad32(int x) { return (x + 31) & ~31; }
+
+// FP32-path problems that contract on the matrix cores (d >= 5) keep, after
+// the FP32 channel table (pad16(p) x pad16(C) floats), the per-channel
+// power-of-two factors unscale[pad16(C)] and the table split into two FP16
+// parts, Gamma_c * scale_c = hi + lo, each laid out [C tile][16 channels]
+// [pad32(p) basis functions] so that a lane reads 8 consecutive basis
+// functions of one channel; all padding is zero.
+__host__ __device__ constexpr bool split_contraction(int d, bool fp32)
+{
+    return fp32 && d >= 5;
+}
+__host__ __device__ constexpr size_t split_unscale_off(int p, int C) // floats
+{
+    return (size_t)pad16(p) * pad16(C);
+}
+__host__ __device__ constexpr size_t split_hi_off(int p, int C) // floats
+{
+    return split_unscale_off(p, C) + pad16(C);
+}
+__host__ __device__ constexpr size_t split_part_halves(int p, int C)
+{
+    return (size_t)pad16(C) * pad32(p);
+}
+__host__ __device__ constexpr size_t split_table_floats(int p, int C)
+{
+    return split_hi_off(p, C) + split_part_halves(p, C); // two parts of halves
+}
+
 // channel 2 + d + idx holds d^2 u / dx_j dx_k for the idx-th pair j <= k
 // (row-major upper triangle)
 __host__ __device__ constexpr int hess_j(int d, int idx)
@@ -344,7 +373,8 @@ struct BatchUpdateDesc {
     double *alpha_out;
     const double *Dmat;    // (C-1) x p x p
     double *g64;
-    float *g32;
+    float *g32;            // FP32 table (+ the split FP16 parts if split)
+    int split;             // split_contraction(d, fp32)
 };
 
 } // namespace bsde

@@ -36,9 +36,10 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
                          const double *Dmat, double *g64, float *g32,
-                         hipEvent_t *ev);
+                         int split, hipEvent_t *ev);
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
-                           const double *Dmat, double *g64, float *g32);
+                           const double *Dmat, double *g64, float *g32,
+                           int split);
 hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter);
@@ -506,6 +507,17 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
     return BSDE_OK;
 }
 
+// the FP32 channel table, with the split FP16 parts when the path kernel
+// contracts on the matrix cores
+static int split_of(const bsde_problem_s *h)
+{
+    return split_contraction(h->d, h->precision == BSDE_FP32_PATHS) ? 1 : 0;
+}
+static size_t g32_floats(const bsde_problem_s *h)
+{
+    return split_of(h) ? split_table_floats(h->p, h->C) : (size_t)pad16(h->p) * pad16(h->C);
+}
+
 static void free_device(bsde_problem_s *h)
 {
     pool_free(h->d_pts);
@@ -786,7 +798,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
               dalloc((void **)&h->d_alpha, sizeof(double) * (size_t)(h->K_it + 1) * h->p) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
               dalloc((void **)&h->d_g64, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C)) &&
-              dalloc((void **)&h->d_g32, sizeof(float) * (size_t)pad16(h->p) * pad16(h->C)) &&
+              dalloc((void **)&h->d_g32, sizeof(float) * g32_floats(h)) &&
               dalloc((void **)&h->d_c, sizeof(double) * (size_t)h->K_it * h->n) &&
               dalloc((void **)&h->d_var, sizeof(double) * (size_t)h->K_it * h->n);
     if (!ok) {
@@ -802,7 +814,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     // the padding of the channel tables stays zero (the update kernels
     // write only the p x C entries)
     if (e == hipSuccess) e = hipMemset(h->d_g64, 0, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C));
-    if (e == hipSuccess) e = hipMemset(h->d_g32, 0, sizeof(float) * (size_t)pad16(h->p) * pad16(h->C));
+    if (e == hipSuccess) e = hipMemset(h->d_g32, 0, sizeof(float) * g32_floats(h));
     if (e != hipSuccess) {
         free_device(h);
         delete h;
@@ -881,7 +893,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     HIP_TRY(hipEventRecord(ev[0], s));
     // channel table of the starting coefficients
     HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                            h->d_D, h->d_g64, h->d_g32));
+                            h->d_D, h->d_g64, h->d_g32, split_of(h)));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
         hipEvent_t *e = &ev[2 + 5 * (size_t)it];
@@ -914,7 +926,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
                               h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
-                              h->d_g32, e + 2)); // records e[2], e[3], e[4]
+                              h->d_g32, split_of(h), e + 2)); // records e[2..4]
     }
     HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipEventSynchronize(ev[1]));
@@ -996,6 +1008,7 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
     u.Dmat = h->d_D;
     u.g64 = h->d_g64;
     u.g32 = h->d_g32;
+    u.split = split_of(h);
     return u;
 }
 } // namespace
@@ -1193,7 +1206,9 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
     const size_t sizes[] = {n * (d + 1) * 8, (size_t)p * n * 8, (C - 1) * p * p * 8,
                             (size_t)(K_it + 1) * p * 8, (size_t)p * 8,
                             (size_t)pad16(p) * pad16((int)C) * 8,
-                            (size_t)pad16(p) * pad16((int)C) * 4, (size_t)K_it * n * 8,
+                            (d >= 5 ? split_table_floats(p, (int)C)
+                                    : (size_t)pad16(p) * pad16((int)C)) * 4,
+                            (size_t)K_it * n * 8,
                             (size_t)K_it * n * 8,
                             n * groups * 16};
     size_t total = 0;
@@ -1257,7 +1272,7 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
     }
     const int k = std::min(h->k_done, h->K_it - 1);
     HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                            h->d_D, h->d_g64, h->d_g32));
+                            h->d_D, h->d_g64, h->d_g32, split_of(h)));
     hipEvent_t e0, e1;
     HIP_TRY(event_get(&e0));
     HIP_TRY(event_get(&e1));

@@ -67,32 +67,67 @@ __global__ __launch_bounds__(256) void project_kernel(
 constexpr int kMaxP = 512;
 
 // channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with a = alpha_in + beta
-// (channel 0 is the identity and also stores a as the next coefficients)
+// (channel 0 is the identity and also stores a as the next coefficients).
+// With split set, also the FP16 parts of the FP32 table (layout in
+// bsde_common.h): Gamma_lc scale_c = hi + lo with scale_c = 2^-e, e the
+// binary exponent of max_l |Gamma_lc| (so the scaled column lies in
+// (-1, 1)), and unscale_c = 2^e.
 __device__ __forceinline__ void channel_col(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
     double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, int c, double *__restrict__ g64, float *__restrict__ g32)
+    int C, int c, double *__restrict__ g64, float *__restrict__ g32,
+    int split)
 {
     __shared__ double a[kMaxP];
+    __shared__ float red[256 / 64];
     const int Cs = pad16(C); // row stride of the channel table
     for (int m = threadIdx.x; m < p; m += 256)
         a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
     __syncthreads();
-    if (c == 0) {
-        for (int l = threadIdx.x; l < p; l += 256) {
-            if (alpha_out) alpha_out[l] = a[l];
-            g64[(size_t)l * Cs] = a[l];
-            g32[(size_t)l * Cs] = (float)a[l];
+    // this thread's entries l = threadIdx.x + 256 j (p <= kMaxP = 512)
+    float mine[kMaxP / 256];
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxP / 256; ++j) {
+        const int l = threadIdx.x + 256 * j;
+        mine[j] = 0.0f;
+        if (l >= p) continue;
+        double v;
+        if (c == 0) {
+            v = a[l];
+            if (alpha_out) alpha_out[l] = v;
+        } else {
+            const double *drow = Dmat + ((size_t)(c - 1) * p + l) * p;
+            v = 0.0;
+            for (int m = 0; m < p; ++m) v += drow[m] * a[m];
         }
-        return;
+        g64[(size_t)l * Cs + c] = v;
+        g32[(size_t)l * Cs + c] = (float)v;
+        mine[j] = (float)v;
+        amax = fmaxf(amax, fabsf((float)v));
     }
-    const double *Dc = Dmat + (size_t)(c - 1) * p * p;
-    for (int l = threadIdx.x; l < p; l += 256) {
-        const double *drow = Dc + (size_t)l * p;
-        double s = 0.0;
-        for (int m = 0; m < p; ++m) s += drow[m] * a[m];
-        g64[(size_t)l * Cs + c] = s;
-        g32[(size_t)l * Cs + c] = (float)s;
+    if (!split) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    const int e = amax > 0.0f ? __builtin_amdgcn_frexp_expf(amax) : 0;
+    const float scale = __builtin_amdgcn_ldexpf(1.0f, -e);
+    float *unscale = g32 + split_unscale_off(p, C);
+    if (threadIdx.x == 0) unscale[c] = __builtin_amdgcn_ldexpf(1.0f, e);
+    _Float16 *hi = (_Float16 *)(g32 + split_hi_off(p, C));
+    _Float16 *lo = hi + split_part_halves(p, C);
+    const int K32 = pad32(p);
+    const size_t col = (size_t)c * K32; // [c / 16][c % 16][l] = c K32 + l
+#pragma unroll
+    for (int j = 0; j < kMaxP / 256; ++j) {
+        const int l = threadIdx.x + 256 * j;
+        if (l >= p) continue;
+        const float v = mine[j] * scale;
+        const _Float16 h = (_Float16)v;
+        hi[col + l] = h;
+        lo[col + l] = (_Float16)(v - (float)h);
     }
 }
 
@@ -100,9 +135,10 @@ __device__ __forceinline__ void channel_col(
 __global__ __launch_bounds__(256) void channel_kernel(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
     double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, double *__restrict__ g64, float *__restrict__ g32)
+    int C, double *__restrict__ g64, float *__restrict__ g32, int split)
 {
-    channel_col(alpha_in, beta, alpha_out, Dmat, p, C, blockIdx.x, g64, g32);
+    channel_col(alpha_in, beta, alpha_out, Dmat, p, C, blockIdx.x, g64, g32,
+                split);
 }
 
 // ---------------------------------------------------------------------------
@@ -130,7 +166,7 @@ __global__ __launch_bounds__(256) void batch_channel_kernel(
     if ((int)blockIdx.x < q.C)
         channel_col(q.alpha_in, with_beta ? q.beta : nullptr,
                     with_beta ? q.alpha_out : nullptr, q.Dmat, q.p, q.C,
-                    blockIdx.x, q.g64, q.g32);
+                    blockIdx.x, q.g64, q.g32, q.split);
 }
 
 __global__ void reset_counters_kernel(unsigned int *c, int n)
@@ -249,7 +285,7 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
                          const double *Dmat, double *g64, float *g32,
-                         hipEvent_t *ev /* 3 events or NULL */)
+                         int split, hipEvent_t *ev /* 3 events or NULL */)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0,
                        s, partial, n, groups, M, c, var);
@@ -258,17 +294,18 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                        beta);
     if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha_in,
-                       beta, alpha_out, Dmat, p, C, g64, g32);
+                       beta, alpha_out, Dmat, p, C, g64, g32, split);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
-                           const double *Dmat, double *g64, float *g32)
+                           const double *Dmat, double *g64, float *g32,
+                           int split)
 {
     hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha,
                        (const double *)nullptr, (double *)nullptr, Dmat, p,
-                       C, g64, g32);
+                       C, g64, g32, split);
     return hipGetLastError();
 }
 

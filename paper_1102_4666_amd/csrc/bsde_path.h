@@ -441,83 +441,226 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             terminal = payoff<D>(prm.payoff, K, X) - uT;
             asm volatile("" : "+v"(terminal));
             __builtin_amdgcn_sched_barrier(0);
-            // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave: the
-            // basis row goes through LDS in chunks of 16 functions into the
-            // A operand; Gamma tiles are the B operand; 4 x NT accumulators
+            // fold of channel c of V (this lane's path) into u and the
+            // frozen generator
+            auto fold = [&](auto cc, Real vc) {
+                constexpr int c = decltype(cc)::value;
+                if constexpr (c == 0) {
+                    u = vc;
+                } else if constexpr (c == 1) {
+                    gen += vc;
+                } else if constexpr (c < 2 + D) {
+                    gen += bst[c - 2] * vc;
+                } else {
+                    constexpr int j = hess_j(D, c - 2 - D);
+                    constexpr int k = hess_k(D, c - 2 - D);
+                    const Real cov = (j == k) ? Real(0.5) * sgs[j] * sgs[j]
+                                              : rho * sgs[j] * sgs[k];
+                    gen += cov * vc;
+                }
+            };
             constexpr int NT = Cs / 16;
-            constexpr int NCH = pad16(NP) / 16;
-            using Acc = typename Mfma<Real>::acc_t;
-            __shared__ Real lds[kBlock / 64][64 * 17];
-            Real *buf = lds[threadIdx.x >> 6];
             const int lane = threadIdx.x & 63;
-            Acc acc[4][NT];
+            if constexpr (std::is_same<Real, float>::value) {
+                // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave on
+                // v_mfma_f32_16x16x32_f16 with both operands split into two
+                // FP16 parts, B = Bh + Bl and Gamma s_c = Gh + Gl, and
+                // V = Bh Gh + Bh Gl + Bl Gh accumulated in FP32 (the dropped
+                // Bl Gl is 2^-22 of the product).  The row is scaled by a
+                // power of two 2^-e so that |B_l| <= 1 for every path
+                // (|B_l| is at most the product of the MAXV largest
+                // max(1, |T_eta(z_v)|), Chebyshev values growing with the
+                // degree outside [-1, 1]); the column scales s_c come with
+                // the table.  Chunks of 32 basis functions go through the
+                // wave's LDS rows ([path][function], 8 functions per 16-byte
+                // access) into the A operand; the table parts, laid out
+                // [channel][function], are the B operand.  A and B agree on
+                // which basis function sits in each K slot of a lane.
+                typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+                constexpr int MAXV = [] {
+                    int m = 0;
+                    for (int l = 0; l < NP; ++l) {
+                        int c = 0;
+                        for (int v = 0; v < DP; ++v) c += BS::tab.nu[l][v] > 0;
+                        m = c > m ? c : m;
+                    }
+                    return m;
+                }();
+                constexpr int K32 = pad32(NP);
+                constexpr int NCH = K32 / 32;
+                constexpr int kRow = 40; // halves per LDS row (32 + padding)
+                float top[MAXV];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+                for (int i = 0; i < MAXV; ++i) top[i] = 1.0f;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
-            static_for<NCH>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                __builtin_amdgcn_sched_barrier(0);
-                static_for<16>([&](auto jc) {
-                    constexpr int jj = decltype(jc)::value;
-                    constexpr int l = q * 16 + jj;
-                    Real v = Real(0);
-                    if constexpr (l < NP)
-                        v = basis(std::integral_constant<int, l>{}, Tz);
-                    buf[jj * 64 + lane] = v; // [function][path]
-                });
-                wave_lds_sync();
-                const auto gq = opaque(q * 16 * Cs);
+                for (int v = 0; v < DP; ++v) {
+                    float x = fabsf(Tz[v][ETA]);
 #pragma unroll
-                for (int kb = 0; kb < 4; ++kb) {
-                    const int lrow = kb * 4 + (lane >> 4);
-                    Real bop[NT];
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        bop[nt] = gq[lrow * Cs + nt * 16 + (lane & 15)];
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt) {
-                        const Real aop = buf[lrow * 64 + mt * 16 + (lane & 15)];
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[mt][nt] = Mfma<Real>::mma(aop, bop[nt], acc[mt][nt]);
+                    for (int i = 0; i < MAXV; ++i) {
+                        const float hi = fmaxf(top[i], x);
+                        x = fminf(top[i], x);
+                        top[i] = hi;
                     }
                 }
-                wave_lds_sync();
-            });
-            // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
-            // 16 nt + col]; back through LDS so that each lane reads its own
-            // path's channels and folds them into u and the generator
-            static_for<NT>([&](auto ntc) {
-                constexpr int nt = decltype(ntc)::value;
+                float bound = top[0];
+#pragma unroll
+                for (int i = 1; i < MAXV; ++i) bound *= top[i];
+                const int rexp = bound > 1.0f ? __builtin_amdgcn_frexp_expf(bound) : 0;
+                const float rscale = __builtin_amdgcn_ldexpf(1.0f, -rexp);
+                __shared__ __attribute__((aligned(16))) _Float16
+                    ldsh[kBlock / 64][2][64 * kRow];
+                _Float16 *rowh = ldsh[threadIdx.x >> 6][0];
+                _Float16 *rowl = ldsh[threadIdx.x >> 6][1];
+                using Acc = typename Mfma<float>::acc_t;
+                Acc acc[4][NT];
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        buf[(16 * mt + Mfma<Real>::row(lane, e)) * 17 + (lane & 15)] =
-                            acc[mt][nt][e];
-                wave_lds_sync();
-                static_for<16>([&](auto cc) {
-                    constexpr int c = nt * 16 + decltype(cc)::value;
-                    if constexpr (c < C) {
-                        const Real vc = buf[lane * 17 + decltype(cc)::value];
-                        if constexpr (c == 0) {
-                            u = vc;
-                        } else if constexpr (c == 1) {
-                            gen += vc;
-                        } else if constexpr (c < 2 + D) {
-                            gen += bst[c - 2] * vc;
-                        } else {
-                            constexpr int j = hess_j(D, c - 2 - D);
-                            constexpr int k = hess_k(D, c - 2 - D);
-                            const Real cov = (j == k) ? Real(0.5) * sgs[j] * sgs[j]
-                                                      : rho * sgs[j] * sgs[k];
-                            gen += cov * vc;
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
+                auto opaque_h = [&](size_t offset) {
+                    uint64_t a = (uint64_t)(uintptr_t)((const _Float16 *)&gamma[split_hi_off(NP, C)] + offset);
+                    asm volatile("" : "+s"(a));
+                    return (const __attribute__((address_space(1))) _Float16 *)a;
+                };
+                static_for<NCH>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    __builtin_amdgcn_sched_barrier(0);
+                    static_for<4>([&](auto gc) {
+                        constexpr int g = decltype(gc)::value;
+                        __builtin_amdgcn_sched_barrier(0);
+                        h8 vh, vl;
+                        static_for<8>([&](auto ic) {
+                            constexpr int i8 = decltype(ic)::value;
+                            constexpr int l = q * 32 + g * 8 + i8;
+                            float v = 0.0f;
+                            if constexpr (l < NP)
+                                v = rscale * basis(std::integral_constant<int, l>{}, Tz);
+                            const _Float16 h = (_Float16)v;
+                            vh[i8] = h;
+                            vl[i8] = (_Float16)(v - (float)h);
+                        });
+                        *(h8 *)&rowh[lane * kRow + g * 8] = vh;
+                        *(h8 *)&rowl[lane * kRow + g * 8] = vl;
+                    });
+                    wave_lds_sync();
+                    // Bh (Gh + Gl) first, then Bl Gh: only one A part is
+                    // live at a time
+                    const auto gh = opaque_h((size_t)q * 32);
+                    static_for<2>([&](auto pc) {
+                        constexpr int part = decltype(pc)::value;
+                        const _Float16 *rows = part == 0 ? rowh : rowl;
+                        h8 a[4];
+#pragma unroll
+                        for (int mt = 0; mt < 4; ++mt)
+                            a[mt] = *(const h8 *)&rows[(mt * 16 + (lane & 15)) * kRow + 8 * (lane >> 4)];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const size_t off = (size_t)(nt * 16 + (lane & 15)) * K32 + 8 * (lane >> 4);
+                            const h8 bh = *(const __attribute__((address_space(1))) h8 *)&gh[off];
+#pragma unroll
+                            for (int mt = 0; mt < 4; ++mt)
+                                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mt], bh, acc[mt][nt], 0, 0, 0);
+                            if constexpr (part == 0) {
+                                const h8 bl = *(const __attribute__((address_space(1))) h8 *)&gh[split_part_halves(NP, C) + off];
+#pragma unroll
+                                for (int mt = 0; mt < 4; ++mt)
+                                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mt], bl, acc[mt][nt], 0, 0, 0);
+                            }
+                        }
+                    });
+                    wave_lds_sync();
+                });
+                // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
+                // 16 nt + col]; back through LDS so that each lane reads its
+                // own path's channels, undoes the column scales and folds
+                float *buf = (float *)rowh;
+                static_for<NT>([&](auto ntc) {
+                    constexpr int nt = decltype(ntc)::value;
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            buf[(16 * mt + Mfma<float>::row(lane, e)) * 17 + (lane & 15)] =
+                                acc[mt][nt][e];
+                    wave_lds_sync();
+                    __builtin_amdgcn_sched_barrier(0);
+                    const auto us = opaque(split_unscale_off(NP, C) + nt * 16);
+                    static_for<16>([&](auto cc) {
+                        constexpr int c = nt * 16 + decltype(cc)::value;
+                        if constexpr (c < C)
+                            fold(std::integral_constant<int, c>{},
+                                 buf[lane * 17 + decltype(cc)::value] * us[decltype(cc)::value]);
+                    });
+                    wave_lds_sync();
+                });
+                // undo the row scale
+                const float runscale = __builtin_amdgcn_ldexpf(1.0f, rexp);
+                u *= runscale;
+                gen *= runscale;
+            } else {
+                // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave: the
+                // basis row goes through LDS in chunks of 16 functions into the
+                // A operand; Gamma tiles are the B operand; 4 x NT accumulators
+                constexpr int NCH = pad16(NP) / 16;
+                using Acc = typename Mfma<Real>::acc_t;
+                __shared__ Real lds[kBlock / 64][64 * 17];
+                Real *buf = lds[threadIdx.x >> 6];
+                Acc acc[4][NT];
+    #pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+    #pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
+                static_for<NCH>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    __builtin_amdgcn_sched_barrier(0);
+                    static_for<16>([&](auto jc) {
+                        constexpr int jj = decltype(jc)::value;
+                        constexpr int l = q * 16 + jj;
+                        Real v = Real(0);
+                        if constexpr (l < NP)
+                            v = basis(std::integral_constant<int, l>{}, Tz);
+                        buf[jj * 64 + lane] = v; // [function][path]
+                    });
+                    wave_lds_sync();
+                    const auto gq = opaque(q * 16 * Cs);
+    #pragma unroll
+                    for (int kb = 0; kb < 4; ++kb) {
+                        const int lrow = kb * 4 + (lane >> 4);
+                        Real bop[NT];
+    #pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            bop[nt] = gq[lrow * Cs + nt * 16 + (lane & 15)];
+    #pragma unroll
+                        for (int mt = 0; mt < 4; ++mt) {
+                            const Real aop = buf[lrow * 64 + mt * 16 + (lane & 15)];
+    #pragma unroll
+                            for (int nt = 0; nt < NT; ++nt)
+                                acc[mt][nt] = Mfma<Real>::mma(aop, bop[nt], acc[mt][nt]);
                         }
                     }
+                    wave_lds_sync();
                 });
-                wave_lds_sync();
-            });
+                // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
+                // 16 nt + col]; back through LDS so that each lane reads its own
+                // path's channels and folds them into u and the generator
+                static_for<NT>([&](auto ntc) {
+                    constexpr int nt = decltype(ntc)::value;
+    #pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            buf[(16 * mt + Mfma<Real>::row(lane, e)) * 17 + (lane & 15)] =
+                                acc[mt][nt][e];
+                    wave_lds_sync();
+                    static_for<16>([&](auto cc) {
+                        constexpr int c = nt * 16 + decltype(cc)::value;
+                        if constexpr (c < C)
+                            fold(std::integral_constant<int, c>{},
+                                 buf[lane * 17 + decltype(cc)::value]);
+                    });
+                    wave_lds_sync();
+                });
+            }
         }
 
         // penalised driver f = -r u + omega (Phi - u)_+ and the path term
