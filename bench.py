@@ -37,10 +37,10 @@ FP64_VECTOR_PEAK = 78.6e12
 # tiling (workgroups per point), scaled by the plain-copy calibration
 # factors (x2.0 and x1.0).  The autotuner picks the tiling at run time;
 # a tiling missing here reports null.
-TRAFFIC_KIB = {"fp32": {1: (185, 64), 2: (313, 128), 4: (313, 256),
-                        8: (313, 512), 16: (315, 1024)},
-               "fp64": {1: (269, 64), 2: (397, 128), 4: (397, 256),
-                        8: (397, 512), 16: (399, 1024)}}
+TRAFFIC_KIB = {"fp32": {1: (179, 64), 2: (307, 128), 4: (307, 256),
+                        8: (307, 512), 16: (309, 1024)},
+               "fp64": {1: (270, 64), 2: (398, 128), 4: (398, 256),
+                        8: (398, 512), 16: (400, 1024)}}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -62,9 +62,9 @@ def traffic_bytes(precision, groups):
 # (FMA = 2, transcendental = 1): Box-Muller 5.5 + local vol 6 + Euler 5 +
 # per-path work 250 / N.  FP64 paths use software transcendentals with no
 # independent operation count: their figure is the measured SQ_INSTS_VALU
-# minus SQ_INSTS_VALU_TRANS_F64 per path-step (213.3 - 2.7).
+# minus SQ_INSTS_VALU_TRANS_F64 per path-step (213.6 - 2.7).
 OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.5 + 5 + 3 + 3 + 270 / 50.0 - 3.12,
-                     "fp64": 210.6}
+                     "fp64": 210.9}
 FP32_FLOP_PER_PATH_STEP = 5.5 + 6 + 5 + 250 / 50.0
 
 
