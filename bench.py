@@ -70,7 +70,7 @@ FP32_FLOP_PER_PATH_STEP = 5.5 + 6 + 5 + 250 / 50.0
 
 def workload(precision: str, omega: float = 100.0):
     import workloads
-    return workloads.config2(omega=omega, precision=precision)
+    return workloads.amer_put_d1(omega=omega, precision=precision)
 
 
 def run_job(cfg, stream, phases=None):
@@ -98,7 +98,7 @@ def accuracy(precision: str, stream):
     """Error against the stored FP64 oracle results of the same workload."""
     out = {}
     for omega in (100.0, 1.0):
-        name = "config2_w100" if omega == 100.0 else "config2_w1"
+        name = "amer_put_d1_w100" if omega == 100.0 else "amer_put_d1_w1"
         path = os.path.join(ROOT, "tests", "golden", name + ".json")
         if not os.path.exists(path):
             continue
@@ -127,7 +127,7 @@ def batched_vs_fp64(stream, reps: int = 2):
 
     import paper_1102_4666_amd as bsde
     import workloads
-    names = ("config2", "config3", "config4")
+    names = ("amer_put_d1", "amer_basket_d2", "geo_basket_d5")
     gold = {}
     for nm in names:
         path = os.path.join(ROOT, "tests", "golden", nm + "_w100.json")
@@ -270,8 +270,8 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
 def single_launches(names):
     """One Picard iteration (one path-kernel launch) of each named workload,
     FP32 paths, default tiling: the runs behind the profiles of the
-    matrix-core kernels.  Names: config2, config3, config4, d10-serving (the
-    d=10 request shape of the serving mix at M=500)."""
+    matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
+    d10-serving (the d=10 request shape of the serving mix at M=500)."""
     import paper_1102_4666_amd as bsde
     import workloads
     out = {}
@@ -308,8 +308,8 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates the "
                          "HBM byte counters of the profiler)")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
-                    help="comma-separated workloads (config2, config3, "
-                         "config4, d10-serving): run one path-kernel launch "
+                    help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
+                         "geo_basket_d5, d10-serving): run one path-kernel launch "
                          "of each and print its time, nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -4,7 +4,7 @@ Calls only the oracle (``oracle/``): the per-point corrections of every
 iteration are spread over worker processes with ``oracle.solve_parallel``,
 which runs the same oracle functions in the same order as ``oracle.solve``.
 
-    python tests/golden/make_golden.py config1 [config2 ...] [--workers 8]
+    python tests/golden/make_golden.py eur_put_d1 [amer_put_d1 ...] [--workers 8]
 """
 from __future__ import annotations
 
@@ -36,14 +36,14 @@ def stored_points(n: int) -> np.ndarray:
 
 # name -> (workload factory, kwargs)
 CASES = {
-    "config1": (workloads.config1, {}),
-    "config2_w100": (workloads.config2, {"omega": 100.0}),
-    "config2_w1": (workloads.config2, {"omega": 1.0}),
-    "config3_w100": (workloads.config3, {"omega": 100.0}),
-    "config3_w1": (workloads.config3, {"omega": 1.0}),
-    "config4_w100": (workloads.config4, {"omega": 100.0}),
-    "config4_w1": (workloads.config4, {"omega": 1.0}),
-    "config4_redraw_w1": (workloads.config4, {"omega": 1.0, "redraw": 1}),
+    "eur_put_d1": (workloads.eur_put_d1, {}),
+    "amer_put_d1_w100": (workloads.amer_put_d1, {"omega": 100.0}),
+    "amer_put_d1_w1": (workloads.amer_put_d1, {"omega": 1.0}),
+    "amer_basket_d2_w100": (workloads.amer_basket_d2, {"omega": 100.0}),
+    "amer_basket_d2_w1": (workloads.amer_basket_d2, {"omega": 1.0}),
+    "geo_basket_d5_w100": (workloads.geo_basket_d5, {"omega": 100.0}),
+    "geo_basket_d5_w1": (workloads.geo_basket_d5, {"omega": 1.0}),
+    "geo_basket_d5_redraw_w1": (workloads.geo_basket_d5, {"omega": 1.0, "redraw": 1}),
 }
 
 

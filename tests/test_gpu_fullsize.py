@@ -33,15 +33,15 @@ def _golden(name):
 
 
 @pytest.mark.parametrize("name,prec", [
-    ("config1", "fp64"), ("config1", "fp32"),
-    ("config2_w1", "fp64"), ("config2_w1", "fp32"),
-    ("config2_w100", "fp64"), ("config2_w100", "fp32"),
-    ("config3_w100", "fp64"), ("config3_w100", "fp32"),
-    ("config3_w1", "fp64"), ("config3_w1", "fp32"),
-    ("config4_w100", "fp64"), ("config4_w100", "fp32"),
-    ("config4_w1", "fp64"), ("config4_w1", "fp32"),
+    ("eur_put_d1", "fp64"), ("eur_put_d1", "fp32"),
+    ("amer_put_d1_w1", "fp64"), ("amer_put_d1_w1", "fp32"),
+    ("amer_put_d1_w100", "fp64"), ("amer_put_d1_w100", "fp32"),
+    ("amer_basket_d2_w100", "fp64"), ("amer_basket_d2_w100", "fp32"),
+    ("amer_basket_d2_w1", "fp64"), ("amer_basket_d2_w1", "fp32"),
+    ("geo_basket_d5_w100", "fp64"), ("geo_basket_d5_w100", "fp32"),
+    ("geo_basket_d5_w1", "fp64"), ("geo_basket_d5_w1", "fp32"),
     # points redrawn at every iteration (Algorithm 1)
-    ("config4_redraw_w1", "fp64"), ("config4_redraw_w1", "fp32"),
+    ("geo_basket_d5_redraw_w1", "fp64"), ("geo_basket_d5_redraw_w1", "fp32"),
 ])
 def test_full_size_against_stored_oracle(name, prec):
     g = _golden(name)

@@ -61,8 +61,8 @@ def vol_levels(d: int, seed: int = 0, lo: float = 0.15, hi: float = 0.35):
     return [float(x) for x in rng.uniform(lo, hi, size=d)]
 
 
-# The five benchmark workloads (sizes of the hot-path scope table).
-def config1() -> dict:
+# The benchmark workloads (the serving mix draws its requests from them).
+def eur_put_d1() -> dict:
     """d=1 European put, Black-Scholes sigma=0.2, 64 space x 8 time points,
     M=1000, N=20, 5 Picard iterations, FP64, seed 0."""
     return problem(d=1, vol_kind="const", vol_level=0.2, r=0.05, K=100.0,
@@ -71,7 +71,7 @@ def config1() -> dict:
                    precision="fp64", seed=0)
 
 
-def config2(omega: float = 100.0, precision: str = "fp32") -> dict:
+def amer_put_d1(omega: float = 100.0, precision: str = "fp32") -> dict:
     """d=1 American put (penalised BSDE, penalty 100), local volatility
     0.2 (1 + 0.25 exp(-(log(S/100))^2)), 128 space x 16 time points,
     M=4000, N=50, 8 Picard iterations."""
@@ -82,7 +82,7 @@ def config2(omega: float = 100.0, precision: str = "fp32") -> dict:
                    precision=precision, seed=0)
 
 
-def config3(omega: float = 100.0, precision: str = "fp32") -> dict:
+def amer_basket_d2(omega: float = 100.0, precision: str = "fp32") -> dict:
     """d=2 American arithmetic-basket put, independent bump local vols,
     rho=0.3, 32^2 space x 16 time points, M=2000, N=50, 8 iterations."""
     return problem(d=2, vol_kind="bump", vol_level=0.2, bump_a=0.25,
@@ -91,8 +91,8 @@ def config3(omega: float = 100.0, precision: str = "fp32") -> dict:
                    eta=5, M=2000, N=50, K_it=8, precision=precision, seed=0)
 
 
-def config4(omega: float = 100.0, precision: str = "fp32",
-            redraw: int = 0) -> dict:
+def geo_basket_d5(omega: float = 100.0, precision: str = "fp32",
+                  redraw: int = 0) -> dict:
     """d=5 American geometric-basket put, per-asset levels U[0.15, 0.35]
     (seeded), rho=0.2, 4096 random spatial points x 10 times, M=1000,
     N=50, 10 iterations (redraw=1: new spatial points every iteration)."""
@@ -113,11 +113,11 @@ def serving_request(idx: int, rng: np.random.Generator,
     american = bool(rng.integers(0, 2))
     M = int(rng.choice([500, 1000, 2000, 4000]))
     if d == 1:
-        base = config2()
+        base = amer_put_d1()
     elif d == 2:
-        base = config3()
+        base = amer_basket_d2()
     elif d == 5:
-        base = config4()
+        base = geo_basket_d5()
     else:
         base = problem(d=10, vol_kind="bump", vol_level=vol_levels(10, 0),
                        bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, S0=100.0,
@@ -130,5 +130,5 @@ def serving_request(idx: int, rng: np.random.Generator,
     return cfg
 
 
-CONFIGS = {"config1": config1, "config2": config2, "config3": config3,
-           "config4": config4}
+WORKLOADS = {"eur_put_d1": eur_put_d1, "amer_put_d1": amer_put_d1,
+             "amer_basket_d2": amer_basket_d2, "geo_basket_d5": geo_basket_d5}
