@@ -241,9 +241,15 @@ __host__ __device__ constexpr size_t split_part_halves(int p, int C)
 {
     return (size_t)pad16(C) * pad32(p);
 }
-__host__ __device__ constexpr size_t split_table_floats(int p, int C)
+// then the coefficients alpha (channel 0) once more as contiguous FP32,
+// for the value u^k(T, X_T) on the vector ALUs
+__host__ __device__ constexpr size_t split_alpha_off(int p, int C) // floats
 {
     return split_hi_off(p, C) + split_part_halves(p, C); // two parts of halves
+}
+__host__ __device__ constexpr size_t split_table_floats(int p, int C)
+{
+    return split_alpha_off(p, C) + pad16(p);
 }
 
 // channel 2 + d + idx holds d^2 u / dx_j dx_k for the idx-th pair j <= k

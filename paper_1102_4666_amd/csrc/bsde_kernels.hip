@@ -116,6 +116,14 @@ __device__ __forceinline__ void channel_col(
     const float scale = __builtin_amdgcn_ldexpf(1.0f, -e);
     float *unscale = g32 + split_unscale_off(p, C);
     if (threadIdx.x == 0) unscale[c] = __builtin_amdgcn_ldexpf(1.0f, e);
+    if (c == 0) {
+        float *alpha32 = g32 + split_alpha_off(p, C);
+#pragma unroll
+        for (int j = 0; j < kMaxP / 256; ++j) {
+            const int l = threadIdx.x + 256 * j;
+            if (l < p) alpha32[l] = mine[j];
+        }
+    }
     _Float16 *hi = (_Float16 *)(g32 + split_hi_off(p, C));
     _Float16 *lo = hi + split_part_halves(p, C);
     const int K32 = pad32(p);

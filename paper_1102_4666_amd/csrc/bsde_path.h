@@ -424,16 +424,20 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 return (const __attribute__((address_space(4))) Real *)a;
             };
             // u^k(T, X_T): one dot product with channel 0, 16 terms at a time
-            // (the scheduling barriers keep the loads next to their use)
+            // (the scheduling barriers keep the loads next to their use);
+            // FP32 problems keep channel 0 contiguous as well, so that 16
+            // coefficients come in one scalar load
+            constexpr bool kAlpha32 = std::is_same<Real, float>::value;
             static_for<pad16(NP) / 16>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 __builtin_amdgcn_sched_barrier(0);
-                const auto g0 = opaque(q * 16 * Cs);
+                const auto g0 = kAlpha32 ? opaque((int)split_alpha_off(NP, C) + q * 16)
+                                         : opaque(q * 16 * Cs);
                 static_for<16>([&](auto jc) {
                     constexpr int l = q * 16 + decltype(jc)::value;
                     if constexpr (l < NP)
                         uT += basis(std::integral_constant<int, l>{}, TzT) *
-                              g0[(l - q * 16) * Cs];
+                              g0[kAlpha32 ? (l - q * 16) : (l - q * 16) * Cs];
                 });
             });
             // the terminal term is complete here (nothing of X_T stays live
