@@ -39,8 +39,8 @@ FP64_VECTOR_PEAK = 78.6e12
 # a tiling missing here reports null.
 TRAFFIC_KIB = {"fp32": {1: (179, 64), 2: (307, 128), 4: (307, 256),
                         8: (307, 512), 16: (309, 1024)},
-               "fp64": {1: (270, 64), 2: (398, 128), 4: (398, 256),
-                        8: (398, 512), 16: (400, 1024)}}
+               "fp64": {1: (268, 64), 2: (396, 128), 4: (396, 256),
+                        8: (396, 512), 16: (398, 1024)}}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -54,18 +54,18 @@ def traffic_bytes(precision, groups):
 # Algorithmic work per Euler path-step of the path kernel for the d = 1
 # local-volatility workload (N = 50 steps per path), derived operation by
 # operation in the design doc section 6.  VALU operations: normal 13.25 (1/4 of a
-# Philox4x32-10 block) + Box-Muller 5.5 + local vol 5 + Euler 3 + state at
-# j* 3 + per-path work 270 / N = 34.4, of which 3.12 are transcendentals.
+# Philox4x32-10 block) + Box-Muller 5 + local vol 3 + Euler 3 + state at
+# j* 1 + per-path work 270 / N = 30.65, of which 3.12 are transcendentals.
 # The counters show the transcendentals issuing beside the other VALU work
 # (every instruction at 4 cycles would exceed the issue peak), so the
-# roofline counts the 31.3 others against the VALU issue rate.  FP32 FLOP
-# (FMA = 2, transcendental = 1): Box-Muller 5.5 + local vol 6 + Euler 5 +
+# roofline counts the 27.53 others against the VALU issue rate.  FP32 FLOP
+# (FMA = 2, transcendental = 1): Box-Muller 4.5 + local vol 4 + Euler 6 +
 # per-path work 250 / N.  FP64 paths use software transcendentals with no
 # independent operation count: their figure is the measured SQ_INSTS_VALU
-# minus SQ_INSTS_VALU_TRANS_F64 per path-step (213.6 - 2.7).
-OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.5 + 5 + 3 + 3 + 270 / 50.0 - 3.12,
-                     "fp64": 210.9}
-FP32_FLOP_PER_PATH_STEP = 5.5 + 6 + 5 + 250 / 50.0
+# minus SQ_INSTS_VALU_TRANS_F64 per path-step (162.7 - 1.1).
+OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.0 + 3 + 3 + 1 + 270 / 50.0 - 3.12,
+                     "fp64": 161.6}
+FP32_FLOP_PER_PATH_STEP = 4.5 + 4 + 6 + 250 / 50.0
 
 
 def workload(precision: str, omega: float = 100.0):
@@ -267,11 +267,12 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
             "load_0.9": run_phase(0.9 * x_sat)}
 
 
-def single_launches(names):
+def single_launches(names, euler_steps=None):
     """One Picard iteration (one path-kernel launch) of each named workload,
     FP32 paths, default tiling: the runs behind the profiles of the
     matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
-    d10-serving (the d=10 request shape of the serving mix at M=500)."""
+    d10-serving (the d=10 request shape of the serving mix at M=500).
+    euler_steps replaces N (separates per-step from per-path cost)."""
     import paper_1102_4666_amd as bsde
     import workloads
     out = {}
@@ -282,6 +283,8 @@ def single_launches(names):
         else:
             cfg = getattr(workloads, nm)(precision="fp32")
         cfg.update(K_it=1)
+        if euler_steps:
+            cfg.update(N=euler_steps)
         with bsde.Problem(cfg) as P:
             P.solve()
             out[nm] = {"path_kernel_ms": P.timings()[0],
@@ -307,6 +310,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the "
                          "HBM byte counters of the profiler)")
+    ap.add_argument("--euler-steps", type=int, default=0, metavar="N",
+                    help="with --single-launch: Euler steps per path "
+                         "instead of the workload's")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
                     help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
                          "geo_basket_d5, d10-serving): run one path-kernel launch "
@@ -332,7 +338,8 @@ def main():
                           "copies": 3}))
         return
     if args.single_launch:
-        print(json.dumps(single_launches(args.single_launch.split(","))))
+        print(json.dumps(single_launches(args.single_launch.split(","),
+                                         args.euler_steps or None)))
         return
     stream = torch.cuda.current_stream().cuda_stream
     cfg = workload(args.precision)

@@ -38,24 +38,28 @@ struct u32x4 {
     uint32_t x, y, z, w;
 };
 
+// one round: two 32x32->64 products, the high halves mixed with the other
+// words and the round key, then the key bumped by the Weyl constants
+__host__ __device__ __forceinline__ void philox_round(u32x4 &c, uint32_t &k0,
+                                                      uint32_t &k1)
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    c = {n0, (uint32_t)p1, n2, (uint32_t)p0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+}
+
 __host__ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1,
                                                    uint32_t c2, uint32_t c3,
                                                    uint32_t k0, uint32_t k1)
 {
+    u32x4 c{c0, c1, c2, c3};
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return {c0, c1, c2, c3};
+    for (int r = 0; r < 10; ++r) philox_round(c, k0, k1);
+    return c;
 }
 
 // ---------------------------------------------------------------------------

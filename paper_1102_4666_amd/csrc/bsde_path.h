@@ -42,7 +42,10 @@ struct Arith<float> {
                                                       float &n1)
     {
         float R = __builtin_amdgcn_sqrtf(scale * __builtin_amdgcn_logf(u01(wa)));
-        float ub = u01(wb);
+        // angle: 1 + (top 23 bits of wb) 2^-23 in [1, 2) revolutions, built
+        // by one funnel shift that puts the exponent of 1.0 above them
+        // (sine and cosine have period one revolution)
+        const float ub = __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, wb, 9u));
         n0 = R * __builtin_amdgcn_cosf(ub);
         n1 = R * __builtin_amdgcn_sinf(ub);
     }
@@ -126,6 +129,41 @@ __device__ __forceinline__ Real local_vol(Real level, Real level_a, Real lc,
     return level;
 }
 
+// Coordinates of the Euler state.  With the bump volatility the paths carry
+// y = kappa (x - log c) -- kappa^2 = log2 e in FP32, 1 in FP64 -- so that
+// the volatility costs a square, one exponential and one fused multiply-add
+// per asset and step: level + (level a) 2^{-y^2} (FP32), level + (level a)
+// e^{-y^2} (FP64).  Every increment of x is scaled by kappa as well.  The
+// other volatility kinds keep y = x.
+template <int VOL, typename Real>
+struct EulerState {
+    static constexpr bool kShift = VOL == kVolBump;
+    static constexpr Real kappa =
+        (kShift && sizeof(Real) == 4) ? Real(1.2011224087864498) : Real(1);
+    static __device__ __forceinline__ Real to(Real x, Real lc)
+    {
+        if constexpr (kShift) return (x - lc) * kappa;
+        else return x;
+    }
+    static __device__ __forceinline__ Real from(Real y, Real lc)
+    {
+        if constexpr (kShift) return fma(y, Real(1) / kappa, lc);
+        else return y;
+    }
+    static __device__ __forceinline__ Real vol(Real level, Real level_a, Real spot,
+                                               const VolTime<Real> &vt, Real y)
+    {
+        if constexpr (kShift) {
+            if constexpr (sizeof(Real) == 4)
+                return fmaf(level_a, __builtin_amdgcn_exp2f(-y * y), level);
+            else
+                return fma(level_a, ::exp(-y * y), level);
+        } else {
+            return local_vol<VOL>(level, level_a, Real(0), spot, vt, y);
+        }
+    }
+};
+
 template <int D, typename Real>
 __device__ __forceinline__ Real payoff(int kind, Real K, const Real *x)
 {
@@ -202,6 +240,26 @@ struct Mfma<double> {
     }
 };
 
+// One Philox4x32-10 block in the path kernel (the same function as
+// philox10).  After the second round the key passes through an empty asm
+// statement, so that the keys of rounds 3-10, k + r (W0, W1), are formed on
+// the scalar unit per block instead of being hoisted out of the path loops,
+// where sixteen of them would stay live in scalar registers (at d >= 5 the
+// compiler parks the excess in vector-register lanes and reads it back with
+// one vector instruction per use).  The first two rounds keep their
+// hoistable work on the uniform counter words (i, k).
+__device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t c2,
+                                              uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    u32x4 c{c0, c1, c2, c3};
+    philox_round(c, k0, k1);
+    philox_round(c, k0, k1);
+    asm volatile("" : "+s"(k0), "+s"(k1));
+#pragma unroll
+    for (int r = 2; r < 10; ++r) philox_round(c, k0, k1);
+    return c;
+}
+
 // ---------------------------------------------------------------------------
 // The Monte Carlo path kernel.
 // Grid: n * groups workgroups of kBlock lanes; workgroup (i, g) runs the
@@ -235,8 +293,10 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     const Real T = (Real)prm.T;
     const Real t0 = (Real)row[0];
     const Real h = (T - t0) / (Real)prm.N;
-    // step normals come out of Box-Muller already scaled by sqrt(h)
-    const Real step_scale = Arith<Real>::bm_scale(h);
+    // Euler state coordinates y = kappa (x - off); step normals come out of
+    // Box-Muller already scaled by kappa sqrt(h)
+    using ES = EulerState<VOL, Real>;
+    const Real step_scale = Arith<Real>::bm_scale(h * (ES::kappa * ES::kappa));
     const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
     const Real lc = (Real)prm.log_bump_c;
     const Real rho = (Real)prm.rho;
@@ -247,7 +307,26 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     // terms of sum_k L_jk G_k in the same order, O(d) instead of O(d^2)
     const AssetConsts<Real> &ac = asset_consts<Real>(prm);
     const Real tscale = Real(2) / T;
-    const Real neg_half_h = Real(-0.5) * h;
+    const Real neg_half_hk = Real(-0.5) * ES::kappa * h;
+    const Real hk = ES::kappa * h;
+    // The volatility levels as vector operands: the volatility's fused
+    // multiply-add has another scalar operand (level a) already, and a
+    // second one costs a register move per asset and step.  At d = 10 the
+    // vector registers are the scarcer ones (the moves are cheaper than the
+    // spills that ten more live registers cause).
+    Real lev[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lev[j] = ac.level[j];
+        if constexpr (D <= 5) asm volatile("" : "+v"(lev[j]));
+    }
+    // X and the normals G at the step j* of each path: written to LDS by
+    // the one step that matches, a store under the lane mask, where a
+    // select in every step would take two vector-ALU slots per asset
+    struct alignas(2 * sizeof(Real)) Rec {
+        Real y, g;
+    };
+    __shared__ Rec rec[D][kBlock];
 
     double sum = 0.0, sumsq = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
@@ -262,7 +341,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         }
 
         // U, j* = floor(U N) and theta = U N - j* in integer arithmetic
-        const u32x4 wu = philox10((uint32_t)m, (uint32_t)i, prm.k, 1u << 24,
+        const u32x4 wu = philox_block((uint32_t)m, (uint32_t)i, prm.k, 1u << 24,
                                   k0, k1);
         const uint64_t num = (2ull * wu.x + 1ull) * (uint64_t)prm.N;
         const int jstar = (int)(num >> 33);
@@ -270,19 +349,15 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         const Real U = Arith<Real>::u01(wu.x);
         const Real tau = t0 + (T - t0) * U;
 
-        Real X[D], Xs[D], LGs[D];
+        Real X[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            X[j] = (Real)row[1 + j];
-            Xs[j] = X[j];
-            LGs[j] = Real(0);
-        }
+        for (int j = 0; j < D; ++j) X[j] = ES::to((Real)row[1 + j], lc);
         const int ngroups = (prm.N + SG - 1) / SG;
         for (int grp = 0; grp < ngroups; ++grp) {
             Real G[4 * NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
+                const u32x4 w = philox_block((uint32_t)m, (uint32_t)i, prm.k,
                                          (uint32_t)(grp * NB + b), k0, k1);
                 Arith<Real>::box_muller(w.x, w.y, step_scale, G[4 * b],
                                         G[4 * b + 1]);
@@ -293,24 +368,26 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             for (int ss = 0; ss < SG; ++ss) {
                 const int s = grp * SG + ss;
                 if (s < prm.N) {
-                    const bool at = (s == jstar);
+                    if (s == jstar) {
+#pragma unroll
+                        for (int j = 0; j < D; ++j)
+                            rec[j][threadIdx.x] = Rec{X[j], G[ss * D + j]};
+                    }
                     const VolTime<Real> vt = vol_time<VOL>(t0 + Real(s) * h, r);
                     Real S = Real(0);
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
-                        // sqrt(h) (L G)_j; the first row of the Cholesky
+                        // kappa sqrt(h) (L G)_j; the first row of the Cholesky
                         // factor of a correlation matrix is (1, 0, ..., 0)
                         Real lg = G[ss * D];
                         if (j > 0) lg = fma(ac.Ldiag[j], G[ss * D + j], S);
                         if (j + 1 < D) S = j == 0 ? ac.Lcol[0] * G[ss * D]
                                                   : fma(ac.Lcol[j], G[ss * D + j], S);
-                        const Real sig = local_vol<VOL>(ac.level[j], ac.level_a[j], lc,
-                                                        ac.spot[j], vt, X[j]);
-                        Xs[j] = at ? X[j] : Xs[j];
-                        LGs[j] = at ? lg : LGs[j];
+                        const Real sig = ES::vol(lev[j], ac.level_a[j], ac.spot[j], vt, X[j]);
                         // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
-                        //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2)
-                        X[j] = fma(ac.drift[j], h, fma(sig, fma(neg_half_h, sig, lg), X[j]));
+                        //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2),
+                        // every term times kappa
+                        X[j] = fma(ac.drift[j], hk, fma(sig, fma(neg_half_hk, sig, lg), X[j]));
                     }
                 }
             }
@@ -323,12 +400,29 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         Real Gb[4 * NBB];
 #pragma unroll
         for (int b = 0; b < NBB; ++b) {
-            const u32x4 w = philox10((uint32_t)m, (uint32_t)i, prm.k,
+            const u32x4 w = philox_block((uint32_t)m, (uint32_t)i, prm.k,
                                      (1u << 24) | (uint32_t)(1 + b), k0, k1);
             Arith<Real>::box_muller(w.x, w.y, bridge_scale, Gb[4 * b],
                                     Gb[4 * b + 1]);
             Arith<Real>::box_muller(w.z, w.w, bridge_scale, Gb[4 * b + 2],
                                     Gb[4 * b + 3]);
+        }
+        // back to x: the state at T and at t_{j*} with sqrt(h) (L G) of the
+        // step j* (every j* < N is a step of the path, so each lane has
+        // written its own record)
+        Real Xs[D], LGs[D];
+        {
+            Real Sr = Real(0);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const Rec rj = rec[j][threadIdx.x];
+                Xs[j] = ES::from(rj.y, lc);
+                Real lg = rj.g;
+                if (j > 0) lg = fma(ac.Ldiag[j], rj.g, Sr);
+                if (j + 1 < D) Sr = j == 0 ? ac.Lcol[0] * rj.g : fma(ac.Lcol[j], rj.g, Sr);
+                LGs[j] = lg * (Real(1) / ES::kappa);
+                X[j] = ES::from(X[j], lc);
+            }
         }
         Real sgs[D], bst[D], Xt[D];
         Real Sb = Real(0);
