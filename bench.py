@@ -73,14 +73,21 @@ def workload(precision: str, omega: float = 100.0):
     return workloads.amer_put_d1(omega=omega, precision=precision)
 
 
-def run_job(cfg, stream, phases=None):
+def run_job(cfg, stream, phases=None, solve_lock=None):
     """One pricing job; phases (if a dict) accumulates the host wall time
-    of create / solve / query / destroy in milliseconds."""
+    of create / solve / query / destroy in milliseconds.  With solve_lock,
+    the solve holds it (jobs of other threads create and query meanwhile)."""
     import paper_1102_4666_amd as bsde
     t0 = time.perf_counter()
     P = bsde.Problem(cfg)
+    if solve_lock is not None:
+        solve_lock.acquire()
     t1 = time.perf_counter()
-    P.solve(stream)
+    try:
+        P.solve(stream)
+    finally:
+        if solve_lock is not None:
+            solve_lock.release()
     t2 = time.perf_counter()
     price, delta = P.price_delta()
     timings = P.timings()
@@ -92,6 +99,46 @@ def run_job(cfg, stream, phases=None):
                         ("query", t3 - t2), ("destroy", t4 - t3)):
             phases[key] = phases.get(key, 0.0) + 1e3 * dt
     return price[0], delta[0], timings
+
+
+def run_jobs(cfg, n_jobs, streams):
+    """n_jobs pricing jobs of cfg over len(streams) host threads, one HIP
+    stream each: job j runs on thread j % depth.  The solves (the Picard
+    iterations) take a lock, so that path kernels of two jobs never share
+    the GPU; the set-up of a job (host work and its small device kernels)
+    and the query and release of the previous one overlap the solve of
+    another.  Returns per-job latencies (s), path-kernel ms, timings and the
+    summed phase times."""
+    import threading
+    depth = len(streams)
+    lat, path_ms, kern_ms = [0.0] * n_jobs, [0.0] * n_jobs, [None] * n_jobs
+    phases = [dict() for _ in range(depth)]
+    errors = []
+    lock = threading.Lock() if depth > 1 else None
+
+    def worker(w):
+        try:
+            for j in range(w, n_jobs, depth):
+                ts = time.perf_counter()
+                _, _, tim = run_job(cfg, streams[w], phases[w], lock)
+                lat[j] = time.perf_counter() - ts
+                path_ms[j] = tim[0]
+                kern_ms[j] = tim
+        except Exception as e:  # reported by the caller
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(depth)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    merged = {}
+    for ph in phases:
+        for k, v in ph.items():
+            merged[k] = merged.get(k, 0.0) + v
+    return lat, path_ms, kern_ms, merged
 
 
 def accuracy(precision: str, stream):
@@ -298,6 +345,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--pipeline", type=int, default=1, metavar="DEPTH",
+                    help="pricing jobs in flight (host threads): the set-up "
+                         "of one overlaps the Picard iterations of another "
+                         "(default 1: one job after the other)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-accuracy", action="store_true",
@@ -341,6 +392,8 @@ def main():
         print(json.dumps(single_launches(args.single_launch.split(","),
                                          args.euler_steps or None)))
         return
+    if args.pipeline < 1:
+        ap.error("--pipeline must be at least 1")
     stream = torch.cuda.current_stream().cuda_stream
     cfg = workload(args.precision)
     n = cfg["n_t"] * cfg["n_x"]
@@ -351,20 +404,13 @@ def main():
     import paper_1102_4666_amd as bsde
     with bsde.Problem(cfg) as P:
         tiling = P.autotune(stream)
-    for _ in range(args.warmup):
-        run_job(cfg, stream)
+    # job pipeline: one stream per host thread (default priority)
+    streams = [stream] + [torch.cuda.Stream().cuda_stream
+                          for _ in range(args.pipeline - 1)]
+    run_jobs(cfg, args.warmup, streams)
     torch.cuda.synchronize()
-    lat = []
-    path_ms = []
-    kern_ms = []
-    phases = {}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, _, tim = run_job(cfg, stream, phases)
-        lat.append(time.perf_counter() - ts)
-        path_ms.append(tim[0])
-        kern_ms.append(tim)
+    lat, path_ms, kern_ms, phases = run_jobs(cfg, args.steps, streams)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
@@ -388,6 +434,7 @@ def main():
                                "bump local vol, 128x16 grid, M=4000, N=50, "
                                "8 Picard iterations, eta=4",
                    "path_steps_per_job": steps_per_job,
+                   "jobs_in_flight": args.pipeline,
                    "precision": args.precision},
         "requests_per_s": args.steps / wall,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
@@ -396,8 +443,9 @@ def main():
         "tiling": {"groups_per_point": tiling[0], "paths_per_lane": tiling[1]},
         "job_phase_ms": {k: v / args.steps for k, v in phases.items()},
         "kernel_ms_per_iteration": dict(zip(
-            ["path", "reduce", "project", "update", "solve_total"],
-            [float(x) for x in np.mean(kern_ms, axis=0)])),
+            ["path", "reduce_project_update"],
+            [float(x) for x in np.mean(kern_ms, axis=0)[:2]])),
+        "solve_ms": float(np.mean(kern_ms, axis=0)[4]),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "T VALU lane-ops/s (transcendentals excluded)",

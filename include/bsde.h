@@ -230,10 +230,21 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups,
                           int *paths_per_lane, double *ms);
 
 /* Average duration in milliseconds of the last solve's kernels, measured
- * with HIP events on the solve's stream: [0] Monte Carlo path kernel,
- * [1] reduction of the per-point sums, [2] projection R^{-1} Q' c,
- * [3] coefficient/channel update, [4] whole solve. */
+ * with HIP events on the solve's stream, per Picard iteration unless noted:
+ * [0] Monte Carlo path kernel, [1] reduction of the per-point sums,
+ * [2] projection R^{-1} Q' c, [3] coefficient/channel update, [4] whole
+ * solve (not averaged).  What is measured depends on the timing level
+ * (bsde_set_timing): level 1 (the default) times the path kernel, and
+ * [1] then holds reduction, projection and update together ([2] = [3] =
+ * 0); level 2 times each kernel; level 0 only the whole solve. */
 bsde_status bsde_last_timings(bsde_problem h, double *ms5);
+
+/* Timing level of later solves of h: 0 = whole solve only, 1 = also the
+ * path kernel of every iteration (default), 2 = every kernel.  Each level
+ * adds HIP event records to the stream between kernels, and each record
+ * costs the stream a few microseconds.  Results do not depend on it.
+ * Errors: EINVAL for a null handle or a level outside 0..2. */
+bsde_status bsde_set_timing(bsde_problem h, int level);
 
 /* Solves many problems together (hot-path row "batching"): all remaining
  * Picard iterations of every problem, with one persistent kernel launch per

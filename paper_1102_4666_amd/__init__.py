@@ -34,7 +34,7 @@ EXPORTS = [
     "bsde_create_problem", "bsde_solve", "bsde_query_price_delta",
     "bsde_problem_sizes", "bsde_get_points", "bsde_get_coefficients",
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
-    "bsde_set_tiling", "bsde_autotune", "bsde_last_timings",
+    "bsde_set_tiling", "bsde_autotune", "bsde_last_timings", "bsde_set_timing",
     "bsde_solve_batch",
     "bsde_destroy", "bsde_status_string", "bsde_last_error",
     "bsde_server_create", "bsde_server_submit", "bsde_server_poll",
@@ -118,6 +118,7 @@ def lib():
         L.bsde_get_corrections.argtypes = [H, C.c_int, _dp, _dp]
         L.bsde_set_tiling.argtypes = [H, C.c_int, C.c_int]
         L.bsde_last_timings.argtypes = [H, _dp]
+        L.bsde_set_timing.argtypes = [H, C.c_int]
         L.bsde_autotune.argtypes = [H, C.c_void_p, _ip, _ip, _dp]
         L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
                                        C.c_int, _dp]
@@ -267,6 +268,10 @@ def bsde_autotune(h, stream=None):
     return g.value, p_.value, ms.value
 
 
+def bsde_set_timing(h, level):
+    _check(lib().bsde_set_timing(h, int(level)), "bsde_set_timing")
+
+
 def bsde_last_timings(h):
     t = np.zeros(5)
     _check(lib().bsde_last_timings(h, _d(t)), "bsde_last_timings")
@@ -334,6 +339,11 @@ class Problem:
 
     def timings(self):
         return bsde_last_timings(self.h)
+
+    def set_timing(self, level):
+        """0 = whole solve only, 1 = path kernel per iteration (default),
+        2 = every kernel (each level adds event records to the stream)."""
+        bsde_set_timing(self.h, level)
 
     def autotune(self, stream=None):
         """(groups per point, paths per lane, path-kernel ms) chosen."""

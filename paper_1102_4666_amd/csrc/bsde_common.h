@@ -29,6 +29,9 @@ __host__ __device__ __forceinline__ void static_for(F &&f)
 
 constexpr int kMaxD = 10;
 constexpr int kBlock = 256; // lanes per workgroup of the path kernel
+// largest basis whose set-up factorisations run on the device (two
+// kSmallFactorP^2 FP64 matrices in the LDS of one wave's workgroup)
+constexpr int kSmallFactorP = 56;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter words:

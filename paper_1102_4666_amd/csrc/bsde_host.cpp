@@ -28,9 +28,11 @@
 namespace bsde {
 bool kernel_exists(int d, int eta, int q10);
 int index_table(int d, int eta, int q10, int8_t *nu, int cap);
+// ev0/ev1 (may be null): start and end times of the path-kernel dispatch
 hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream_t s,
                        const PathParams &prm, const double *pts,
-                       const void *gamma, double *partial);
+                       const void *gamma, double *partial,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_update(int n, int groups, int M, int p, int C,
                          hipStream_t s, const double *partial, double *c,
                          double *var, const double *W, double *beta,
@@ -59,7 +61,10 @@ hipError_t launch_gram(const double *A, int ld, int pap, int rows_per_chunk,
                        double *partial, int pa, double *G, hipStream_t s);
 hipError_t launch_gemm_ax(const double *A, int ld, const double *X, int pap,
                           double *Y, int ldy, int nrows, const int *colmap,
-                          int ncols, hipStream_t s);
+                          int ncols, hipStream_t s, const int *skip = nullptr);
+hipError_t launch_small_factor(const double *G, int pa, int pap, double rel_tol,
+                               int stage, double *X1, double *Xp, int *status,
+                               hipStream_t s);
 } // namespace bsde
 
 using namespace bsde;
@@ -371,19 +376,58 @@ static void setup_shape(int n, int pap, int &ld, int &rpc, int &chunks)
 {
     ld = (n + 63) & ~63;
     const int nb = (pap + 63) / 64;
+    // about 2048 single-wave workgroups over the block pairs and chunks,
+    // at least 64 rows a chunk (a chunk's loads are a dependent chain, so
+    // small problems want many short chunks)
     const int want = std::max(1, 2048 / (nb * (nb + 1) / 2));
-    rpc = std::max(256, ((ld + want - 1) / want + 15) & ~15);
+    rpc = std::max(64, ((ld + want - 1) / want + 15) & ~15);
     chunks = (ld + rpc - 1) / rpc;
+}
+
+// Pinned host staging buffers for uploads: size classes of powers of two,
+// reused, held until the process ends (like the device pool).
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void *> g_pin_free;
+constexpr size_t kPinnedMax = size_t(16) << 20; // larger uploads stage in HIP
+} // namespace
+static void *pinned_get(size_t bytes, size_t *cap)
+{
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    *cap = c;
+    {
+        std::lock_guard<std::mutex> g(g_pin_mu);
+        auto it = g_pin_free.find(c);
+        if (it != g_pin_free.end()) {
+            void *p = it->second;
+            g_pin_free.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+static void pinned_put(void *p, size_t cap)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_pin_free.emplace(cap, p);
 }
 
 // Pseudo-inverse W = B^+ (p x n, row-major; rows of inactive multi-indices
 // zero) of the basis matrix of the grid by CholeskyQR2 on the device:
 // B (n x pa) is formed from the device copy of the points, the Gram
-// matrices and the tall-skinny products run on the device, the two pa x pa
-// Cholesky factorisations and triangular inverses on the host.  Returns
+// matrices and the tall-skinny products run on the device; the two pa x pa
+// Cholesky factorisations and triangular inverses run on the device too
+// when pa <= kSmallFactorP (one wave, LDS), else on the host.  Returns
 // BSDE_ERANK when B is numerically rank deficient (a Cholesky pivot of B'B
 // below 1e-7 of the largest, i.e. a condition number beyond ~1e7).
-static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<int> &act)
+// Stream-ordered on s (the points must be uploaded on s or before); the
+// call synchronizes s.
+static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<int> &act,
+                                         hipStream_t s)
 {
     const int n = h->n, pa = (int)act.size(), pap = pad16(pa), dp = h->d + 1;
     std::vector<int2> pairs;
@@ -401,12 +445,29 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
         ms[kMaxD + j] = h->base.scale[j];
     }
 
+    // the small inputs of the set-up kernels travel in one upload:
+    // index set | domain map | Gram block pairs | active columns | status
+    auto al8 = [](size_t b) { return (b + 7) & ~(size_t)7; };
+    const size_t o_ms = al8(nu_act.size()), o_pairs = o_ms + sizeof(double) * ms.size(),
+                 o_map = o_pairs + sizeof(int2) * pairs.size(),
+                 o_status = al8(o_map + sizeof(int) * pa), n_small = o_status + 8;
+    size_t pin_cap = 0;
+    unsigned char *stage = (unsigned char *)pinned_get(n_small, &pin_cap);
+    std::vector<unsigned char> stage_pageable;
+    if (!stage) {
+        stage_pageable.resize(n_small);
+        stage = stage_pageable.data();
+    }
+    std::memset(stage, 0, n_small);
+    std::memcpy(stage, nu_act.data(), nu_act.size());
+    std::memcpy(stage + o_ms, ms.data(), sizeof(double) * ms.size());
+    std::memcpy(stage + o_pairs, pairs.data(), sizeof(int2) * pairs.size());
+    std::memcpy(stage + o_map, act.data(), sizeof(int) * pa);
+    const bool small = pa <= kSmallFactorP;
+
     double *dB = nullptr, *dQ = nullptr, *dPart = nullptr, *dG = nullptr,
-           *dX = nullptr, *dMS = nullptr;
-    int8_t *dNu = nullptr;
-    int2 *dPairs = nullptr;
-    int *dMap = nullptr;
-    hipStream_t s = nullptr;
+           *dX = nullptr, *dX1 = nullptr;
+    unsigned char *dSmall = nullptr;
     bsde_status st = BSDE_OK;
     std::string why;
     auto chk = [&](hipError_t e, const char *what) {
@@ -417,22 +478,54 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
     };
     std::vector<double> G((size_t)pa * pa), R1, R2;
     do {
-        if (!chk(setup_stream_get(&s), "set-up stream")) break;
         if (!chk(pool_alloc((void **)&dB, sizeof(double) * ld * pap), "device allocation") ||
             !chk(pool_alloc((void **)&dQ, sizeof(double) * ld * pap), "device allocation") ||
             !chk(pool_alloc((void **)&dPart, sizeof(double) * chunks * pap * pap), "device allocation") ||
             !chk(pool_alloc((void **)&dG, sizeof(double) * pa * pa), "device allocation") ||
             !chk(pool_alloc((void **)&dX, sizeof(double) * pap * pap), "device allocation") ||
-            !chk(pool_alloc((void **)&dMS, sizeof(double) * ms.size()), "device allocation") ||
-            !chk(pool_alloc((void **)&dNu, nu_act.size()), "device allocation") ||
-            !chk(pool_alloc((void **)&dPairs, sizeof(int2) * pairs.size()), "device allocation") ||
-            !chk(pool_alloc((void **)&dMap, sizeof(int) * pa), "device allocation"))
+            !chk(pool_alloc((void **)&dSmall, n_small), "device allocation") ||
+            (small && !chk(pool_alloc((void **)&dX1, sizeof(double) * pa * pa), "device allocation")))
             break;
-        if (!chk(hipMemcpyAsync(dNu, nu_act.data(), nu_act.size(), hipMemcpyHostToDevice, s), "upload") ||
-            !chk(hipMemcpyAsync(dMS, ms.data(), sizeof(double) * ms.size(), hipMemcpyHostToDevice, s), "upload") ||
-            !chk(hipMemcpyAsync(dPairs, pairs.data(), sizeof(int2) * pairs.size(), hipMemcpyHostToDevice, s), "upload") ||
-            !chk(hipMemcpyAsync(dMap, act.data(), sizeof(int) * pa, hipMemcpyHostToDevice, s), "upload"))
+        if (!chk(hipMemcpyAsync(dSmall, stage, n_small, hipMemcpyHostToDevice, s), "upload"))
             break;
+        const int8_t *dNu = (const int8_t *)dSmall;
+        const double *dMS = (const double *)(dSmall + o_ms);
+        const int2 *dPairs = (const int2 *)(dSmall + o_pairs);
+        const int *dMap = (const int *)(dSmall + o_map);
+        int *dStatus = (int *)(dSmall + o_status);
+        if (small) {
+            // CholeskyQR2 with the p x p steps on the device: stream-ordered,
+            // one synchronisation (the status) at the end; the last product
+            // leaves W untouched when a rank test failed
+            int status = 0;
+            if (!chk(launch_basis_matrix(h->d_pts, n, ld, dp, dNu, pa, pap, dMS, dMS + kMaxD,
+                                         h->base.T, dB, s), "basis kernel") ||
+                !chk(launch_gram(dB, ld, pap, rpc, chunks, dPairs, (int)pairs.size(), dPart, pa,
+                                 dG, s), "gram kernel") ||
+                !chk(launch_small_factor(dG, pa, pap, 1e-7, 1, dX1, dX, dStatus, s),
+                     "factor kernel") ||
+                !chk(launch_gemm_ax(dB, ld, dX, pap, dQ, ld, ld, nullptr, pap, s, dStatus),
+                     "gemm kernel") ||
+                !chk(launch_gram(dQ, ld, pap, rpc, chunks, dPairs, (int)pairs.size(), dPart, pa,
+                                 dG, s), "gram kernel") ||
+                !chk(launch_small_factor(dG, pa, pap, 1e-3, 2, dX1, dX, dStatus, s),
+                     "factor kernel"))
+                break;
+            if (pa < h->p &&
+                !chk(hipMemsetAsync(h->d_W, 0, sizeof(double) * (size_t)h->p * n, s), "memset"))
+                break;
+            if (!chk(launch_gemm_ax(dQ, ld, dX, pap, h->d_W, n, n, dMap, pa, s, dStatus),
+                     "gemm kernel") ||
+                !chk(hipMemcpyAsync(&status, dStatus, sizeof(int), hipMemcpyDeviceToHost, s),
+                     "download") ||
+                !chk(hipStreamSynchronize(s), "set-up"))
+                break;
+            if (status != 0) {
+                st = BSDE_ERANK;
+                why = "basis matrix is numerically rank deficient on the grid";
+            }
+            break;
+        }
         // B and G1 = B'B
         if (!chk(launch_basis_matrix(h->d_pts, n, ld, dp, dNu, pa, pap, dMS, dMS + kMaxD,
                                      h->base.T, dB, s), "basis kernel") ||
@@ -496,12 +589,10 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
             !chk(hipStreamSynchronize(s), "set-up"))
             break;
     } while (false);
-    if (s) {
-        if (st != BSDE_OK) (void)hipStreamSynchronize(s);
-        setup_stream_put(s);
-    }
+    if (st != BSDE_OK) (void)hipStreamSynchronize(s);
+    if (stage_pageable.empty()) pinned_put(stage, pin_cap);
     for (void *q : {(void *)dB, (void *)dQ, (void *)dPart, (void *)dG, (void *)dX,
-                    (void *)dMS, (void *)dNu, (void *)dPairs, (void *)dMap})
+                    (void *)dX1, (void *)dSmall})
         pool_free(q);
     if (st != BSDE_OK) return fail(st, why);
     return BSDE_OK;
@@ -520,20 +611,19 @@ static size_t g32_floats(const bsde_problem_s *h)
 
 static void free_device(bsde_problem_s *h)
 {
-    pool_free(h->d_pts);
+    pool_free(h->d_block);
     pool_free(h->d_W);
-    pool_free(h->d_D);
-    pool_free(h->d_alpha);
     pool_free(h->d_beta);
-    pool_free(h->d_g64);
-    pool_free(h->d_g32);
     pool_free(h->d_partial);
     pool_free(h->d_c);
     pool_free(h->d_var);
     h->d_pts = h->d_W = h->d_D = h->d_alpha = h->d_beta = h->d_g64 = nullptr;
     h->d_partial = h->d_c = h->d_var = nullptr;
     h->d_g32 = nullptr;
+    h->d_block = nullptr;
 }
+
+
 
 #define HIP_TRY(expr)                                                          \
     do {                                                                       \
@@ -792,13 +882,19 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         alloc_err = pool_alloc(ptr, bytes == 0 ? 8 : bytes);
         return alloc_err == hipSuccess;
     };
-    bool ok = dalloc((void **)&h->d_pts, sizeof(double) * h->pts.size()) &&
+    // points, channel matrices, coefficients and channel tables in one
+    // block (256-byte aligned parts)
+    auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_pts = sizeof(double) * h->pts.size(), b_D = sizeof(double) * Dm.size(),
+                 b_alpha = sizeof(double) * (size_t)(h->K_it + 1) * h->p,
+                 b_g64 = sizeof(double) * (size_t)pad16(h->p) * pad16(h->C),
+                 b_g32 = sizeof(float) * g32_floats(h);
+    const size_t o_D = al256(b_pts), o_alpha = o_D + al256(b_D),
+                 o_g64 = o_alpha + al256(b_alpha), o_g32 = o_g64 + al256(b_g64),
+                 n_block = o_g32 + al256(b_g32);
+    bool ok = dalloc(&h->d_block, n_block) &&
               dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n) &&
-              dalloc((void **)&h->d_D, sizeof(double) * Dm.size()) &&
-              dalloc((void **)&h->d_alpha, sizeof(double) * (size_t)(h->K_it + 1) * h->p) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
-              dalloc((void **)&h->d_g64, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C)) &&
-              dalloc((void **)&h->d_g32, sizeof(float) * g32_floats(h)) &&
               dalloc((void **)&h->d_c, sizeof(double) * (size_t)h->K_it * h->n) &&
               dalloc((void **)&h->d_var, sizeof(double) * (size_t)h->K_it * h->n);
     if (!ok) {
@@ -808,20 +904,51 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
             return fail(BSDE_ENOMEM, "device allocation failed");
         return fail(BSDE_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(alloc_err));
     }
-    hipError_t e = hipMemcpy(h->d_pts, h->pts.data(), sizeof(double) * h->pts.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h->d_D, Dm.data(), sizeof(double) * Dm.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(h->d_alpha, 0, sizeof(double) * (size_t)(h->K_it + 1) * h->p);
-    // the padding of the channel tables stays zero (the update kernels
-    // write only the p x C entries)
-    if (e == hipSuccess) e = hipMemset(h->d_g64, 0, sizeof(double) * (size_t)pad16(h->p) * pad16(h->C));
-    if (e == hipSuccess) e = hipMemset(h->d_g32, 0, sizeof(float) * g32_floats(h));
+    {
+        char *b = (char *)h->d_block;
+        h->d_pts = (double *)b;
+        h->d_D = (double *)(b + o_D);
+        h->d_alpha = (double *)(b + o_alpha);
+        h->d_g64 = (double *)(b + o_g64);
+        h->d_g32 = (float *)(b + o_g32);
+    }
+    // uploads and the set-up kernels go to a set-up stream of the library
+    // (non-blocking: a problem created while another one solves does not
+    // wait for it).  The block goes up in one copy from pinned staging
+    // memory: points, channel matrices and zeros for the starting
+    // coefficients and the channel tables (whose padding stays zero: the
+    // update kernels write only the p x C entries).
+    hipStream_t us = nullptr;
+    size_t pin_cap = 0;
+    void *pin = n_block <= kPinnedMax ? pinned_get(n_block, &pin_cap) : nullptr;
+    hipError_t e = setup_stream_get(&us);
+    if (e == hipSuccess && pin) {
+        std::memset(pin, 0, n_block);
+        std::memcpy(pin, h->pts.data(), b_pts);
+        std::memcpy((char *)pin + o_D, Dm.data(), b_D);
+        e = hipMemcpyAsync(h->d_block, pin, n_block, hipMemcpyHostToDevice, us);
+    } else if (e == hipSuccess) {
+        e = hipMemcpyAsync(h->d_pts, h->pts.data(), b_pts, hipMemcpyHostToDevice, us);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->d_D, Dm.data(), b_D, hipMemcpyHostToDevice, us);
+        if (e == hipSuccess)
+            e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, n_block - o_alpha, us);
+    }
     if (e != hipSuccess) {
+        if (us) {
+            (void)hipStreamSynchronize(us);
+            setup_stream_put(us);
+        }
+        pinned_put(pin, pin_cap);
         free_device(h);
         delete h;
         return fail(BSDE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
-    // pseudo-inverse of the basis matrix of the grid, on the device
-    const bsde_status pst = device_pseudo_inverse(h, act);
+    // pseudo-inverse of the basis matrix of the grid, on the device (it
+    // synchronizes the set-up stream: Dm and the points may go out of scope)
+    const bsde_status pst = device_pseudo_inverse(h, act, us);
+    setup_stream_put(us);
+    pinned_put(pin, pin_cap);
     if (pst != BSDE_OK) {
         free_device(h);
         delete h;
@@ -881,9 +1008,13 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     if (st != BSDE_OK) return st;
     const bool fp32 = h->precision == BSDE_FP32_PATHS;
     const int iters = h->K_it - h->k_done;
-    // events: start, end, and 5 per iteration (before path, after path,
-    // after reduction, after projection, after the channel update)
-    std::vector<hipEvent_t> ev(2 + 5 * (size_t)iters);
+    // events: start, end, and per iteration (timing level 1) the start and
+    // end of the path-kernel dispatch (taken by the dispatch itself, no
+    // marker packets), (level 2) also after the reduction, the projection
+    // and the channel update
+    const int lvl = h->timing;
+    const int per = lvl >= 2 ? 5 : (lvl == 1 ? 2 : 0);
+    std::vector<hipEvent_t> ev(2 + (size_t)per * iters);
     for (auto &x : ev) HIP_TRY(event_get(&x));
     struct Release {
         std::vector<hipEvent_t> &v;
@@ -896,7 +1027,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
                             h->d_D, h->d_g64, h->d_g32, split_of(h)));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
-        hipEvent_t *e = &ev[2 + 5 * (size_t)it];
+        hipEvent_t *e = per ? &ev[2 + (size_t)per * it] : nullptr;
         if (h->redraw && h->pts_k != k) {
             // Algorithm 1: new points for this iteration, and the
             // pseudo-inverse of their basis matrix (after the previous
@@ -904,9 +1035,9 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
             HIP_TRY(hipStreamSynchronize(s));
             const auto t0 = std::chrono::steady_clock::now();
             make_points(h, k, h->pts);
-            HIP_TRY(hipMemcpy(h->d_pts, h->pts.data(), sizeof(double) * h->pts.size(),
-                              hipMemcpyHostToDevice));
-            const bsde_status pst = device_pseudo_inverse(h, h->act);
+            HIP_TRY(hipMemcpyAsync(h->d_pts, h->pts.data(), sizeof(double) * h->pts.size(),
+                                   hipMemcpyHostToDevice, s));
+            const bsde_status pst = device_pseudo_inverse(h, h->act, s);
             if (pst != BSDE_OK) return pst;
             h->pts_k = k;
             t_setup += std::chrono::duration<double, std::milli>(
@@ -917,33 +1048,40 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
         prm.groups = groups;
         prm.paths_per_lane = ppl;
         prm.n = h->n;
-        HIP_TRY(hipEventRecord(e[0], s));
         HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * groups, s, prm, h->d_pts,
                             fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
-                            h->d_partial));
-        HIP_TRY(hipEventRecord(e[1], s));
+                            h->d_partial, e ? e[0] : nullptr, e ? e[1] : nullptr));
         HIP_TRY(launch_update(h->n, groups, h->M, h->p, h->C, s, h->d_partial,
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
                               h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
-                              h->d_g32, split_of(h), e + 2)); // records e[2..4]
+                              h->d_g32, split_of(h),
+                              per == 5 ? e + 2 : nullptr)); // records e[2..4]
     }
     HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipEventSynchronize(ev[1]));
     double t_path = 0, t_fin = 0, t_proj = 0, t_chan = 0;
-    for (int it = 0; it < iters; ++it) {
-        hipEvent_t *e = &ev[2 + 5 * (size_t)it];
+    for (int it = 0; it < iters && per; ++it) {
+        hipEvent_t *e = &ev[2 + (size_t)per * it];
         float ms;
         hipEventElapsedTime(&ms, e[0], e[1]); t_path += ms;
-        hipEventElapsedTime(&ms, e[1], e[2]); t_fin += ms;
-        hipEventElapsedTime(&ms, e[2], e[3]); t_proj += ms;
-        hipEventElapsedTime(&ms, e[3], e[4]); t_chan += ms;
+        if (per == 5) {
+            hipEventElapsedTime(&ms, e[1], e[2]); t_fin += ms;
+            hipEventElapsedTime(&ms, e[2], e[3]); t_proj += ms;
+            hipEventElapsedTime(&ms, e[3], e[4]); t_chan += ms;
+        } else {
+            // the rest of the iteration: up to the next path kernel (or
+            // the end of the solve)
+            hipEvent_t next = it + 1 < iters ? ev[2 + (size_t)per * (it + 1)] : ev[1];
+            hipEventElapsedTime(&ms, e[1], next); t_fin += ms;
+        }
     }
     float tot;
     hipEventElapsedTime(&tot, ev[0], ev[1]);
     (void)t_setup; // included in the total (host-side set-up between launches)
-    HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
-                      sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(h->alpha_hist.data(), h->d_alpha,
+                           sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     if (iters > 0) {
         h->timings[0] = t_path / iters;
         h->timings[1] = t_fin / iters;
@@ -1172,9 +1310,12 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         bsde_problem h = probs[q];
         h->k_done += R[q];
         h->have_alpha = true;
-        if (copy_back)
-            HIP_TRY(hipMemcpy(h->alpha_hist.data(), h->d_alpha,
-                              sizeof(double) * h->alpha_hist.size(), hipMemcpyDeviceToHost));
+        if (copy_back) {
+            HIP_TRY(hipMemcpyAsync(h->alpha_hist.data(), h->d_alpha,
+                                   sizeof(double) * h->alpha_hist.size(),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
     }
     return BSDE_OK;
 }
@@ -1203,11 +1344,15 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
     tmp.M = M;
     int groups, ppl;
     auto_tiling(&tmp, groups, ppl);
-    const size_t sizes[] = {n * (d + 1) * 8, (size_t)p * n * 8, (C - 1) * p * p * 8,
-                            (size_t)(K_it + 1) * p * 8, (size_t)p * 8,
-                            (size_t)pad16(p) * pad16((int)C) * 8,
-                            (d >= 5 ? split_table_floats(p, (int)C)
-                                    : (size_t)pad16(p) * pad16((int)C)) * 4,
+    // the block of points, channel matrices, coefficients and tables (one
+    // allocation, 256-byte aligned parts), then the separate buffers
+    auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t block = al256(n * (d + 1) * 8) + al256((C - 1) * p * p * 8) +
+                         al256((size_t)(K_it + 1) * p * 8) +
+                         al256((size_t)pad16(p) * pad16((int)C) * 8) +
+                         al256((d >= 5 ? split_table_floats(p, (int)C)
+                                       : (size_t)pad16(p) * pad16((int)C)) * 4);
+    const size_t sizes[] = {block, (size_t)p * n * 8, (size_t)p * 8,
                             (size_t)K_it * n * 8,
                             (size_t)K_it * n * 8,
                             n * groups * 16};
@@ -1286,11 +1431,9 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
         prm.n = h->n;
         double t_min = 1e300;
         for (int rep = 0; rep < 5; ++rep) { // first launch warms up
-            HIP_TRY(hipEventRecord(e0, s));
             HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * c.first, s, prm, h->d_pts,
                                 fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
-                                h->d_partial));
-            HIP_TRY(hipEventRecord(e1, s));
+                                h->d_partial, e0, e1));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1314,6 +1457,14 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
     if (groups_out) *groups_out = pick.first;
     if (ppl_out) *ppl_out = pick.second;
     if (ms_out) *ms_out = best;
+    return BSDE_OK;
+}
+
+bsde_status bsde_set_timing(bsde_problem h, int level)
+{
+    if (!h) return fail(BSDE_EINVAL, "null handle");
+    if (level < 0 || level > 2) return fail(BSDE_EINVAL, "timing level must be 0, 1 or 2");
+    h->timing = level;
     return BSDE_OK;
 }
 

@@ -32,6 +32,8 @@ struct bsde_problem_s {
            *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
            *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
     float *d_g32 = nullptr;
+    // d_pts, d_D, d_alpha, d_g64 and d_g32 live in this one allocation
+    void *d_block = nullptr;
     size_t partial_cap = 0;
     // state
     int k_done = 0;
@@ -39,6 +41,7 @@ struct bsde_problem_s {
     std::vector<double> alpha_hist; // (K_it + 1) x p, host mirror
     int groups = 0, ppl = 0;       // tiling (0 = automatic)
     double timings[5] = {0, 0, 0, 0, 0};
+    int timing = 1; // event level of bsde_solve (bsde_set_timing)
 };
 
 

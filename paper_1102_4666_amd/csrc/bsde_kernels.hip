@@ -218,7 +218,8 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
     hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,        \
                                 hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
-                                const void *gamma, double *partial);           \
+                                const void *gamma, double *partial,            \
+                                hipEvent_t ev0, hipEvent_t ev1);               \
     int index_table_d##D(int eta, int q10, int8_t *nu, int cap);               \
     hipError_t launch_batch_d##D(int eta, int q10, bool fp32, int vol,         \
                                  int blocks,                                   \
@@ -255,12 +256,13 @@ bool variant_exists(int d, int eta, int q10, bool fp32, int vol)
 
 hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream_t s,
                        const PathParams &prm, const double *pts,
-                       const void *gamma, double *partial)
+                       const void *gamma, double *partial, hipEvent_t ev0,
+                       hipEvent_t ev1)
 {
 #define X(D)                                                                   \
     if (d == D)                                                                \
         return launch_path_d##D(eta, q10, fp32, blocks, s, prm, pts, gamma,    \
-                                partial);
+                                partial, ev0, ev1);
     BSDE_DIMS(X)
 #undef X
     return hipErrorInvalidValue;

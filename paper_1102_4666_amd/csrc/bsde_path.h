@@ -14,6 +14,7 @@
 
 #include "bsde_common.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace bsde {
@@ -912,7 +913,8 @@ int copy_index_table(int8_t *nu, int cap)
     hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,       \
                                 hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
-                                const void *gamma, double *partial)            \
+                                const void *gamma, double *partial,            \
+                                hipEvent_t ev0, hipEvent_t ev1)                \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         SETS(BSDE_PATH_SET)                                                    \
@@ -953,10 +955,12 @@ int copy_index_table(int8_t *nu, int cap)
         return dispatch_variant<D_, E, F64, DUP>(                              \
             fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
                 using R = typename decltype(rt)::type;                         \
-                hipLaunchKernelGGL(                                            \
+                /* ev0/ev1 (may be null) take the start and end times   \
+                   of the dispatch itself: no marker packets around it */  \
+                hipExtLaunchKernelGGL(                                         \
                     (path_kernel<D_, E, R, decltype(vt)::value, Q>),           \
-                                   dim3(blocks), dim3(kBlock), 0, s, prm, pts, \
-                                   (const R *)gamma, partial);                 \
+                    dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0u, prm, pts,  \
+                    (const R *)gamma, partial);                                \
                 return hipGetLastError();                                      \
             });
 #define BSDE_TABLE_SET(E, Q, F64, DUP)                                         \

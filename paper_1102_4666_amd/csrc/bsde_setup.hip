@@ -7,8 +7,11 @@
 //   G2 = Q1'Q1, R2 = chol(G2),  B^+' = Q1 R2^{-1} R2^{-T} R1^{-T}.
 //
 // The Gram products and the tall-skinny products run on the FP64 matrix
-// cores (v_mfma_f64_16x16x4f64); the two p x p Cholesky factorisations and
-// the triangular inverses stay on the host.
+// cores (v_mfma_f64_16x16x4f64).  The two p x p Cholesky factorisations,
+// the triangular inverses and the p x p products run in one wave with
+// the matrices in LDS when p <= kSmallFactorP (small_factor_kernel), so that
+// the whole set-up is stream-ordered with one host synchronisation at the
+// end; larger bases take them on the host.
 //
 // Matrices over the points are column-major with a leading dimension that
 // is a multiple of 64 (each basis function's values over the points are
@@ -154,8 +157,10 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
 __global__ __launch_bounds__(64) void gemm_ax_kernel(
     const double *__restrict__ A, int ld, const double *__restrict__ X,
     int pap, double *__restrict__ Y, int ldy, int nrows,
-    const int *__restrict__ colmap, int ncols)
+    const int *__restrict__ colmap, int ncols, const int *__restrict__ skip)
 {
+    // a failed factorisation upstream (skip != 0) leaves Y untouched
+    if (skip && *skip != 0) return;
     const int lane = threadIdx.x;
     const int i0 = blockIdx.x * 64;
     const int c0 = blockIdx.y * 64;
@@ -195,6 +200,127 @@ __global__ __launch_bounds__(64) void gemm_ax_kernel(
         }
 }
 
+// ---------------------------------------------------------------------------
+// Small factorisations in LDS, one wave: a wave's LDS operations complete in
+// issue order, so the steps are ordered by wavefront-scope fences (which
+// keep the compiler from moving LDS accesses across them) instead of
+// workgroup barriers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Upper Cholesky factor of the symmetric pa x pa matrix in R (row-major, in
+// LDS), in place: R'R = G.  The rank test is that of the host version: every
+// pivot must be positive and its square root above rel_tol times the square
+// root of the largest diagonal entry of G.  Returns false in every lane when
+// a pivot fails.
+__device__ bool chol_upper_lds(double *R, int pa, double rel_tol)
+{
+    const int t = threadIdx.x;
+    double dmax = 0.0;
+    for (int j = 0; j < pa; ++j) dmax = fmax(dmax, R[j * pa + j]);
+    dmax = sqrt(fmax(dmax, 0.0));
+    for (int j = 0; j < pa; ++j) {
+        const double piv = R[j * pa + j];
+        if (!(piv > 0.0) || !(sqrt(piv) > rel_tol * dmax)) return false;
+        const double r = sqrt(piv);
+        wave_sync();
+        for (int c = j + t; c < pa; c += 64) R[j * pa + c] /= r;
+        wave_sync();
+        // trailing update of the upper triangle: rows rr > j, columns c >= rr
+        const int m = pa - j - 1;
+        for (int e = t; e < m * m; e += 64) {
+            const int rr = j + 1 + e / m, c = j + 1 + e % m;
+            if (c >= rr) R[rr * pa + c] -= R[j * pa + rr] * R[j * pa + c];
+        }
+        wave_sync();
+    }
+    for (int e = t; e < pa * pa; e += 64)
+        if (e % pa < e / pa) R[e] = 0.0;
+    wave_sync();
+    return true;
+}
+
+// X = R^{-1} for upper triangular R (pa x pa, row-major, LDS): one lane per
+// column, back substitution from the diagonal up
+__device__ void tri_inv_upper_lds(const double *R, double *X, int pa)
+{
+    for (int c = threadIdx.x; c < pa; c += 64) {
+        X[c * pa + c] = 1.0 / R[c * pa + c];
+        for (int r = c - 1; r >= 0; --r) {
+            double s = 0.0;
+            for (int k = r + 1; k <= c; ++k) s += R[r * pa + k] * X[k * pa + c];
+            X[r * pa + c] = -s / R[r * pa + r];
+        }
+        for (int r = c + 1; r < pa; ++r) X[r * pa + c] = 0.0;
+    }
+    wave_sync();
+}
+
+// Stage 1 (R1 from G1): X1 = R1^{-1} to X1 (pa x pa) and, zero-padded, to Xp
+// (pap x pap), the right factor of Q1 = B X1.  Stage 2 (R2 from G2): Xp =
+// P' with P = R2^{-1} R2^{-T} R1^{-T}, the right factor of B^+' = Q1 P.
+// status: 0, or the stage whose rank test failed (stage 2 does nothing when
+// stage 1 failed).  One wave.
+__global__ __launch_bounds__(64) void small_factor_kernel(
+    const double *__restrict__ G, int pa, int pap, double rel_tol, int stage,
+    double *__restrict__ X1, double *__restrict__ Xp, int *__restrict__ status)
+{
+    __shared__ double A[kSmallFactorP * kSmallFactorP];
+    __shared__ double Y[kSmallFactorP * kSmallFactorP];
+    const int t = threadIdx.x;
+    if (stage == 2 && *status != 0) return;
+    for (int e = t; e < pa * pa; e += 64) A[e] = G[e];
+    wave_sync();
+    if (!chol_upper_lds(A, pa, rel_tol)) {
+        if (t == 0) *status = stage;
+        return;
+    }
+    tri_inv_upper_lds(A, Y, pa); // Y = R^{-1}
+    if (stage == 1) {
+        for (int e = t; e < pa * pa; e += 64) X1[e] = Y[e];
+        for (int e = t; e < pap * pap; e += 64) {
+            const int r = e / pap, c = e % pap;
+            Xp[e] = (r < pa && c < pa) ? Y[r * pa + c] : 0.0;
+        }
+        if (t == 0) *status = 0;
+        return;
+    }
+    // T2 = Y2 Y2' (upper factors: the sum starts at max(r, c)) into A
+    for (int e = t; e < pa * pa; e += 64) {
+        const int r = e / pa, c = e % pa;
+        double v = 0.0;
+        for (int k = max(r, c); k < pa; ++k) v += Y[r * pa + k] * Y[c * pa + k];
+        A[e] = v;
+    }
+    wave_sync();
+    for (int e = t; e < pa * pa; e += 64) Y[e] = X1[e];
+    wave_sync();
+    // Xp[r][c] = sum_k T2[r][k] X1[c][k] (X1 upper: k >= c)
+    for (int e = t; e < pap * pap; e += 64) {
+        const int r = e / pap, c = e % pap;
+        double v = 0.0;
+        if (r < pa && c < pa)
+            for (int k = c; k < pa; ++k) v += A[r * pa + k] * Y[c * pa + k];
+        Xp[e] = v;
+    }
+    if (t == 0) *status = 0;
+}
+
+hipError_t launch_small_factor(const double *G, int pa, int pap, double rel_tol,
+                               int stage, double *X1, double *Xp, int *status,
+                               hipStream_t s)
+{
+    if (pa > kSmallFactorP || pa < 1 || (stage != 1 && stage != 2))
+        return hipErrorInvalidValue;
+    small_factor_kernel<<<1, 64, 0, s>>>(G, pa, pap, rel_tol, stage, X1, Xp, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_basis_matrix(const double *pts, int n, int ld, int dp,
                                const int8_t *nu, int pa, int pap,
                                const double *mid, const double *scale,
@@ -219,10 +345,10 @@ hipError_t launch_gram(const double *A, int ld, int pap, int rows_per_chunk,
 
 hipError_t launch_gemm_ax(const double *A, int ld, const double *X, int pap,
                           double *Y, int ldy, int nrows, const int *colmap,
-                          int ncols, hipStream_t s)
+                          int ncols, hipStream_t s, const int *skip)
 {
     dim3 grid(ld / 64, (pap + 63) / 64);
-    gemm_ax_kernel<<<grid, 64, 0, s>>>(A, ld, X, pap, Y, ldy, nrows, colmap, ncols);
+    gemm_ax_kernel<<<grid, 64, 0, s>>>(A, ld, X, pap, Y, ldy, nrows, colmap, ncols, skip);
     return hipGetLastError();
 }
 

@@ -58,3 +58,7 @@ def test_valid_problem_without_gpu_reports_device_error():
     with pytest.raises(bsde.BsdeError) as e:
         bsde.Problem(problem(eta=4))
     assert e.value.status == 4
+
+
+def test_set_timing_rejects_a_null_handle():
+    assert bsde.lib().bsde_set_timing(None, 1) == 1

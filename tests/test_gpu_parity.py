@@ -249,6 +249,14 @@ def test_rank_deficient_grids_are_rejected():
     with pytest.raises(BsdeError) as e:
         Problem(problem(d=2, n_t=2, n_x=2, eta=3))
     assert e.value.status == 3, str(e.value)
+    # a basis too large for the on-device factorisation (p = 84): the host
+    # Cholesky applies the same test
+    with pytest.raises(BsdeError) as e:
+        Problem(problem(d=5, vol_level=0.2, S0=100.0, n_t=5, n_x=2, eta=3))
+    assert e.value.status == 3, str(e.value)
+    # both paths still accept a well-posed grid afterwards
+    with Problem(problem(d=1, n_t=5, n_x=8, eta=3)) as P:
+        assert P.n == 40
 
 
 def test_redraw_resumes_and_is_solve_only():
