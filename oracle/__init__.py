@@ -62,6 +62,7 @@ class Problem(C.Structure):
         ("omega", C.c_double),
         ("seed", C.c_uint64),
         ("redraw", C.c_int),
+        ("kernel_bw", C.c_double),
     ]
 
 
@@ -125,6 +126,13 @@ def lib():
         L.oracle_basis_matrix_k.argtypes = [P, C.c_uint32, _dp]
         L.oracle_price_delta.argtypes = [P, _dp, C.c_int, _dp, _dp, _dp,
                                          _dp]
+        L.oracle_kernel_eval.argtypes = [P, _dp, _dp, C.c_int, C.c_double,
+                                         _dp, _dp, _dp, _dp, _dp]
+        L.oracle_kernel_corrections.argtypes = [P, _dp, C.c_uint32, C.c_int,
+                                                C.c_int, _dp, _dp]
+        L.oracle_kernel_solve.argtypes = [P, _dp, _dp, _dp, _dp]
+        L.oracle_kernel_price_delta.argtypes = [P, _dp, C.c_int, _dp, _dp,
+                                                _dp, _dp]
         _lib = L
     return _lib
 
@@ -170,7 +178,13 @@ def make_problem(cfg: dict) -> Problem:
     p.omega = float(cfg.get("omega", 0.0))
     p.seed = int(cfg.get("seed", 0))
     p.redraw = int(bool(cfg.get("redraw", 0)))
+    p.kernel_bw = float(cfg.get("kernel_bw", 0.0))
     return p
+
+
+def kernel_op(cfg) -> bool:
+    """True when cfg asks for the kernel operator of Section 3.2."""
+    return float(cfg.get("kernel_bw", 0.0)) > 0.0
 
 
 # ----------------------------------------------------------------------------
@@ -291,19 +305,51 @@ def path_term(cfg, alpha, t0, x0, i, m, k):
 
 
 def corrections(cfg, alpha, k, i_begin, i_end):
+    """c_i, var_i for points i_begin..i_end-1 at iteration k; alpha is the
+    coefficient vector of u^k (the point values y^{k-1} with the kernel
+    operator), None for u^k = 0."""
     pb = make_problem(cfg)
     cnt = i_end - i_begin
     c = np.zeros(cnt)
     v = np.zeros(cnt)
     a = None if alpha is None else np.ascontiguousarray(alpha, float)
-    lib().oracle_corrections(C.byref(pb), None if a is None else _d(a), k,
-                             i_begin, i_end, _d(c), _d(v))
+    fn = lib().oracle_kernel_corrections if kernel_op(cfg) else lib().oracle_corrections
+    fn(C.byref(pb), None if a is None else _d(a), k, i_begin, i_end, _d(c), _d(v))
     return c, v
 
 
-def solve(cfg, k_start=0, alpha_start=None, k_end=None):
-    """Run Picard iterations k_start..k_end-1; returns a dict of histories."""
+def kernel_eval(cfg, y, t, x):
+    """u, u_t, grad_x u, hess_x u of the kernel operator applied to the
+    values y at the problem's points, at (t, x)."""
     pb = make_problem(cfg)
+    pts = np.ascontiguousarray(points(cfg, 0))
+    y = np.ascontiguousarray(y, float)
+    x = np.ascontiguousarray(np.broadcast_to(np.asarray(x, float), (pb.d,)))
+    u, ut = np.zeros(1), np.zeros(1)
+    ux, uxx = np.zeros(pb.d), np.zeros((pb.d, pb.d))
+    lib().oracle_kernel_eval(C.byref(pb), _d(pts), _d(y), len(pts), t, _d(x),
+                             _d(u), _d(ut), _d(ux), _d(uxx))
+    return u[0], ut[0], ux, uxx
+
+
+def solve(cfg, k_start=0, alpha_start=None, k_end=None):
+    """Run Picard iterations k_start..k_end-1; returns a dict of histories.
+    With the kernel operator (cfg kernel_bw > 0) the whole loop runs from
+    u^0 = 0 and "alpha" holds the point values: row 0 zeros, row k + 1 = y^k
+    (u^{k+1} is the kernel operator applied to row k + 1)."""
+    pb = make_problem(cfg)
+    if kernel_op(cfg):
+        if k_start != 0 or alpha_start is not None or k_end not in (None, pb.K_it):
+            raise ValueError("the kernel operator runs whole solves only")
+        n = lib().oracle_num_points(C.byref(pb))
+        yh = np.zeros((pb.K_it + 1, n))
+        ch = np.zeros((pb.K_it, n))
+        vh = np.zeros((pb.K_it, n))
+        uh = np.zeros((pb.K_it, n))
+        st = lib().oracle_kernel_solve(C.byref(pb), _d(yh), _d(ch), _d(vh), _d(uh))
+        if st:
+            raise RuntimeError("oracle_kernel_solve failed with status %d" % st)
+        return {"alpha": yh, "c": ch, "var": vh, "u": uh, "n": n, "p": n}
     if k_end is None:
         k_end = pb.K_it
     n = lib().oracle_num_points(C.byref(pb))
@@ -338,6 +384,8 @@ def solve_parallel(cfg, workers=8, chunk=64, k_start=0, alpha_start=None,
     order per point), with the per-point corrections of each iteration
     spread over worker processes.  Results are identical to ``solve``."""
     import multiprocessing as mp
+    if kernel_op(cfg):
+        raise ValueError("solve_parallel covers the least-squares operator")
     pb = make_problem(cfg)
     if k_end is None:
         k_end = pb.K_it
@@ -391,12 +439,14 @@ def fit(cfg, y):
 
 
 def price_delta(cfg, alpha, t, S):
+    """Price and dollar deltas of u = sum alpha_l B_l (the kernel operator
+    applied to point values alpha when cfg asks for it) at (t, S)."""
     pb = make_problem(cfg)
     t = np.ascontiguousarray(np.atleast_1d(t), float)
     S = np.ascontiguousarray(np.asarray(S, float).reshape(len(t), pb.d))
     a = np.ascontiguousarray(alpha, float)
     price = np.zeros(len(t))
     delta = np.zeros((len(t), pb.d))
-    lib().oracle_price_delta(C.byref(pb), _d(a), len(t), _d(t), _d(S),
-                             _d(price), _d(delta))
+    fn = lib().oracle_kernel_price_delta if kernel_op(cfg) else lib().oracle_price_delta
+    fn(C.byref(pb), _d(a), len(t), _d(t), _d(S), _d(price), _d(delta))
     return price, delta

@@ -493,6 +493,12 @@ void oracle_path(const oracle_problem *pb, double t0, const double *x0,
 /* a_m = psi^N(t_i, x_i, f_{u^k} + (d_t + L^N) u^k, Phi - u^k, W, U)
  * (Algorithm line "MC"; eq. psiN), with f(t,x,y,z) = -r y + omega (Phi(x) - y)_+
  * (eq. bsde-penal-2) and L^N frozen at the last Euler node. */
+/* a_m from the path and u^k (value, derivatives at (tau, X_tau), value at
+ * (T, X_T)): eq. (3.3) with the penalised driver */
+static double path_term_from(const oracle_problem *pb, const oracle_path_out *pp,
+                             double t0, double u, double ut, const double *ux,
+                             const double *uxx, double uT);
+
 double oracle_path_term(const oracle_problem *pb, const int *nu, int p,
                         const double *alpha, double t0, const double *x0,
                         uint32_t i, uint32_t m, uint32_t k)
@@ -511,6 +517,17 @@ double oracle_path_term(const oracle_problem *pb, const int *nu, int p,
         oracle_eval(pb, nu, p, alpha, T, P.xT, &uT, &dummy_t, dummy_x,
                     dummy_xx);
     }
+    (void)d;
+    return path_term_from(pb, &P, t0, u, ut, ux, uxx, uT);
+}
+
+static double path_term_from(const oracle_problem *pb, const oracle_path_out *pp,
+                             double t0, double u, double ut, const double *ux,
+                             const double *uxx, double uT)
+{
+    const oracle_path_out P = *pp;
+    int d = pb->d;
+    double T = pb->T;
     double f = -pb->r * u + pb->omega * fmax(oracle_payoff(pb, P.xtau) - u, 0.0);
     double gen = ut;
     for (int j = 0; j < d; ++j) gen += P.bstar[j] * ux[j];
@@ -702,4 +719,169 @@ void oracle_price_delta(const oracle_problem *pb, const double *alpha,
             delta[(size_t)qi * d + j] = ux[j] / S[(size_t)qi * d + j];
     }
     free(nu);
+}
+
+/* ===================================================================== */
+/* The kernel operator of Section 3.2 ("A kernel operator", the first      */
+/* version of the method): h(t, x) = sum_i y_i K_t(t - t_i) K_x(x - x_i),  */
+/* taken in its normalised form h = sum_i y_i k_i / sum_i k_i (so that it  */
+/* reproduces constants up to the edges of the domain) with Gaussian k_i   */
+/* of one bandwidth b in the mapped coordinates z.  With S_0 = sum k_i and */
+/* S_1 = sum y_i k_i, h = S_1 / S_0 and, for derivatives in z,             */
+/*   d_v h = (d_v S_1 - h d_v S_0) / S_0,                                  */
+/*   d_vw h = (d_vw S_1 - h d_vw S_0 - d_v h d_w S_0 - d_w h d_v S_0) / S_0. */
+/* ===================================================================== */
+static void map_z(const oracle_problem *pb, const double *lo, const double *hi,
+                  double t, const double *x, double *z)
+{
+    z[0] = 2.0 * t / pb->T - 1.0;
+    for (int j = 0; j < pb->d; ++j)
+        z[1 + j] = 2.0 * (x[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
+}
+
+void oracle_kernel_eval(const oracle_problem *pb, const double *pts,
+                        const double *y, int n, double t, const double *x,
+                        double *u, double *ut, double *ux, double *uxx)
+{
+    const int d = pb->d, dp = d + 1;
+    const double b2 = pb->kernel_bw * pb->kernel_bw;
+    double lo[ORACLE_DMAX], hi[ORACLE_DMAX], z[ORACLE_DMAX + 1];
+    oracle_domain(pb, lo, hi);
+    map_z(pb, lo, hi, t, x, z);
+    double S0 = 0.0, S1 = 0.0;
+    double S0v[ORACLE_DMAX + 1] = { 0 }, S1v[ORACLE_DMAX + 1] = { 0 };
+    double S0vw[(ORACLE_DMAX + 1) * (ORACLE_DMAX + 1)] = { 0 };
+    double S1vw[(ORACLE_DMAX + 1) * (ORACLE_DMAX + 1)] = { 0 };
+    for (int i = 0; i < n; ++i) {
+        const double *row = pts + (size_t)i * dp;
+        double zi[ORACLE_DMAX + 1], dz[ORACLE_DMAX + 1], q = 0.0;
+        map_z(pb, lo, hi, row[0], row + 1, zi);
+        for (int v = 0; v < dp; ++v) {
+            dz[v] = z[v] - zi[v];
+            q += dz[v] * dz[v];
+        }
+        const double e = q / (2.0 * b2);
+        const int flat = e > 60.0; /* clamped: constant weight */
+        const double w = exp(-(flat ? 60.0 : e));
+        const double yi = y ? y[i] : 0.0;
+        S0 += w;
+        S1 += yi * w;
+        if (flat) continue;
+        for (int v = 0; v < dp; ++v) {
+            const double g = -dz[v] / b2; /* d/dz_v of the Gaussian, / w */
+            S0v[v] += w * g;
+            S1v[v] += yi * w * g;
+            for (int ww = 0; ww < dp; ++ww) {
+                const double g2 = dz[v] * dz[ww] / (b2 * b2) - (v == ww ? 1.0 / b2 : 0.0);
+                S0vw[v * dp + ww] += w * g2;
+                S1vw[v * dp + ww] += yi * w * g2;
+            }
+        }
+    }
+    const double h = S1 / S0;
+    double hv[ORACLE_DMAX + 1];
+    for (int v = 0; v < dp; ++v) hv[v] = (S1v[v] - h * S0v[v]) / S0;
+    /* chain rule: dz_0/dt = 2/T, dz_j/dx_j = 2/(hi_j - lo_j) */
+    double sc[ORACLE_DMAX + 1];
+    sc[0] = 2.0 / pb->T;
+    for (int j = 0; j < d; ++j) sc[1 + j] = 2.0 / (hi[j] - lo[j]);
+    *u = h;
+    *ut = hv[0] * sc[0];
+    for (int j = 0; j < d; ++j) {
+        ux[j] = hv[1 + j] * sc[1 + j];
+        for (int l = 0; l < d; ++l) {
+            const int v = 1 + j, ww = 1 + l;
+            const double hvw = (S1vw[v * dp + ww] - h * S0vw[v * dp + ww] -
+                                hv[v] * S0v[ww] - hv[ww] * S0v[v]) / S0;
+            uxx[j * d + l] = hvw * sc[v] * sc[ww];
+        }
+    }
+}
+
+void oracle_kernel_corrections(const oracle_problem *pb, const double *y,
+                               uint32_t k, int i_begin, int i_end, double *c,
+                               double *var)
+{
+    const int d = pb->d, n = oracle_num_points(pb);
+    double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
+    double *a = (double *)malloc(sizeof(double) * (size_t)pb->M);
+    oracle_points(pb, pts);
+    for (int i = i_begin; i < i_end; ++i) {
+        const double *row = pts + (size_t)i * (d + 1);
+        double sum = 0.0;
+        for (int m = 0; m < pb->M; ++m) {
+            oracle_path_out P;
+            oracle_path(pb, row[0], row + 1, (uint32_t)i, (uint32_t)m, k, &P);
+            double u = 0.0, ut = 0.0, ux[ORACLE_DMAX] = { 0 },
+                   uxx[ORACLE_DMAX * ORACLE_DMAX] = { 0 }, uT = 0.0;
+            if (y) {
+                double dt, dx[ORACLE_DMAX], dxx[ORACLE_DMAX * ORACLE_DMAX];
+                oracle_kernel_eval(pb, pts, y, n, P.tau, P.xtau, &u, &ut, ux, uxx);
+                oracle_kernel_eval(pb, pts, y, n, pb->T, P.xT, &uT, &dt, dx, dxx);
+            }
+            a[m] = path_term_from(pb, &P, row[0], u, ut, ux, uxx, uT);
+            sum += a[m];
+        }
+        const double mean = sum / pb->M;
+        double ss = 0.0;
+        for (int m = 0; m < pb->M; ++m) ss += (a[m] - mean) * (a[m] - mean);
+        c[i - i_begin] = mean;
+        if (var) var[i - i_begin] = pb->M > 1 ? ss / (pb->M - 1) : 0.0;
+    }
+    free(pts); free(a);
+}
+
+int oracle_kernel_solve(const oracle_problem *pb, double *y_hist,
+                        double *c_hist, double *var_hist, double *u_hist)
+{
+    const int d = pb->d;
+    if (d < 1 || d > ORACLE_DMAX || pb->N < 1 || pb->M < 1 ||
+        !(pb->kernel_bw > 0.0) || pb->redraw ||
+        (pb->grid != ORACLE_GRID_UNIFORM && pb->n_t < 2) || pb->n_x < 1)
+        return ORACLE_EINVAL;
+    double Ltest[ORACLE_DMAX * ORACLE_DMAX];
+    if (oracle_cholesky(d, pb->rho, Ltest) != ORACLE_OK) return ORACLE_EINVAL;
+    const int n = oracle_num_points(pb);
+    double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
+    double *y = (double *)calloc((size_t)n, sizeof(double));
+    double *ynew = (double *)malloc(sizeof(double) * (size_t)n);
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *var = (double *)malloc(sizeof(double) * (size_t)n);
+    oracle_points(pb, pts);
+    if (y_hist) memset(y_hist, 0, sizeof(double) * (size_t)n);
+    for (int k = 0; k < pb->K_it; ++k) {
+        /* c_i with u^k = h[y^{k-1}] (u^0 = 0) */
+        oracle_kernel_corrections(pb, k ? y : NULL, (uint32_t)k, 0, n, c, var);
+        /* y^k_i = u^k(t_i, x_i) + c^k_i */
+        for (int i = 0; i < n; ++i) {
+            double u = 0.0, ut, ux[ORACLE_DMAX], uxx[ORACLE_DMAX * ORACLE_DMAX];
+            const double *row = pts + (size_t)i * (d + 1);
+            if (k) oracle_kernel_eval(pb, pts, y, n, row[0], row + 1, &u, &ut, ux, uxx);
+            ynew[i] = u + c[i];
+            if (u_hist) u_hist[(size_t)k * n + i] = u;
+        }
+        memcpy(y, ynew, sizeof(double) * (size_t)n);
+        if (y_hist) memcpy(y_hist + (size_t)(k + 1) * n, y, sizeof(double) * (size_t)n);
+        if (c_hist) memcpy(c_hist + (size_t)k * n, c, sizeof(double) * (size_t)n);
+        if (var_hist) memcpy(var_hist + (size_t)k * n, var, sizeof(double) * (size_t)n);
+    }
+    free(pts); free(y); free(ynew); free(c); free(var);
+    return ORACLE_OK;
+}
+
+void oracle_kernel_price_delta(const oracle_problem *pb, const double *y,
+                               int nq, const double *t, const double *S,
+                               double *price, double *delta)
+{
+    const int d = pb->d, n = oracle_num_points(pb);
+    double *pts = (double *)malloc(sizeof(double) * (size_t)n * (d + 1));
+    oracle_points(pb, pts);
+    for (int qi = 0; qi < nq; ++qi) {
+        double x[ORACLE_DMAX], u, ut, ux[ORACLE_DMAX], uxx[ORACLE_DMAX * ORACLE_DMAX];
+        for (int j = 0; j < d; ++j) x[j] = log(S[(size_t)qi * d + j]);
+        oracle_kernel_eval(pb, pts, y, n, t[qi], x, &u, &ut, ux, uxx);
+        price[qi] = u;
+        for (int j = 0; j < d; ++j) delta[(size_t)qi * d + j] = ux[j] / S[(size_t)qi * d + j];
+    }
+    free(pts);
 }

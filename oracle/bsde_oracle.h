@@ -101,6 +101,9 @@ typedef struct {
     uint64_t seed;
     int redraw;                     /* random/uniform points: new points    */
                                     /* every Picard iteration (Algorithm 1) */
+    double kernel_bw;               /* > 0: the kernel operator of Section  */
+                                    /* 3.2 with this bandwidth (mapped z)   */
+                                    /* instead of the least-squares one     */
 } oracle_problem;
 
 /* --- randomness ------------------------------------------------------- */
@@ -177,6 +180,30 @@ int oracle_fit(const oracle_problem *pb, const double *y, double *alpha);
 void oracle_price_delta(const oracle_problem *pb, const double *alpha,
                         int nq, const double *t, const double *S,
                         double *price, double *delta);
+
+/* --- the kernel operator of Section 3.2 (first version of the method) --- */
+/* h(t, x) = sum_i y_i k_i(t, x) / sum_i k_i(t, x), the normalised form of
+ * the paper's sum_i u(t_i, x_i) K_t(t - t_i) K_x(x - x_i), with Gaussian
+ * kernels k_i = exp(-min(|z - z_i|^2 / (2 b^2), 60)) in the mapped
+ * coordinates z of the basis (z_0 = 2t/T - 1, z_j = the map of x_j onto
+ * [-1, 1]), b = kernel_bw.  Beyond the clamp a weight is constant (zero
+ * derivative).  u, u_t, grad_x u and hess_x u of h at (t, x) over the n
+ * points pts with values y. */
+void oracle_kernel_eval(const oracle_problem *pb, const double *pts,
+                        const double *y, int n, double t, const double *x,
+                        double *u, double *ut, double *ux, double *uxx);
+/* c_i and variances at iteration k with u^k = h[y] (y NULL: u^k = 0) */
+void oracle_kernel_corrections(const oracle_problem *pb, const double *y,
+                               uint32_t k, int i_begin, int i_end, double *c,
+                               double *var);
+/* Picard loop with the kernel operator: y^k = u^k(t_i, x_i) + c^k_i and
+ * u^{k+1} = h[y^k].  y_hist: (K_it + 1) x n, row 0 all zero (u^0 = 0),
+ * row k + 1 = y^k; c_hist, var_hist, u_hist: K_it x n (each may be NULL). */
+int oracle_kernel_solve(const oracle_problem *pb, double *y_hist,
+                        double *c_hist, double *var_hist, double *u_hist);
+void oracle_kernel_price_delta(const oracle_problem *pb, const double *y,
+                               int nq, const double *t, const double *S,
+                               double *price, double *delta);
 
 #ifdef __cplusplus
 }
