@@ -318,7 +318,8 @@ def single_launches(names, euler_steps=None):
     """One Picard iteration (one path-kernel launch) of each named workload,
     FP32 paths, default tiling: the runs behind the profiles of the
     matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
-    d10-serving (the d=10 request shape of the serving mix at M=500).
+    eur_put_d1_kernel (the kernel operator of Section 3.2), d10-serving
+    (the d=10 request shape of the serving mix at M=500).
     euler_steps replaces N (separates per-step from per-path cost)."""
     import paper_1102_4666_amd as bsde
     import workloads
@@ -336,6 +337,9 @@ def single_launches(names, euler_steps=None):
             P.solve()
             out[nm] = {"path_kernel_ms": P.timings()[0],
                        "path_steps": P.n * cfg["M"] * cfg["N"]}
+            if cfg.get("kernel_bw", 0.0) > 0.0:
+                # the kernel operator weighs every (path, point) pair
+                out[nm]["kernel_pairs"] = P.n * cfg["M"] * P.n
     return out
 
 
@@ -366,8 +370,9 @@ def main():
                          "instead of the workload's")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
                     help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
-                         "geo_basket_d5, d10-serving): run one path-kernel launch "
-                         "of each and print its time, nothing else")
+                         "geo_basket_d5, eur_put_d1_kernel, d10-serving): run one "
+                         "path-kernel launch of each and print its time, nothing "
+                         "else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU "

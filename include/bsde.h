@@ -121,6 +121,20 @@ typedef struct {
                       on the device for each; bsde_solve only (the batched
                       entry points and the server return
                       BSDE_EUNSUPPORTED).  0: one fixed grid.             */
+    double kernel_bw; /* > 0: extrapolate with the kernel operator of
+                      Section 3.2 (the first version of the method) instead
+                      of least squares on the basis: u^{k+1}(t, x) =
+                      sum_i y_i w_i / sum_i w_i over the points, y_i =
+                      u^k(t_i, x_i) + c^k_i, w_i = exp(-min(|z - z_i|^2 /
+                      (2 kernel_bw^2), 60)) in the coordinates z in
+                      [-1, 1]^{d+1} that map [0, T] x D (the bandwidth is in
+                      those units).  Supported for d <= 2, constant or bump
+                      volatility, fixed points (no redraw), bsde_solve only;
+                      eta and q are not used.  The coefficients of such a
+                      problem are its point values: p = n, coefficient row
+                      k = y^{k-1} (row 0 zero); bsde_set_coefficients and
+                      bsde_fit_values return BSDE_EUNSUPPORTED.  0: the
+                      least-squares operator.                             */
 } bsde_grid;
 
 typedef enum {

@@ -65,7 +65,7 @@ class Payoff(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_t", C.c_int), ("n_x", C.c_int),
                 ("width", C.c_double), ("eta", C.c_int), ("q", C.c_double),
-                ("redraw", C.c_int)]
+                ("redraw", C.c_int), ("kernel_bw", C.c_double)]
 
 
 class Request(C.Structure):
@@ -182,7 +182,7 @@ def _marshal(cfg: dict):
     grid = Grid(GRIDS[cfg.get("grid", "tensor")], int(cfg["n_t"]),
                 int(cfg["n_x"]), float(cfg.get("width", 4.0)),
                 int(cfg["eta"]), float(cfg.get("q", 1.0)),
-                int(bool(cfg.get("redraw", 0))))
+                int(bool(cfg.get("redraw", 0))), float(cfg.get("kernel_bw", 0.0)))
     return d, sig, pay, grid, (level, div, S0)
 
 

@@ -327,7 +327,16 @@ struct PathParams {
     double spot[kMaxD];        // S0_j
     AssetConsts<float> cf;     // the per-asset constants in FP32
     AssetConsts<double> cd;    // and in FP64
+    double kbw;                // kernel operator: bandwidth in z (0: least squares)
 };
+
+// Extrapolating operators: least squares on the polynomial basis, or the
+// kernel operator of Section 3.2 (path kernels with OP = kOpKernel read a
+// table of rows {z_0, .., z_d, y} of kKernelRow entries instead of Gamma)
+enum { kOpBasis = 0, kOpKernel = 1 };
+constexpr int kKernelRow = 4;
+// weights beyond this exponent are constant (the clamp of the kernel)
+constexpr double kKernelClamp = 60.0;
 
 template <typename Real>
 __host__ __device__ __forceinline__ const AssetConsts<Real> &asset_consts(const PathParams &p);

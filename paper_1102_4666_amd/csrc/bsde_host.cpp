@@ -65,6 +65,16 @@ hipError_t launch_gemm_ax(const double *A, int ld, const double *X, int pap,
 hipError_t launch_small_factor(const double *G, int pa, int pap, double rel_tol,
                                int stage, double *X1, double *Xp, int *status,
                                hipStream_t s);
+bool kernel_op_exists(int d, int vol);
+hipError_t launch_kernel_path(int d, bool fp32, int blocks, hipStream_t s,
+                              const PathParams &prm, const double *pts,
+                              const void *table, double *partial,
+                              hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_kernel_update(const PathParams &prm, int d, const double *pts,
+                                const double *yprev, const double *c, double *ynew,
+                                void *table, int fp32, hipStream_t s);
+hipError_t launch_finalize(const double *partial, int n, int groups, int M,
+                           double *c, double *var, hipStream_t s);
 } // namespace bsde
 
 using namespace bsde;
@@ -606,6 +616,7 @@ static int split_of(const bsde_problem_s *h)
 }
 static size_t g32_floats(const bsde_problem_s *h)
 {
+    if (h->kop) return 0; // the kernel operator reads its point table instead
     return split_of(h) ? split_table_floats(h->p, h->C) : (size_t)pad16(h->p) * pad16(h->C);
 }
 
@@ -722,14 +733,27 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     for (int j = 0; j < d; ++j)
         if (!(sigma->level[j] > 0.0) || !(payoff->S0[j] > 0.0))
             return fail(BSDE_EINVAL, "levels and spots must be > 0");
+    // the kernel operator of Section 3.2 instead of least squares
+    const bool kop = grid->kernel_bw != 0.0;
+    if (kop) {
+        if (!(grid->kernel_bw > 0.0) || !std::isfinite(grid->kernel_bw))
+            return fail(BSDE_EINVAL, "kernel_bw must be 0 or a finite bandwidth > 0");
+        if (grid->redraw)
+            return fail(BSDE_EUNSUPPORTED, "the kernel operator takes fixed points");
+        if (!kernel_op_exists(d, sigma->kind))
+            return fail(BSDE_EUNSUPPORTED, "the kernel operator is built for d <= 2 "
+                                           "with constant or bump volatility");
+    }
     // a kernel of the hyperbolic set itself when one is built, else the
     // total-degree kernel with the entries outside the set kept at zero
     const int q10 = kernel_q10(d, grid->eta, grid->q);
-    if (!kernel_exists(d, grid->eta, q10))
+    if (kop) {
+        // no basis: eta and q are not used
+    } else if (!kernel_exists(d, grid->eta, q10))
         return fail(BSDE_EUNSUPPORTED, "no kernel instantiated for d=" +
                                            std::to_string(d) + ", eta=" +
                                            std::to_string(grid->eta));
-    if (!variant_exists(d, grid->eta, q10, precision == BSDE_FP32_PATHS, sigma->kind))
+    if (!kop && !variant_exists(d, grid->eta, q10, precision == BSDE_FP32_PATHS, sigma->kind))
         return fail(BSDE_EUNSUPPORTED,
                     "no kernel instantiated for d=" + std::to_string(d) + ", eta=" +
                         std::to_string(grid->eta) + " with this precision and "
@@ -777,15 +801,18 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         b.scale[j] = 2.0 / (h->hi[j] - h->lo[j]);
     }
     fill_asset_consts(b, d);
+    h->kop = kop;
+    b.kbw = kop ? grid->kernel_bw : 0.0;
 
-    // index set in kernel order; hyperbolic subset marked active
+    // index set in kernel order; hyperbolic subset marked active (a
+    // one-function placeholder for the kernel operator)
     const int dp = d + 1;
     h->q10 = q10;
-    h->p = index_table(d, grid->eta, q10, nullptr, 0);
-    h->nu.resize((size_t)h->p * dp);
-    index_table(d, grid->eta, q10, h->nu.data(), h->p);
+    h->p = kop ? 1 : index_table(d, grid->eta, q10, nullptr, 0);
+    h->nu.assign((size_t)h->p * dp, 0);
+    if (!kop) index_table(d, grid->eta, q10, h->nu.data(), h->p);
     h->active.assign(h->p, 1);
-    if (grid->q < 1.0) {
+    if (!kop && grid->q < 1.0) {
         for (int l = 0; l < h->p; ++l) {
             double s = 0.0;
             for (int v = 0; v < dp; ++v)
@@ -876,6 +903,13 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
                 }
         }
 
+    if (kop) {
+        // the coefficients of a kernel-operator problem are its point values
+        Dm.clear();
+        h->Dfirst.clear();
+        h->p = h->n;
+    }
+
     // device buffers
     hipError_t alloc_err = hipSuccess;
     auto dalloc = [&](void **ptr, size_t bytes) {
@@ -885,15 +919,17 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     // points, channel matrices, coefficients and channel tables in one
     // block (256-byte aligned parts)
     auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t real_size = precision == BSDE_FP32_PATHS ? sizeof(float) : sizeof(double);
     const size_t b_pts = sizeof(double) * h->pts.size(), b_D = sizeof(double) * Dm.size(),
                  b_alpha = sizeof(double) * (size_t)(h->K_it + 1) * h->p,
-                 b_g64 = sizeof(double) * (size_t)pad16(h->p) * pad16(h->C),
-                 b_g32 = sizeof(float) * g32_floats(h);
+                 b_g64 = kop ? 0 : sizeof(double) * (size_t)pad16(h->p) * pad16(h->C),
+                 b_g32 = sizeof(float) * g32_floats(h),
+                 b_ktab = kop ? real_size * kKernelRow * (size_t)h->n : 0;
     const size_t o_D = al256(b_pts), o_alpha = o_D + al256(b_D),
                  o_g64 = o_alpha + al256(b_alpha), o_g32 = o_g64 + al256(b_g64),
-                 n_block = o_g32 + al256(b_g32);
+                 o_ktab = o_g32 + al256(b_g32), n_block = o_ktab + al256(b_ktab);
     bool ok = dalloc(&h->d_block, n_block) &&
-              dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n) &&
+              (kop || dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n)) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
               dalloc((void **)&h->d_c, sizeof(double) * (size_t)h->K_it * h->n) &&
               dalloc((void **)&h->d_var, sizeof(double) * (size_t)h->K_it * h->n);
@@ -911,6 +947,24 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         h->d_alpha = (double *)(b + o_alpha);
         h->d_g64 = (double *)(b + o_g64);
         h->d_g32 = (float *)(b + o_g32);
+        h->d_ktab = kop ? (void *)(b + o_ktab) : nullptr;
+    }
+    // the kernel operator's table: rows {z_0, .., z_d, y = 0} in the path
+    // precision, z the mapped coordinates of the points
+    std::vector<unsigned char> ktab(b_ktab, 0);
+    for (int i = 0; kop && i < h->n; ++i) {
+        double z[kKernelRow] = {0, 0, 0, 0};
+        z[0] = 2.0 * h->pts[(size_t)i * dp] / payoff->T - 1.0;
+        for (int j = 0; j < d; ++j)
+            z[1 + j] = (h->pts[(size_t)i * dp + 1 + j] - b.mid[j]) * b.scale[j];
+        for (int v = 0; v < kKernelRow; ++v) {
+            if (real_size == sizeof(float)) {
+                const float f = (float)z[v];
+                std::memcpy(&ktab[((size_t)i * kKernelRow + v) * real_size], &f, sizeof(f));
+            } else {
+                std::memcpy(&ktab[((size_t)i * kKernelRow + v) * real_size], &z[v], sizeof(double));
+            }
+        }
     }
     // uploads and the set-up kernels go to a set-up stream of the library
     // (non-blocking: a problem created while another one solves does not
@@ -925,14 +979,17 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     if (e == hipSuccess && pin) {
         std::memset(pin, 0, n_block);
         std::memcpy(pin, h->pts.data(), b_pts);
-        std::memcpy((char *)pin + o_D, Dm.data(), b_D);
+        if (b_D) std::memcpy((char *)pin + o_D, Dm.data(), b_D);
+        if (b_ktab) std::memcpy((char *)pin + o_ktab, ktab.data(), b_ktab);
         e = hipMemcpyAsync(h->d_block, pin, n_block, hipMemcpyHostToDevice, us);
     } else if (e == hipSuccess) {
         e = hipMemcpyAsync(h->d_pts, h->pts.data(), b_pts, hipMemcpyHostToDevice, us);
-        if (e == hipSuccess)
+        if (e == hipSuccess && b_D)
             e = hipMemcpyAsync(h->d_D, Dm.data(), b_D, hipMemcpyHostToDevice, us);
         if (e == hipSuccess)
-            e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, n_block - o_alpha, us);
+            e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, o_ktab - o_alpha, us);
+        if (e == hipSuccess && b_ktab)
+            e = hipMemcpyAsync(h->d_ktab, ktab.data(), b_ktab, hipMemcpyHostToDevice, us);
     }
     if (e != hipSuccess) {
         if (us) {
@@ -946,7 +1003,15 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     }
     // pseudo-inverse of the basis matrix of the grid, on the device (it
     // synchronizes the set-up stream: Dm and the points may go out of scope)
-    const bsde_status pst = device_pseudo_inverse(h, act, us);
+    // (the kernel operator fits nothing: only the upload to wait for)
+    bsde_status pst = BSDE_OK;
+    if (!kop) {
+        pst = device_pseudo_inverse(h, act, us);
+    } else {
+        const hipError_t se = hipStreamSynchronize(us);
+        if (se != hipSuccess)
+            pst = fail(BSDE_EDEVICE, std::string("upload: ") + hipGetErrorString(se));
+    }
     setup_stream_put(us);
     pinned_put(pin, pin_cap);
     if (pst != BSDE_OK) {
@@ -999,6 +1064,20 @@ static bsde_status prepare_tiling(bsde_problem h, int &groups, int &ppl)
     return BSDE_OK;
 }
 
+// the Monte Carlo path kernel of h's operator (least squares: the channel
+// table; kernel operator: the point table)
+static hipError_t launch_problem_path(const bsde_problem_s *h, int blocks, hipStream_t s,
+                                      const PathParams &prm, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const bool fp32 = h->precision == BSDE_FP32_PATHS;
+    if (h->kop)
+        return launch_kernel_path(h->d, fp32, blocks, s, prm, h->d_pts, h->d_ktab,
+                                  h->d_partial, ev0, ev1);
+    return launch_path(h->d, h->eta, h->q10, fp32, blocks, s, prm, h->d_pts,
+                       fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
+                       h->d_partial, ev0, ev1);
+}
+
 bsde_status bsde_solve(bsde_problem h, void *hip_stream)
 {
     if (!h) return fail(BSDE_EINVAL, "null handle");
@@ -1022,9 +1101,11 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     } release_events{ev};
     double t_setup = 0.0;
     HIP_TRY(hipEventRecord(ev[0], s));
-    // channel table of the starting coefficients
-    HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                            h->d_D, h->d_g64, h->d_g32, split_of(h)));
+    // channel table of the starting coefficients (the kernel operator's
+    // table already holds the current point values)
+    if (!h->kop)
+        HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
+                                h->d_D, h->d_g64, h->d_g32, split_of(h)));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
         hipEvent_t *e = per ? &ev[2 + (size_t)per * it] : nullptr;
@@ -1048,9 +1129,25 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
         prm.groups = groups;
         prm.paths_per_lane = ppl;
         prm.n = h->n;
-        HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * groups, s, prm, h->d_pts,
-                            fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
-                            h->d_partial, e ? e[0] : nullptr, e ? e[1] : nullptr));
+        HIP_TRY(launch_problem_path(h, h->n * groups, s, prm, e ? e[0] : nullptr,
+                                    e ? e[1] : nullptr));
+        if (h->kop) {
+            // c^k, then y^k = u^k(points) + c^k with u^k = h[y^{k-1}]
+            // (alpha row k; row 0 = 0 is u^0 = 0) into row k + 1 and the table
+            double *ck = h->d_c + (size_t)k * h->n;
+            HIP_TRY(launch_finalize(h->d_partial, h->n, groups, h->M, ck,
+                                    h->d_var + (size_t)k * h->n, s));
+            if (per == 5) HIP_TRY(hipEventRecord(e[2], s));
+            HIP_TRY(launch_kernel_update(prm, h->d, h->d_pts,
+                                         k ? h->d_alpha + (size_t)k * h->p : nullptr, ck,
+                                         h->d_alpha + (size_t)(k + 1) * h->p, h->d_ktab,
+                                         fp32 ? 1 : 0, s));
+            if (per == 5) {
+                HIP_TRY(hipEventRecord(e[3], s));
+                HIP_TRY(hipEventRecord(e[4], s));
+            }
+            continue;
+        }
         HIP_TRY(launch_update(h->n, groups, h->M, h->p, h->C, s, h->d_partial,
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
@@ -1378,6 +1475,8 @@ bsde_status bsde_solve_batch(bsde_problem *problems, int count,
             if (problems[r] == problems[q]) return fail(BSDE_EINVAL, "duplicate handle in batch");
         if (problems[q]->redraw)
             return fail(BSDE_EUNSUPPORTED, "points redrawn every iteration: use bsde_solve");
+        if (problems[q]->kop)
+            return fail(BSDE_EUNSUPPORTED, "the kernel operator: use bsde_solve");
     }
     hipStream_t s = (hipStream_t)hip_stream;
     hipStream_t own = nullptr;
@@ -1416,8 +1515,9 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
         h->partial_cap = need;
     }
     const int k = std::min(h->k_done, h->K_it - 1);
-    HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                            h->d_D, h->d_g64, h->d_g32, split_of(h)));
+    if (!h->kop)
+        HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
+                                h->d_D, h->d_g64, h->d_g32, split_of(h)));
     hipEvent_t e0, e1;
     HIP_TRY(event_get(&e0));
     HIP_TRY(event_get(&e1));
@@ -1431,9 +1531,7 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
         prm.n = h->n;
         double t_min = 1e300;
         for (int rep = 0; rep < 5; ++rep) { // first launch warms up
-            HIP_TRY(launch_path(h->d, h->eta, h->q10, fp32, h->n * c.first, s, prm, h->d_pts,
-                                fp32 ? (const void *)h->d_g32 : (const void *)h->d_g64,
-                                h->d_partial, e0, e1));
+            HIP_TRY(launch_problem_path(h, h->n * c.first, s, prm, e0, e1));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1519,6 +1617,7 @@ bsde_status bsde_set_coefficients(bsde_problem h, const double *alpha,
 {
     if (!h || !alpha) return fail(BSDE_EINVAL, "null argument");
     if (k_done < 0 || k_done > h->K_it) return fail(BSDE_EINVAL, "bad k_done");
+    if (h->kop) return fail(BSDE_EUNSUPPORTED, "the kernel operator runs whole solves");
     return store_alpha(h, alpha, k_done);
 }
 
@@ -1526,6 +1625,7 @@ bsde_status bsde_fit_values(bsde_problem h, const double *y, int k_done)
 {
     if (!h || !y) return fail(BSDE_EINVAL, "null argument");
     if (k_done < 0 || k_done > h->K_it) return fail(BSDE_EINVAL, "bad k_done");
+    if (h->kop) return fail(BSDE_EUNSUPPORTED, "the kernel operator fits no basis");
     // alpha = R^{-1} Q' y with the device copy of W, evaluated on the host
     std::vector<double> W((size_t)h->p * h->n);
     HIP_TRY(hipMemcpy(W.data(), h->d_W, sizeof(double) * W.size(), hipMemcpyDeviceToHost));
@@ -1557,6 +1657,47 @@ bsde_status bsde_query_price_delta(bsde_problem h, int nq, const double *t,
     if (!h->have_alpha) return fail(BSDE_ESTATE, "no coefficients yet");
     const int d = h->d, dp = d + 1, p = h->p;
     const double *alpha = &h->alpha_hist[(size_t)h->k_done * p];
+    if (h->kop) {
+        // u = h[y] = S1 / S0 and d_{x_j} u = scale_j (d_j S1 - u d_j S0) / S0
+        // over the points (FP64, the clamped Gaussian weights)
+        const double b2 = h->base.kbw * h->base.kbw;
+        for (int qi = 0; qi < nq; ++qi) {
+            double z[kMaxD + 1];
+            z[0] = 2.0 * t[qi] / h->base.T - 1.0;
+            for (int j = 0; j < d; ++j) {
+                if (!(S[(size_t)qi * d + j] > 0.0)) return fail(BSDE_EINVAL, "price must be > 0");
+                z[1 + j] = (std::log(S[(size_t)qi * d + j]) - h->base.mid[j]) * h->base.scale[j];
+            }
+            double S0 = 0.0, S1 = 0.0, D0[kMaxD] = {0}, D1[kMaxD] = {0};
+            for (int i = 0; i < h->n; ++i) {
+                double dz[kMaxD + 1], q = 0.0;
+                dz[0] = z[0] - (2.0 * h->pts[(size_t)i * dp] / h->base.T - 1.0);
+                q = dz[0] * dz[0];
+                for (int j = 0; j < d; ++j) {
+                    dz[1 + j] = z[1 + j] - (h->pts[(size_t)i * dp + 1 + j] - h->base.mid[j]) *
+                                               h->base.scale[j];
+                    q += dz[1 + j] * dz[1 + j];
+                }
+                const double e = q / (2.0 * b2);
+                const bool flat = e > kKernelClamp;
+                const double w = std::exp(-(flat ? kKernelClamp : e));
+                S0 += w;
+                S1 += alpha[i] * w;
+                if (flat) continue;
+                for (int j = 0; j < d; ++j) {
+                    D0[j] += w * (-dz[1 + j] / b2);
+                    D1[j] += alpha[i] * w * (-dz[1 + j] / b2);
+                }
+            }
+            const double u = S1 / S0;
+            price[qi] = u;
+            if (delta)
+                for (int j = 0; j < d; ++j)
+                    delta[(size_t)qi * d + j] =
+                        (D1[j] - u * D0[j]) / S0 * h->base.scale[j] / S[(size_t)qi * d + j];
+        }
+        return BSDE_OK;
+    }
     const size_t pp = (size_t)p * p;
     std::vector<double> g((size_t)d * p, 0.0); // d_{x_j} coefficients
     for (int j = 0; j < d; ++j)

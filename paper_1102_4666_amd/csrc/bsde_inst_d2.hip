@@ -1,5 +1,6 @@
 // bsde_inst_d2.hip -- path kernels for d = 2: eta in {2, 3, 4, 5}, FP32 and
 // FP64 paths; the Dupire-type volatility at eta = 3.
+// Also the path kernels of the kernel operator of Section 3.2.
 #include "bsde_path.h"
 
 namespace bsde {
@@ -7,4 +8,5 @@ namespace bsde {
     X(2, 10, true, false) X(3, 10, true, true) X(4, 10, true, false)           \
     X(5, 10, true, false)
 BSDE_DEFINE_DIMENSION(2, SETS_D2)
+BSDE_DEFINE_KERNEL_OP(2)
 } // namespace bsde

@@ -32,8 +32,13 @@ struct bsde_problem_s {
            *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
            *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
     float *d_g32 = nullptr;
-    // d_pts, d_D, d_alpha, d_g64 and d_g32 live in this one allocation
+    // d_pts, d_D, d_alpha, d_g64, d_g32 and d_ktab live in this one allocation
     void *d_block = nullptr;
+    // kernel operator of Section 3.2 (kop): bandwidth and the path kernel's
+    // table of rows {z_0, .., z_d, y} (FP32 or FP64 as the paths); d_alpha
+    // then holds the point values y (p = n)
+    bool kop = false;
+    void *d_ktab = nullptr;
     size_t partial_cap = 0;
     // state
     int k_done = 0;

@@ -177,6 +177,68 @@ __global__ __launch_bounds__(256) void batch_channel_kernel(
                     blockIdx.x, q.g64, q.g32, q.split);
 }
 
+// Point values of the kernel operator (Section 3.2) for the next iteration:
+// y^k_i = u^k(t_i, x_i) + c^k_i with u^k = h[y^{k-1}] = sum_j y_j w_j /
+// sum_j w_j (FP64), w_j = exp(-min(|z_i - z_j|^2 / (2 b^2), clamp)) in the
+// mapped coordinates; yprev null for u^k = 0.  Writes y^k (FP64) and the y
+// column of the path kernel's table (FP32 or FP64).  One lane per point;
+// the loop over the points j is uniform (scalar loads of their rows).
+__global__ __launch_bounds__(256) void kernel_update_kernel(
+    const PathParams prm, int d, const double *__restrict__ pts,
+    const double *__restrict__ yprev, const double *__restrict__ c,
+    double *__restrict__ ynew, void *__restrict__ table, int fp32)
+{
+    const int n = prm.n;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int dp = d + 1;
+    const double inv2b2 = 0.5 / (prm.kbw * prm.kbw);
+    double zi[kMaxD + 1];
+    zi[0] = 2.0 * pts[(size_t)i * dp] / prm.T - 1.0;
+    for (int j = 0; j < d; ++j)
+        zi[1 + j] = (pts[(size_t)i * dp + 1 + j] - prm.mid[j]) * prm.scale[j];
+    double u = 0.0;
+    if (yprev) {
+        double S0 = 0.0, S1 = 0.0;
+        for (int q = 0; q < n; ++q) {
+            const double *row = pts + (size_t)q * dp;
+            double dz = zi[0] - (2.0 * row[0] / prm.T - 1.0);
+            double qq = dz * dz;
+            for (int j = 0; j < d; ++j) {
+                dz = zi[1 + j] - (row[1 + j] - prm.mid[j]) * prm.scale[j];
+                qq += dz * dz;
+            }
+            const double w = exp(-fmin(qq * inv2b2, kKernelClamp));
+            S0 += w;
+            S1 += yprev[q] * w;
+        }
+        u = S1 / S0;
+    }
+    const double y = u + c[i];
+    ynew[i] = y;
+    if (fp32)
+        ((float *)table)[(size_t)i * kKernelRow + 1 + d] = (float)y;
+    else
+        ((double *)table)[(size_t)i * kKernelRow + 1 + d] = y;
+}
+
+hipError_t launch_kernel_update(const PathParams &prm, int d, const double *pts,
+                                const double *yprev, const double *c, double *ynew,
+                                void *table, int fp32, hipStream_t s)
+{
+    hipLaunchKernelGGL(kernel_update_kernel, dim3((prm.n + 255) / 256), dim3(256), 0, s,
+                       prm, d, pts, yprev, c, ynew, table, fp32);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partial, int n, int groups, int M,
+                           double *c, double *var, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                       partial, n, groups, M, c, var);
+    return hipGetLastError();
+}
+
 __global__ void reset_counters_kernel(unsigned int *c, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -230,6 +292,33 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
     bool has_variant_d##D(int eta, int q10, bool fp32, int vol);
 BSDE_DIMS(DECL)
 #undef DECL
+hipError_t launch_kernel_path_d1(bool fp32, int blocks, hipStream_t s,
+                                 const PathParams &prm, const double *pts,
+                                 const void *table, double *partial,
+                                 hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_kernel_path_d2(bool fp32, int blocks, hipStream_t s,
+                                 const PathParams &prm, const double *pts,
+                                 const void *table, double *partial,
+                                 hipEvent_t ev0, hipEvent_t ev1);
+
+// path kernels of the kernel operator exist for d <= 2, constant and bump
+// volatility, FP32 and FP64 paths
+bool kernel_op_exists(int d, int vol)
+{
+    return (d == 1 || d == 2) && (vol == kVolConst || vol == kVolBump);
+}
+
+hipError_t launch_kernel_path(int d, bool fp32, int blocks, hipStream_t s,
+                              const PathParams &prm, const double *pts,
+                              const void *table, double *partial,
+                              hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (d == 1)
+        return launch_kernel_path_d1(fp32, blocks, s, prm, pts, table, partial, ev0, ev1);
+    if (d == 2)
+        return launch_kernel_path_d2(fp32, blocks, s, prm, pts, table, partial, ev0, ev1);
+    return hipErrorInvalidValue;
+}
 
 int index_table(int d, int eta, int q10, int8_t *nu, int cap)
 {

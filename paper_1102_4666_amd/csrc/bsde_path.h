@@ -270,7 +270,8 @@ __device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t
 // Gamma is read-only, uniform across the workgroup and read once per basis
 // function and channel per path: its loads must stay scalar (SGPR) loads,
 // so GammaPtr is a global restrict pointer or a constant-address-space one.
-template <int D, int ETA, typename Real, int VOL, int Q, typename GammaPtr>
+template <int D, int ETA, typename Real, int VOL, int Q, typename GammaPtr,
+          int OP = kOpBasis>
 __device__ __forceinline__ void run_tile(const PathParams &prm,
                                          const double *__restrict__ pts,
                                          GammaPtr gamma, const int i,
@@ -455,7 +456,99 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         // Phi(X_T) - u^k(T, X_T)
         Real phi_tau = payoff<D>(prm.payoff, K, Xt);
         Real u = Real(0), gen = Real(0), uT = Real(0), terminal;
-        if constexpr (!kMfma) {
+        if constexpr (OP == kOpKernel) {
+            // u^k = h[y] of the kernel operator (Section 3.2) in its
+            // normalised form h = S1 / S0, S0 = sum_i w_i, S1 = sum_i y_i w_i,
+            // w_i = exp(-min(|z - z_i|^2 / (2 b^2), clamp)) in the mapped
+            // coordinates z; a clamped weight is constant (no derivative).
+            // With L the frozen generator (d_t + b*.grad + sum_jk a_jk d_jk,
+            // a_jk = sigma*_j sigma*_k C_jk / 2), in z units,
+            //   L h = [L S1 - h L S0 - 2 sum_jk a_jk d_j h d_k S0] / S0,
+            //   d_j h = (d_j S1 - h d_j S0) / S0,
+            // and L w_i / w_i = l(dz), the polynomial below.  The table rows
+            // {z_0, .., z_d, y} are uniform across the workgroup (scalar loads).
+            const Real b2 = Real(prm.kbw * prm.kbw);
+            const Real inv2b2 = Real(0.5) / b2, invb2 = Real(1) / b2;
+            const Real clamp = Real(kKernelClamp);
+            Real zt[DP], zT[DP];
+            zt[0] = tau * tscale - Real(1);
+            zT[0] = Real(1);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                zt[1 + j] = (Xt[j] - ac.mid[j]) * ac.scale[j];
+                zT[1 + j] = (X[j] - ac.mid[j]) * ac.scale[j];
+            }
+            // l(dz) = c0 + ct dz_0 + sum_j cj dz_j + sum_{j<=k} cjk dz_j dz_k
+            Real ajk[D][D];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    ajk[j][k] = Real(0.5) * sgs[j] * sgs[k] * (j == k ? Real(1) : rho) *
+                                ac.scale[j] * ac.scale[k];
+            const Real ct = -tscale * invb2;
+            Real cj[D], cjk[D][D], c0 = Real(0);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                cj[j] = -bst[j] * ac.scale[j] * invb2;
+                c0 -= ajk[j][j] * invb2;
+#pragma unroll
+                for (int k = j; k < D; ++k)
+                    cjk[j][k] = (j == k ? ajk[j][j] : Real(2) * ajk[j][k]) * invb2 * invb2;
+            }
+            Real S0 = 0, S1 = 0, L0 = 0, L1 = 0, S0T = 0, S1T = 0;
+            Real G0[D], G1[D]; // sum w dz_j and sum y w dz_j (unclamped weights)
+#pragma unroll
+            for (int j = 0; j < D; ++j) G0[j] = G1[j] = Real(0);
+#pragma unroll 4
+            for (int q = 0; q < prm.n; ++q) {
+                const auto row = gamma + (size_t)q * kKernelRow;
+                Real dz[DP], qq = Real(0), qT = Real(0);
+#pragma unroll
+                for (int v = 0; v < DP; ++v) {
+                    dz[v] = zt[v] - row[v];
+                    qq = fma(dz[v], dz[v], qq);
+                    const Real dT = zT[v] - row[v];
+                    qT = fma(dT, dT, qT);
+                }
+                const Real y = row[1 + D];
+                const Real e = qq * inv2b2;
+                const bool flat = e > clamp;
+                const Real w = Arith<Real>::exp(-fmin(e, clamp));
+                const Real wy = w * y;
+                S0 += w;
+                S1 += wy;
+                const Real wd = flat ? Real(0) : w, wyd = flat ? Real(0) : wy;
+                Real l = fma(ct, dz[0], c0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    l = fma(cj[j], dz[1 + j], l);
+#pragma unroll
+                    for (int k = j; k < D; ++k) l = fma(cjk[j][k], dz[1 + j] * dz[1 + k], l);
+                    G0[j] = fma(wd, dz[1 + j], G0[j]);
+                    G1[j] = fma(wyd, dz[1 + j], G1[j]);
+                }
+                L0 = fma(wd, l, L0);
+                L1 = fma(wyd, l, L1);
+                const Real wT = Arith<Real>::exp(-fmin(qT * inv2b2, clamp));
+                S0T += wT;
+                S1T = fma(wT, y, S1T);
+            }
+            u = S1 / S0;
+            // d_j S = -G_j / b^2 (z units), d_j h = (d_j S1 - h d_j S0) / S0
+            Real hj[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) hj[j] = -(G1[j] - u * G0[j]) * invb2 / S0;
+            Real acc = L1 - u * L0;
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    acc -= Real(2) * ajk[j][k] * hj[j] * (-G0[k] * invb2);
+            gen = acc / S0;
+            uT = S1T / S0T;
+            terminal = payoff<D>(prm.payoff, K, X) - uT;
+        } else if constexpr (!kMfma) {
             Real Bv[NP], BT[NP];
             Real V[C];
 #pragma unroll
@@ -811,15 +904,15 @@ constexpr int min_waves()
 
 // One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
 // writes its sums to partial[2 b].
-template <int D, int ETA, typename Real, int VOL, int Q>
+template <int D, int ETA, typename Real, int VOL, int Q, int OP = kOpBasis>
 __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL>())) void path_kernel(
     const PathParams prm, const double *__restrict__ pts,
     const Real *__restrict__ gamma, double *__restrict__ partial)
 {
     const int i = blockIdx.x / prm.groups;
     const int g = blockIdx.x - i * prm.groups;
-    run_tile<D, ETA, Real, VOL, Q>(prm, pts, gamma, i, g,
-                                partial + 2 * (size_t)blockIdx.x);
+    run_tile<D, ETA, Real, VOL, Q, const Real *__restrict__, OP>(
+        prm, pts, gamma, i, g, partial + 2 * (size_t)blockIdx.x);
 }
 
 // Many problems of one kernel signature in one persistent launch.  Tiles
@@ -909,6 +1002,26 @@ int copy_index_table(int8_t *nu, int cap)
 // Defines launch_path_dD, index_table_dD, launch_batch_dD,
 // batch_occupancy_dD and has_variant_dD for the (eta, q-norm, FP64, Dupire)
 // sets listed by SETS(X) as X(E, Q, FP64, DUP), with q = Q / 10.
+// Path kernels of the kernel operator (Section 3.2) for d = D: FP32 and
+// FP64 paths, constant and bump volatility; table = rows {z, y}
+#define BSDE_DEFINE_KERNEL_OP(D)                                               \
+    hipError_t launch_kernel_path_d##D(bool fp32, int blocks, hipStream_t s,   \
+                                       const PathParams &prm,                  \
+                                       const double *pts, const void *table,   \
+                                       double *partial, hipEvent_t ev0,        \
+                                       hipEvent_t ev1)                         \
+    {                                                                          \
+        return dispatch_variant<D, 1, true, false>(                            \
+            fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
+                using R = typename decltype(rt)::type;                         \
+                hipExtLaunchKernelGGL(                                         \
+                    (path_kernel<D, 1, R, decltype(vt)::value, 10, kOpKernel>), \
+                    dim3(blocks), dim3(kBlock), 0, s, ev0, ev1, 0u, prm, pts,  \
+                    (const R *)table, partial);                                \
+                return hipGetLastError();                                      \
+            });                                                                \
+    }
+
 #define BSDE_DEFINE_DIMENSION(D, SETS)                                         \
     hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,       \
                                 hipStream_t s,                                 \

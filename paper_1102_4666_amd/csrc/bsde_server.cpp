@@ -257,6 +257,8 @@ bsde_status bsde_server_submit(bsde_server S, const bsde_request *req,
     if (d < 1 || d > kMaxD) return fail(BSDE_EINVAL, "d must be in [1, 10]");
     if (req->grid.redraw)
         return fail(BSDE_EUNSUPPORTED, "points redrawn every iteration are not served");
+    if (req->grid.kernel_bw != 0.0)
+        return fail(BSDE_EUNSUPPORTED, "the kernel operator is not served");
     auto *q = new (std::nothrow) Request();
     if (!q) return fail(BSDE_ENOMEM, "host allocation");
     q->d = d;

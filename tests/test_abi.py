@@ -43,6 +43,11 @@ def test_status_strings():
     (dict(d=3, rho=-0.6, vol_level=0.2, S0=100.0, eta=3), 1),
     (dict(eta=7), 6), (dict(d=4, vol_level=0.2, S0=100.0, eta=3), 6),
     (dict(n_t=2, n_x=3, eta=4), 3),  # 6 points < 15 basis functions
+    # the kernel operator: bandwidth > 0, d <= 2, no redraw, no Dupire vol
+    (dict(kernel_bw=-0.1), 1), (dict(kernel_bw=float("inf")), 1),
+    (dict(d=3, vol_level=0.2, S0=100.0, eta=2, kernel_bw=0.3), 6),
+    (dict(grid="random", redraw=1, kernel_bw=0.3), 6),
+    (dict(vol_kind="dupire", kernel_bw=0.3), 6),
 ])
 def test_invalid_arguments(bad, status):
     cfg = problem(**bad)

@@ -1,0 +1,108 @@
+"""The kernel operator of Section 3.2 on the GPU: parity with the oracle
+(same Philox streams, element by element on the per-point corrections and
+point values of every iteration, the price and the deltas), the entry
+points that do not take it, and the European put it converges to."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close_c, run_gpu
+from workloads import problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": dict(c=1e-8, price=1e-6, delta=1e-6),
+       "fp32": dict(c=2e-3, price=5e-4, delta=5e-3)}
+
+CASES = {
+    # d = 1 European put, Black-Scholes, tensor grid
+    "eur_bs": problem(d=1, n_t=6, n_x=20, eta=2, M=300, N=7, K_it=3,
+                      kernel_bw=0.2),
+    # d = 1 American put (penalty 1), bump local vol, ragged M
+    "amer_bump": problem(d=1, vol_kind="bump", bump_a=0.25, n_t=5, n_x=17,
+                         eta=2, M=333, N=9, K_it=3, omega=1.0, kernel_bw=0.15),
+    # d = 2 correlated basket put on random points, dividends
+    "d2_basket": problem(d=2, vol_kind="bump", vol_level=[0.2, 0.3],
+                         bump_a=0.25, rho=0.3, div=[0.0, 0.02],
+                         S0=[100.0, 95.0], grid="random", n_t=4, n_x=30,
+                         eta=2, M=260, N=6, K_it=3, omega=1.0, kernel_bw=0.3),
+    # points (t, x) uniform over [0, T] x D
+    "d2_uniform": problem(d=2, vol_level=[0.25, 0.2], rho=-0.2, payoff="call",
+                          S0=[100.0, 100.0], grid="uniform", n_x=150, eta=2,
+                          M=200, N=5, K_it=2, kernel_bw=0.35),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_results():
+    return {}
+
+
+def _oracle(cache, name):
+    if name not in cache:
+        cfg = CASES[name]
+        res = oracle.solve(cfg)
+        pr, de = oracle.price_delta(cfg, res["alpha"][-1], [0.0], [cfg["S0"]])
+        res["price"], res["delta"] = pr[0], de[0]
+        cache[name] = res
+    return cache[name]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_kernel_operator_parity(name, prec, oracle_results):
+    cfg = dict(CASES[name], precision=prec)
+    print("kernel-operator case", name, prec, flush=True)
+    ref = _oracle(oracle_results, name)
+    got = run_gpu(cfg)
+    tol = TOL[prec]
+    np.testing.assert_allclose(got["pts"], oracle.points(cfg), rtol=1e-15, atol=1e-15)
+    assert_close_c(got["c"], ref["c"], tol["c"], "c")
+    # the point values y^k (coefficient rows; row 0 = 0 is u^0)
+    assert np.all(got["alpha"][0] == 0.0)
+    assert_close_c(got["alpha"], ref["alpha"], tol["c"] * 3, "y")
+    K = cfg["K"]
+    assert abs(got["price"] - ref["price"]) <= tol["price"] * K, (got["price"], ref["price"])
+    np.testing.assert_allclose(got["delta"], ref["delta"], rtol=0, atol=tol["delta"])
+
+
+def test_kernel_operator_rejections():
+    from paper_1102_4666_amd import BsdeError, Problem, Server, solve_batch
+    cfg = CASES["eur_bs"]
+    with Problem(cfg) as P:
+        with pytest.raises(BsdeError) as e:
+            solve_batch([P])
+        assert e.value.status == 6
+        with pytest.raises(BsdeError) as e:
+            P.set_coefficients(np.zeros(P.p), 0)
+        assert e.value.status == 6
+        assert P.p == P.n
+    with Server(1 << 30) as S:
+        with pytest.raises(BsdeError) as e:
+            S.submit(cfg)
+        assert e.value.status == 6
+
+
+def _bs_put(S, K, r, sig, T):
+    d1 = (math.log(S / K) + (r + 0.5 * sig * sig) * T) / (sig * math.sqrt(T))
+    d2 = d1 - sig * math.sqrt(T)
+    N = lambda x: 0.5 * math.erfc(-x / math.sqrt(2.0))
+    return K * math.exp(-r * T) * N(-d2) - S * N(-d1), N(d1) - 1.0
+
+
+def test_kernel_operator_european_put_near_black_scholes():
+    # the first version of the method on a fine grid with a narrow window:
+    # the price is the Black-Scholes one up to the smoothing bias of the
+    # window and the Monte Carlo error (FP64 paths, M = 20000).  The window
+    # is 0.05 x 0.8 = 0.04 in log-price, a bias of about
+    # u_xx 0.04^2 / 2 = 157 x 0.0008 = +0.13 at the money (measured +0.115)
+    cfg = problem(d=1, n_t=16, n_x=96, eta=2, M=20000, N=20, K_it=5,
+                  kernel_bw=0.05, precision="fp64", seed=11)
+    got = run_gpu(cfg)
+    ref, dref = _bs_put(100.0, 100.0, 0.05, 0.2, 1.0)
+    print("kernel operator price %.5f delta %.5f, Black-Scholes %.5f %.5f"
+          % (got["price"], got["delta"][0], ref, dref), flush=True)
+    assert 0.0 < got["price"] - ref < 0.03 * ref
+    assert abs(got["delta"][0] - dref) < 0.01

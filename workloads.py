@@ -35,6 +35,7 @@ def problem(**kw) -> dict:
         "S0": [100.0],
         "grid": "tensor",      # tensor | random
         "redraw": 0,           # random grid: new points every iteration
+        "kernel_bw": 0.0,      # > 0: the kernel operator (Section 3.2)
         "n_t": 8,
         "n_x": 16,
         "width": 4.0,
@@ -103,6 +104,16 @@ def geo_basket_d5(omega: float = 100.0, precision: str = "fp32",
                    M=1000, N=50, K_it=10, precision=precision, seed=0)
 
 
+def eur_put_d1_kernel(precision: str = "fp32") -> dict:
+    """d=1 European put, Black-Scholes sigma=0.2, with the kernel operator of
+    Section 3.2 (bandwidth 0.1 in the mapped coordinates) in place of least
+    squares: 64 space x 8 time points, M=1000, N=20, 5 Picard iterations."""
+    return problem(d=1, vol_kind="const", vol_level=0.2, r=0.05, K=100.0,
+                   S0=100.0, T=1.0, payoff="put", omega=0.0, grid="tensor",
+                   n_t=8, n_x=64, eta=2, M=1000, N=20, K_it=5,
+                   kernel_bw=0.1, precision=precision, seed=0)
+
+
 def serving_request(idx: int, rng: np.random.Generator,
                     dims=(1, 2, 5, 10)) -> dict:
     """One request of the serving mix: d drawn from dims, strike U[80,120],
@@ -131,4 +142,5 @@ def serving_request(idx: int, rng: np.random.Generator,
 
 
 WORKLOADS = {"eur_put_d1": eur_put_d1, "amer_put_d1": amer_put_d1,
-             "amer_basket_d2": amer_basket_d2, "geo_basket_d5": geo_basket_d5}
+             "amer_basket_d2": amer_basket_d2, "geo_basket_d5": geo_basket_d5,
+             "eur_put_d1_kernel": eur_put_d1_kernel}
