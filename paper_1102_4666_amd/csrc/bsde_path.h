@@ -468,8 +468,16 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             // and L w_i / w_i = l(dz), the polynomial below.  The table rows
             // {z_0, .., z_d, y} are uniform across the workgroup (scalar loads).
             const Real b2 = Real(prm.kbw * prm.kbw);
-            const Real inv2b2 = Real(0.5) / b2, invb2 = Real(1) / b2;
-            const Real clamp = Real(kKernelClamp);
+            const Real invb2 = Real(1) / b2;
+            // FP32: the exponent in base 2 (log2 e folded into the scale and
+            // the clamp), so that a weight is one v_exp_f32
+            constexpr bool kF32 = sizeof(Real) == 4;
+            const Real kq = Real(0.5 / (prm.kbw * prm.kbw) * (kF32 ? 1.4426950408889634 : 1.0));
+            const Real clamp = Real(kKernelClamp * (kF32 ? 1.4426950408889634 : 1.0));
+            auto weight = [&](Real e) {
+                if constexpr (kF32) return __builtin_amdgcn_exp2f(-fminf(e, clamp));
+                else return ::exp(-fmin(e, clamp));
+            };
             Real zt[DP], zT[DP];
             zt[0] = tau * tscale - Real(1);
             zT[0] = Real(1);
@@ -512,9 +520,9 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                     qT = fma(dT, dT, qT);
                 }
                 const Real y = row[1 + D];
-                const Real e = qq * inv2b2;
+                const Real e = qq * kq;
                 const bool flat = e > clamp;
-                const Real w = Arith<Real>::exp(-fmin(e, clamp));
+                const Real w = weight(e);
                 const Real wy = w * y;
                 S0 += w;
                 S1 += wy;
@@ -530,7 +538,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 }
                 L0 = fma(wd, l, L0);
                 L1 = fma(wyd, l, L1);
-                const Real wT = Arith<Real>::exp(-fmin(qT * inv2b2, clamp));
+                const Real wT = weight(qT * kq);
                 S0T += wT;
                 S1T = fma(wT, y, S1T);
             }
