@@ -32,6 +32,13 @@ CASES = {
     "d2_uniform": problem(d=2, vol_level=[0.25, 0.2], rho=-0.2, payoff="call",
                           S0=[100.0, 100.0], grid="uniform", n_x=150, eta=2,
                           M=200, N=5, K_it=2, kernel_bw=0.35),
+    # a narrow window: the points farther than 11 windows (most of them)
+    # sit at the clamp
+    "d1_clamped": problem(d=1, vol_kind="bump", bump_a=0.25, n_t=4, n_x=8,
+                          eta=2, M=100, N=5, K_it=2, omega=1.0, kernel_bw=0.08),
+    # degenerate sizes: two points, one path, one Euler step
+    "d1_tiny": problem(d=1, n_t=2, n_x=1, eta=2, M=1, N=1, K_it=2, K=110.0,
+                       kernel_bw=0.5, seed=4),
 }
 
 
