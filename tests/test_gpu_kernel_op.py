@@ -113,3 +113,22 @@ def test_kernel_operator_european_put_near_black_scholes():
           % (got["price"], got["delta"][0], ref, dref), flush=True)
     assert 0.0 < got["price"] - ref < 0.03 * ref
     assert abs(got["delta"][0] - dref) < 0.01
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kernel_operator_full_size_sampled(prec):
+    # the measured workload at its full size (512 points, M = 1000, N = 20),
+    # two iterations in the default tiling: every correction of iteration 0
+    # and sampled corrections of iteration 1, each from the oracle's own
+    # point values y^0 (no GPU output feeds the oracle)
+    import workloads
+    cfg = dict(workloads.eur_put_d1_kernel(precision=prec), K_it=2)
+    got = run_gpu(cfg)
+    n = len(got["pts"])
+    c0, _ = oracle.corrections(cfg, None, 0, 0, n)
+    tol = TOL[prec]["c"]
+    assert_close_c(got["c"][0], c0, tol, "c0")
+    sample = np.random.default_rng(5).choice(n, 12, replace=False)
+    for i in sample:
+        c1, _ = oracle.corrections(cfg, c0, 1, int(i), int(i) + 1)
+        assert_close_c(got["c"][1][i:i + 1], c1, tol, "c1[%d]" % i)
