@@ -28,8 +28,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 CUs x 4 SIMDs x 16 lanes per cycle at 2.4 GHz.
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # 3.93e13 full-rate lane-ops/s
+# MI355X (gfx950): 256 CUs x 4 SIMDs at 2.4 GHz.  The path kernel is bound
+# by vector-ALU issue; its roofline counts shader cycles of issue per SIMD:
+# peak = 1024 SIMDs x 2.4e9 cycles/s.
+SIMD_ISSUE_CYCLES_PEAK = 256 * 4 * 2.4e9
 FP32_VECTOR_PEAK = 157.3e12                     # FLOP/s (packed FMA)
 FP64_VECTOR_PEAK = 78.6e12
 # HBM traffic of one path-kernel launch of the benchmark workload, from
@@ -37,8 +39,8 @@ FP64_VECTOR_PEAK = 78.6e12
 # tiling (workgroups per point), scaled by the plain-copy calibration
 # factors (x2.0 and x1.0).  The autotuner picks the tiling at run time;
 # a tiling missing here reports null.
-TRAFFIC_KIB = {"fp32": {1: (179, 64), 2: (307, 128), 4: (307, 256),
-                        8: (307, 512), 16: (309, 1024)},
+TRAFFIC_KIB = {"fp32": {1: (177, 64), 2: (305, 128), 4: (305, 256),
+                        8: (305, 512), 16: (305, 1024)},
                "fp64": {1: (268, 64), 2: (396, 128), 4: (396, 256),
                         8: (396, 512), 16: (398, 1024)}}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
@@ -51,26 +53,55 @@ def traffic_bytes(precision, groups):
     return (fw[0] * FETCH_FACTOR + fw[1] * WRITE_FACTOR) * 1024
 
 
-# Algorithmic work per Euler path-step of the path kernel for the d = 1
-# local-volatility workload (N = 50 steps per path), derived operation by
-# operation in the design doc section 6.  VALU operations: normal 13.25 (1/4 of a
-# Philox4x32-10 block) + Box-Muller 5 + local vol 3 + Euler 3 + state at
-# j* 1 + per-path work 270 / N = 30.65, of which 3.12 are transcendentals.
-# The counters show the transcendentals issuing beside the other VALU work
-# (every instruction at 4 cycles would exceed the issue peak), so the
-# roofline counts the 27.53 others against the VALU issue rate.  FP32 FLOP
-# (FMA = 2, transcendental = 1): Box-Muller 4.5 + local vol 4 + Euler 6 +
-# per-path work 250 / N.  FP64 paths use software transcendentals with no
-# independent operation count: their figure is the measured SQ_INSTS_VALU
-# minus SQ_INSTS_VALU_TRANS_F64 per path-step (162.7 - 1.1).
-OPS_PER_PATH_STEP = {"fp32": 13.25 + 5.0 + 3 + 3 + 1 + 270 / 50.0 - 3.12,
-                     "fp64": 161.6}
+# Algorithmic issue cycles per Euler path-step of one wave (64 paths) for
+# the d = 1 local-volatility workload (N = 50 steps per path), derived
+# operation by operation in the design doc section 6.  Issue cost per wave64
+# instruction on gfx950, measured by paper_1102_4666_amd/probe/issue_rates.hip
+# (profiles/valu_issue_rates_gfx950.md): 32-bit adds, multiplies, fused
+# multiply-adds and logic operations (v_bitop3_b32 included) whose operands
+# are all vector registers 2 cycles at best (2.1-3.3 measured), the same
+# with a scalar or literal operand 4, 64-bit multiply-adds, 32-bit integer
+# multiplies, conversions and funnel shifts 4, transcendentals 8 (they do
+# not issue beside other vector instructions).  Each operation is priced at
+# the cheapest form that computes it, so the bound is an optimistic one.
+ISSUE_CYCLES_PER_WAVE_STEP = {
+    "fp32": {
+        # 1/4 Philox4x32-10 block (the work on the uniform counter words and
+        # on m alone done once per path or on the scalar unit): 16
+        # v_mad_u64_u32 (4), two XORs and one three-input XOR with a uniform
+        # operand (4), 15 three-input XORs (2): 106
+        "normal_philox": (16 * 4 + 3 * 4 + 15 * 2) / 4,
+        # 1/2 Box-Muller pair: conversion, funnel shift (4); log, sqrt, sin,
+        # cos (8); fused multiply-add and three multiplies (2)
+        "normal_box_muller": (2 * 4 + 4 * 8 + 4 * 2) / 2,
+        # volatility: y*y (2), exp (8), fused multiply-add (2)
+        "local_vol": 2 + 8 + 2,
+        # Euler update: two fused multiply-adds and an add (2)
+        "euler": 3 * 2,
+        # the compare that selects step j* (2)
+        "record": 2,
+        # per path over N = 50: U and bridge blocks (2 x 106), one Box-Muller
+        # pair (48), 156 other operations at 2 (j*, theta, tau, X_tau, two
+        # Chebyshev rows, the 15 x 4 contraction and u(T), driver and
+        # generator, FP64 sums)
+        "per_path": (2 * 106 + 48 + 156 * 2) / 50.0,
+    },
+    # FP64 paths use software transcendentals with no independent operation
+    # count: the measured instructions per path-step, SQ_INSTS_VALU minus
+    # SQ_INSTS_VALU_TRANS_F64 (162.7 - 1.1) at 4 cycles and 1.1 at 8
+    "fp64": {"measured": 161.6 * 4 + 1.1 * 8},
+}
 FP32_FLOP_PER_PATH_STEP = 4.5 + 4 + 6 + 250 / 50.0
 
 
 def workload(precision: str, omega: float = 100.0):
     import workloads
     return workloads.amer_put_d1(omega=omega, precision=precision)
+
+
+# (groups per point, paths per lane) set on every job by --tiling, in place
+# of the autotuned choice
+FORCED_TILING = None
 
 
 def run_job(cfg, stream, phases=None, solve_lock=None):
@@ -80,6 +111,8 @@ def run_job(cfg, stream, phases=None, solve_lock=None):
     import paper_1102_4666_amd as bsde
     t0 = time.perf_counter()
     P = bsde.Problem(cfg)
+    if FORCED_TILING is not None:
+        P.set_tiling(*FORCED_TILING)
     if solve_lock is not None:
         solve_lock.acquire()
     t1 = time.perf_counter()
@@ -368,6 +401,10 @@ def main():
     ap.add_argument("--euler-steps", type=int, default=0, metavar="N",
                     help="with --single-launch: Euler steps per path "
                          "instead of the workload's")
+    ap.add_argument("--tiling", default="", metavar="G,P",
+                    help="run every job at G workgroups per point and P paths "
+                         "per lane instead of the autotuned tiling (for counter "
+                         "runs that must see one tiling)")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
                     help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
                          "geo_basket_d5, eur_put_d1_kernel, d10-serving): run one "
@@ -407,8 +444,13 @@ def main():
     # tune the path tiling of this kernel signature once; problems created
     # afterwards start with the recorded choice
     import paper_1102_4666_amd as bsde
-    with bsde.Problem(cfg) as P:
-        tiling = P.autotune(stream)
+    global FORCED_TILING
+    if args.tiling:
+        FORCED_TILING = tuple(int(v) for v in args.tiling.split(","))
+        tiling = FORCED_TILING
+    else:
+        with bsde.Problem(cfg) as P:
+            tiling = P.autotune(stream)
     # job pipeline: one stream per host thread (default priority)
     streams = [stream] + [torch.cuda.Stream().cuda_stream
                           for _ in range(args.pipeline - 1)]
@@ -424,8 +466,8 @@ def main():
     # its mean duration (HIP events on the solve's stream)
     t_path = float(np.mean(path_ms)) * 1e-3
     launch_steps = n * cfg["M"] * cfg["N"]
-    ops = OPS_PER_PATH_STEP[args.precision] * launch_steps
-    achieved = ops / t_path
+    cyc = sum(ISSUE_CYCLES_PER_WAVE_STEP[args.precision].values()) * launch_steps / 64
+    achieved = cyc / t_path
     line = {
         "metric": "Euler path-steps/s + priced requests/s (p50/p99) at stated price/delta error",
         "value": steps_per_job * args.steps / wall,
@@ -452,9 +494,9 @@ def main():
             [float(x) for x in np.mean(kern_ms, axis=0)[:2]])),
         "solve_ms": float(np.mean(kern_ms, axis=0)[4]),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_LANE_OPS / 1e12,
-                     "unit": "T VALU lane-ops/s (transcendentals excluded)",
-                     "frac": achieved / VALU_PEAK_LANE_OPS,
+                     "peak": SIMD_ISSUE_CYCLES_PEAK / 1e12,
+                     "unit": "T SIMD vector-issue cycles/s (algorithmic)",
+                     "frac": achieved / SIMD_ISSUE_CYCLES_PEAK,
                      "traffic": traffic_bytes(args.precision, tiling[0])},
     }
     if args.precision == "fp32":

@@ -38,11 +38,15 @@ struct Arith<float> {
     {
         return -1.38629436111989061883f * v;
     }
+    // c32, c33: 2^-32 and 2^-33 of u01, passed in so that the caller can
+    // hold them in vector registers
     static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
                                                       float scale, float &n0,
-                                                      float &n1)
+                                                      float &n1, float c32 = 0x1p-32f,
+                                                      float c33 = 0x1p-33f)
     {
-        float R = __builtin_amdgcn_sqrtf(scale * __builtin_amdgcn_logf(u01(wa)));
+        const float ua = fmaf((float)wa, c32, c33);
+        float R = __builtin_amdgcn_sqrtf(scale * __builtin_amdgcn_logf(ua));
         // angle: 1 + (top 23 bits of wb) 2^-23 in [1, 2) revolutions, built
         // by one funnel shift that puts the exponent of 1.0 above them
         // (sine and cosine have period one revolution)
@@ -75,7 +79,8 @@ struct Arith<double> {
     // Box-Muller pair scaled by sqrt(v), scale = -2 v: R = sqrt(-2 v ln ua)
     static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
                                                       double scale, double &n0,
-                                                      double &n1)
+                                                      double &n1, double = 0.0,
+                                                      double = 0.0)
     {
         double R = ::sqrt(scale * ::log(u01(wa)));
         double phi = (2.0 * 3.14159265358979323846) * u01(wb);
@@ -241,23 +246,91 @@ struct Mfma<double> {
     }
 };
 
+// One Philox4x32-10 round in the path kernel (the function of philox_round).
+// Bit 0 / bit 1 of X3 select, for the new word 0 / word 2, the three-way
+// XOR (high half ^ counter word ^ key) as one v_bitop3_b32 with truth table
+// 0x96 (a ^ b ^ c) instead of two v_xor_b32.  That pays only where the
+// counter word varies across the wave: with a uniform counter word the two
+// uniform operands combine on the scalar unit and leave one vector XOR,
+// while v_bitop3_b32 (one scalar operand at most) would need a move too.
+template <int X3>
+__device__ __forceinline__ void philox_round_dev(u32x4 &c, uint32_t &k0, uint32_t &k1)
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t h1 = (uint32_t)(p1 >> 32), h0 = (uint32_t)(p0 >> 32);
+    const uint32_t n0 = (X3 & 1) ? __builtin_amdgcn_bitop3_b32(h1, c.y, k0, 0x96)
+                                 : h1 ^ c.y ^ k0;
+    const uint32_t n2 = (X3 & 2) ? __builtin_amdgcn_bitop3_b32(h0, c.w, k1, 0x96)
+                                 : h0 ^ c.w ^ k1;
+    c = {n0, (uint32_t)p1, n2, (uint32_t)p0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+}
+
 // One Philox4x32-10 block in the path kernel (the same function as
-// philox10).  After the second round the key passes through an empty asm
-// statement, so that the keys of rounds 3-10, k + r (W0, W1), are formed on
-// the scalar unit per block instead of being hoisted out of the path loops,
-// where sixteen of them would stay live in scalar registers (at d >= 5 the
+// philox10) on the counter (m, i, k, word 3): m varies across the wave, the
+// other three words are uniform.  Rounds 1 and 2 keep their hoistable work
+// on the uniform words; after round 2 only word 3 is still uniform, and from
+// round 4 on every word varies, so with kXor3 round 3 takes the three-input
+// XOR for word 0 and rounds 4-10 for both.  The FP32 kernels below d = 10
+// take it (10 fewer of the ~53 vector instructions of a block); the others
+// keep the two-XOR form, under which the d = 1 FP64 kernel fits 128
+// registers (four waves per SIMD) and the d = 10 kernels spill less.
+// After the second round the key passes through an empty asm statement, so
+// that the keys of rounds 3-10, k + r (W0, W1), are formed on the scalar
+// unit per block instead of being hoisted out of the path loops, where
+// sixteen of them would stay live in scalar registers (at d >= 5 the
 // compiler parks the excess in vector-register lanes and reads it back with
-// one vector instruction per use).  The first two rounds keep their
-// hoistable work on the uniform counter words (i, k).
+// one vector instruction per use).
+// Keys of rounds 3-10, k + r (W0, W1) for r = 2..9, held in vector
+// registers: v_bitop3_b32 with all three operands in vector registers
+// issues in about three cycles instead of four.
+struct PhiloxKeys {
+    uint32_t a[8], b[8];
+};
+
+__device__ __forceinline__ PhiloxKeys philox_vector_keys(uint32_t k0, uint32_t k1)
+{
+    PhiloxKeys kv;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        kv.a[r] = k0 + (uint32_t)(r + 2) * 0x9E3779B9u;
+        kv.b[r] = k1 + (uint32_t)(r + 2) * 0xBB67AE85u;
+        asm volatile("" : "+v"(kv.a[r]), "+v"(kv.b[r]));
+    }
+    return kv;
+}
+
+template <bool kXor3>
 __device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t c2,
                                               uint32_t c3, uint32_t k0, uint32_t k1)
 {
     u32x4 c{c0, c1, c2, c3};
-    philox_round(c, k0, k1);
-    philox_round(c, k0, k1);
+    philox_round_dev<0>(c, k0, k1);
+    philox_round_dev<0>(c, k0, k1);
     asm volatile("" : "+s"(k0), "+s"(k1));
+    philox_round_dev<kXor3 ? 1 : 0>(c, k0, k1);
 #pragma unroll
-    for (int r = 2; r < 10; ++r) philox_round(c, k0, k1);
+    for (int r = 3; r < 10; ++r) philox_round_dev<kXor3 ? 3 : 0>(c, k0, k1);
+    return c;
+}
+
+// The same block with the keys of rounds 3-10 taken from vector registers
+// (every XOR of those rounds one v_bitop3_b32; in round 3 the uniform word
+// 3 is its one scalar operand).
+__device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t c2,
+                                              uint32_t c3, uint32_t k0, uint32_t k1,
+                                              const PhiloxKeys &kv)
+{
+    u32x4 c{c0, c1, c2, c3};
+    philox_round_dev<0>(c, k0, k1);
+    philox_round_dev<0>(c, k0, k1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        uint32_t ka = kv.a[r], kb = kv.b[r];
+        philox_round_dev<3>(c, ka, kb);
+    }
     return c;
 }
 
@@ -288,8 +361,18 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
     constexpr int NB = SG * D / 4;
     constexpr int NBB = (D + 3) / 4; // bridge blocks
+    constexpr bool kXor3 = sizeof(Real) == 4 && D < 10; // Philox XOR form
+    // FP32, d = 1: round keys in vector registers (16 of them; at d = 2
+    // they cost waves per SIMD)
+    constexpr bool kVKeys = sizeof(Real) == 4 && D == 1;
 
     const uint32_t k0 = (uint32_t)prm.seed, k1 = (uint32_t)(prm.seed >> 32);
+    PhiloxKeys kv{};
+    if constexpr (kVKeys) kv = philox_vector_keys(k0, k1);
+    auto block = [&](uint32_t m, uint32_t w3) -> u32x4 {
+        if constexpr (kVKeys) return philox_block((uint32_t)m, (uint32_t)i, prm.k, w3, k0, k1, kv);
+        else return philox_block<kXor3>((uint32_t)m, (uint32_t)i, prm.k, w3, k0, k1);
+    };
 
     const double *row = pts + (size_t)i * DP;
     const Real T = (Real)prm.T;
@@ -322,6 +405,21 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         lev[j] = ac.level[j];
         if constexpr (D <= 5) asm volatile("" : "+v"(lev[j]));
     }
+    // gfx950 issues a 32-bit vector instruction whose operands are all
+    // vector registers in two cycles, one with a scalar or literal operand
+    // in four.  The FP32 kernels up to d = 5 therefore also hold the other
+    // loop-invariant operands of the Euler step (level a, (r - delta) h
+    // kappa) and the constants of the uniform map in vector registers.
+    constexpr bool kVecConst = sizeof(Real) == 4 && D <= 5;
+    Real lva[D], dhk[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lva[j] = ac.level_a[j];
+        dhk[j] = ac.drift[j] * hk;
+        if constexpr (kVecConst) asm volatile("" : "+v"(lva[j]), "+v"(dhk[j]));
+    }
+    Real c32 = Real(0x1p-32), c33 = Real(0x1p-33);
+    if constexpr (kVecConst) asm volatile("" : "+v"(c32), "+v"(c33));
     // X and the normals G at the step j* of each path: written to LDS by
     // the one step that matches, a store under the lane mask, where a
     // select in every step would take two vector-ALU slots per asset
@@ -343,8 +441,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         }
 
         // U, j* = floor(U N) and theta = U N - j* in integer arithmetic
-        const u32x4 wu = philox_block((uint32_t)m, (uint32_t)i, prm.k, 1u << 24,
-                                  k0, k1);
+        const u32x4 wu = block((uint32_t)m, 1u << 24);
         const uint64_t num = (2ull * wu.x + 1ull) * (uint64_t)prm.N;
         const int jstar = (int)(num >> 33);
         const Real theta = Arith<Real>::frac33(num);
@@ -359,12 +456,11 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
             Real G[4 * NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const u32x4 w = philox_block((uint32_t)m, (uint32_t)i, prm.k,
-                                         (uint32_t)(grp * NB + b), k0, k1);
+                const u32x4 w = block((uint32_t)m, (uint32_t)(grp * NB + b));
                 Arith<Real>::box_muller(w.x, w.y, step_scale, G[4 * b],
-                                        G[4 * b + 1]);
+                                        G[4 * b + 1], c32, c33);
                 Arith<Real>::box_muller(w.z, w.w, step_scale, G[4 * b + 2],
-                                        G[4 * b + 3]);
+                                        G[4 * b + 3], c32, c33);
             }
 #pragma unroll
             for (int ss = 0; ss < SG; ++ss) {
@@ -385,11 +481,13 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         if (j > 0) lg = fma(ac.Ldiag[j], G[ss * D + j], S);
                         if (j + 1 < D) S = j == 0 ? ac.Lcol[0] * G[ss * D]
                                                   : fma(ac.Lcol[j], G[ss * D + j], S);
-                        const Real sig = ES::vol(lev[j], ac.level_a[j], ac.spot[j], vt, X[j]);
+                        const Real sig = ES::vol(lev[j], lva[j], ac.spot[j], vt, X[j]);
                         // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
                         //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2),
                         // every term times kappa
-                        X[j] = fma(ac.drift[j], hk, fma(sig, fma(neg_half_hk, sig, lg), X[j]));
+                        const Real inner = fma(sig, fma(neg_half_hk, sig, lg), X[j]);
+                        if constexpr (kVecConst) X[j] = inner + dhk[j];
+                        else X[j] = fma(ac.drift[j], hk, inner);
                     }
                 }
             }
@@ -402,8 +500,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         Real Gb[4 * NBB];
 #pragma unroll
         for (int b = 0; b < NBB; ++b) {
-            const u32x4 w = philox_block((uint32_t)m, (uint32_t)i, prm.k,
-                                     (1u << 24) | (uint32_t)(1 + b), k0, k1);
+            const u32x4 w = block((uint32_t)m, (1u << 24) | (uint32_t)(1 + b));
             Arith<Real>::box_muller(w.x, w.y, bridge_scale, Gb[4 * b],
                                     Gb[4 * b + 1]);
             Arith<Real>::box_muller(w.z, w.w, bridge_scale, Gb[4 * b + 2],
@@ -903,11 +1000,16 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
 // schedule (one wave per SIMD, so nothing hides the matrix-core and LDS
 // latencies); two waves fit in 256 with a little rematerialisation.  The
 // constant-volatility form keeps more per-asset Euler terms live and would
-// spill at two waves, so it stays at one.
+// spill at two waves, so it stays at one.  d = 5 in FP32 fits three waves
+// (at most 168 registers with the accumulators) with no spill; left to
+// itself the compiler schedules more Philox blocks in flight and drops to
+// two.
 template <int D, typename Real, int VOL>
 constexpr int min_waves()
 {
-    return (D >= 10 && sizeof(Real) == 4 && VOL == kVolBump) ? 2 : 1;
+    if (D >= 10) return (sizeof(Real) == 4 && VOL == kVolBump) ? 2 : 1;
+    if (D == 5 && sizeof(Real) == 4) return 3;
+    return 1;
 }
 
 // One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
