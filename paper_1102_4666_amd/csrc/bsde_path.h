@@ -362,10 +362,13 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     constexpr int NB = SG * D / 4;
     constexpr int NBB = (D + 3) / 4; // bridge blocks
     constexpr bool kXor3 = sizeof(Real) == 4 && D < 10; // Philox XOR form
-    // FP32, d = 1: round keys in vector registers (16 of them; at d = 2
-    // they cost waves per SIMD).  Not in the kernel operator, whose pair
-    // loop, not the Euler loop, sets the time and which would lose waves.
-    constexpr bool kVKeys = sizeof(Real) == 4 && D == 1 && OP == kOpBasis;
+    // FP32 round keys in vector registers (16 of them): at d = 1, and at
+    // d = 2 from eta = 5 on, where the kernel's own registers already hold
+    // it to four waves per SIMD and the keys still fit (below, they would
+    // cost waves).  Not in the kernel operator, whose pair loop, not the
+    // Euler loop, sets the time and which would lose waves.
+    constexpr bool kVKeys = sizeof(Real) == 4 && OP == kOpBasis &&
+                            (D == 1 || (D == 2 && ETA >= 5));
 
     const uint32_t k0 = (uint32_t)prm.seed, k1 = (uint32_t)(prm.seed >> 32);
     PhiloxKeys kv{};
