@@ -352,7 +352,8 @@ def single_launches(names, euler_steps=None):
     FP32 paths, default tiling: the runs behind the profiles of the
     matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
     eur_put_d1_kernel (the kernel operator of Section 3.2), d10-serving
-    (the d=10 request shape of the serving mix at M=500).
+    (the d=10 request shape of the serving mix at M=500),
+    call_basket_d10_hyperbolic (the hyperbolic-set kernel, p=221).
     euler_steps replaces N (separates per-step from per-path cost)."""
     import paper_1102_4666_amd as bsde
     import workloads
@@ -407,7 +408,8 @@ def main():
                          "runs that must see one tiling)")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
                     help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
-                         "geo_basket_d5, eur_put_d1_kernel, d10-serving): run one "
+                         "geo_basket_d5, eur_put_d1_kernel, d10-serving, "
+                         "call_basket_d10_hyperbolic): run one "
                          "path-kernel launch of each and print its time, nothing "
                          "else")
     args = ap.parse_args()

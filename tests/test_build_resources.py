@@ -2,21 +2,25 @@
 kernel-resource-usage report written by the build): a spill puts per-lane
 scratch traffic into the innermost loops of the path simulation.
 
-The one exception is the d = 10 local-volatility kernels of the larger
-bases (eta = 3, and the hyperbolic eta = 5, q = 0.6 set), compiled for two
-waves per SIMD: at 256 registers they spill up to ~120 bytes per lane, all
-of it in the per-point set-up, the bridge step and the channel fold --
-outside the Euler loop and the matrix-core contraction (checked on the
-assembly).  One wave per SIMD removes the spill but runs the d = 10
-serving shape 1.5x slower."""
+The exceptions are d = 10 kernels compiled for two waves per SIMD:
+the local-volatility kernels of the larger bases (eta = 3, and the
+hyperbolic eta = 5, q = 0.6 set) spill up to ~120 bytes per lane at 256
+registers, all of it in the per-point set-up, the bridge step and the
+channel fold -- outside the Euler loop and the matrix-core contraction
+(checked on the assembly); one wave per SIMD removes the spill but runs
+the d = 10 serving shape 1.5x slower.  The constant-volatility kernel of
+the hyperbolic set spills 212 bytes: stored once per workgroup and
+reloaded once per path, never inside the Euler loop; at one wave it has
+no spill and runs 1.4x slower."""
 import os
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RES = os.path.join(ROOT, "paper_1102_4666_amd", "_build", "resources.txt")
-ALLOWED = ("path_kernelILi10ELi3EfLi1E", "path_kernelILi10ELi5EfLi1E")
-MAX_ALLOWED_BYTES = 160
+# kernel-name pattern -> largest spill allowed (bytes per lane)
+ALLOWED = {"path_kernelILi10ELi3EfLi1E": 160, "path_kernelILi10ELi5EfLi1E": 160,
+           "path_kernelILi10ELi5EfLi0ELi6E": 240}
 
 
 def test_path_kernels_do_not_spill():
@@ -26,5 +30,5 @@ def test_path_kernels_do_not_spill():
     assert rows, "no path kernels in the resource report"
     for name, vgprs, scratch in rows:
         nbytes = int(scratch.split("=")[1])
-        limit = MAX_ALLOWED_BYTES if any(a in name for a in ALLOWED) else 0
+        limit = max([v for k, v in ALLOWED.items() if k in name], default=0)
         assert nbytes <= limit, (name, vgprs, scratch)

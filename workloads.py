@@ -114,6 +114,17 @@ def eur_put_d1_kernel(precision: str = "fp32") -> dict:
                    kernel_bw=0.1, precision=precision, seed=0)
 
 
+def call_basket_d10_hyperbolic(precision: str = "fp32") -> dict:
+    """d=10 European call basket of Section 6.2.1: Black-Scholes sigma=0.2,
+    rho=0.2, K=S0=100, T=1, hyperbolic index set eta=5, q=0.6 (p=221), 1000
+    points drawn uniformly at every iteration, domain +-1 standard deviation,
+    M=30000, N=10, 10 iterations."""
+    return problem(d=10, vol_level=0.2, rho=0.2, T=1.0, r=0.05, K=100.0,
+                   S0=100.0, payoff="call", omega=0.0, grid="uniform",
+                   redraw=1, n_x=1000, eta=5, q=0.6, N=10, K_it=10,
+                   width=1.0, M=30000, precision=precision, seed=0)
+
+
 def serving_request(idx: int, rng: np.random.Generator,
                     dims=(1, 2, 5, 10)) -> dict:
     """One request of the serving mix: d drawn from dims, strike U[80,120],
