@@ -999,21 +999,19 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     __syncthreads(); // red[] may be reused by the next tile
 }
 
-// Waves per SIMD the register allocation must allow: d = 10 in FP32 with
-// the local volatility needs about 270 registers a lane at its natural
-// schedule (one wave per SIMD, so nothing hides the matrix-core and LDS
-// latencies); two waves fit in 256 with a little rematerialisation.  The
-// constant-volatility form of the hyperbolic set (q < 1, p = 221) needs
-// about 300 and at two waves spills 212 bytes a lane, mostly outside the
-// Euler loop: it still runs 28% faster than at one.  The other
-// constant-volatility d = 10 forms stay at one wave (they would spill up
-// to 264 bytes, unmeasured).  d = 5 in FP32 fits three waves (at most 168
-// registers with the accumulators) with no spill; left to itself the
-// compiler schedules more Philox blocks in flight and drops to two.
-template <int D, typename Real, int VOL, int Q>
+// Waves per SIMD the register allocation must allow.  The FP32 d = 10
+// kernels want 270-300 registers a lane at their natural schedule (one wave
+// per SIMD, so nothing hides the matrix-core and LDS latencies of the
+// per-path work); held to two waves (256 registers) they spill 48-264 bytes
+// a lane, stored once per workgroup and reloaded per path, outside the
+// Euler loop, and run 15-28% faster (measured for both volatility kinds,
+// eta = 2, 3 and the hyperbolic set).  d = 5 in FP32 fits three waves (at
+// most 168 registers with the accumulators) with no spill; left to itself
+// the compiler schedules more Philox blocks in flight and drops to two.
+template <int D, typename Real>
 constexpr int min_waves()
 {
-    if (D >= 10) return (sizeof(Real) == 4 && (VOL == kVolBump || Q != 10)) ? 2 : 1;
+    if (D >= 10) return sizeof(Real) == 4 ? 2 : 1;
     if (D == 5 && sizeof(Real) == 4) return 3;
     return 1;
 }
@@ -1021,7 +1019,7 @@ constexpr int min_waves()
 // One problem: workgroup b runs tile (i, g) = (b / groups, b % groups) and
 // writes its sums to partial[2 b].
 template <int D, int ETA, typename Real, int VOL, int Q, int OP = kOpBasis>
-__global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL, Q>())) void path_kernel(
+__global__ __launch_bounds__(kBlock, (min_waves<D, Real>())) void path_kernel(
     const PathParams prm, const double *__restrict__ pts,
     const Real *__restrict__ gamma, double *__restrict__ partial)
 {
@@ -1038,7 +1036,7 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL, Q>())) void path_k
 // computes exactly what the one-problem kernel computes for the same
 // (i, g), so a problem's result does not depend on the batch.
 template <int D, int ETA, typename Real, int VOL, int Q>
-__global__ __launch_bounds__(kBlock, (min_waves<D, Real, VOL, Q>())) void batch_path_kernel(
+__global__ __launch_bounds__(kBlock, (min_waves<D, Real>())) void batch_path_kernel(
     const BatchTileDesc *__restrict__ probs, int nprob,
     const long long *__restrict__ tile_begin, unsigned int *counter)
 {
