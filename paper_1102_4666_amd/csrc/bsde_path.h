@@ -1010,12 +1010,15 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
 // the compiler schedules more Philox blocks in flight and drops to two.
 // d = 5 in FP64 wants a little over 256 with the accumulators (one wave);
 // at two it fits (local volatility) or spills about 110 bytes a lane
-// outside the Euler loop (constant volatility), and runs 30% faster.
+// outside the Euler loop (constant volatility), and runs 30% faster.  So
+// does d = 2 in FP64 (eta = 5 wants over 256 registers; at two waves it
+// spills 28 bytes a lane and runs 29% faster).
 template <int D, typename Real>
 constexpr int min_waves()
 {
     if (D >= 10) return sizeof(Real) == 4 ? 2 : 1;
     if (D == 5) return sizeof(Real) == 4 ? 3 : 2;
+    if (D == 2) return sizeof(Real) == 4 ? 1 : 2;
     return 1;
 }
 
