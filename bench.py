@@ -347,27 +347,47 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
             "load_0.9": run_phase(0.9 * x_sat)}
 
 
-def single_launches(names, euler_steps=None):
+def _overrides(text):
+    """'k=v,k=v' -> dict, values as int, float or string."""
+    out = {}
+    for item in filter(None, text.split(",")):
+        k, v = item.split("=", 1)
+        for conv in (int, float):
+            try:
+                out[k] = conv(v)
+                break
+            except ValueError:
+                pass
+        else:
+            out[k] = v
+    return out
+
+
+def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
     """One Picard iteration (one path-kernel launch) of each named workload,
     FP32 paths, default tiling: the runs behind the profiles of the
     matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
     eur_put_d1_kernel (the kernel operator of Section 3.2), d10-serving
     (the d=10 request shape of the serving mix at M=500),
     call_basket_d10_hyperbolic (the hyperbolic-set kernel, p=221).
-    euler_steps replaces N (separates per-step from per-path cost)."""
+    euler_steps replaces N (separates per-step from per-path cost);
+    overrides (a dict) replaces workload fields (eta, q, vol_kind, ...)."""
     import paper_1102_4666_amd as bsde
     import workloads
     out = {}
     for nm in names:
         if nm == "d10-serving":
             cfg = workloads.serving_request(1, np.random.default_rng(0), dims=(10,))
-            cfg.update(M=500, K=100.0, omega=1.0)
+            cfg.update(M=500, K=100.0, omega=1.0, precision=precision)
         else:
-            cfg = getattr(workloads, nm)(precision="fp32")
+            cfg = getattr(workloads, nm)(precision=precision)
         cfg.update(K_it=1)
+        cfg.update(overrides or {})
         if euler_steps:
             cfg.update(N=euler_steps)
         with bsde.Problem(cfg) as P:
+            if FORCED_TILING is not None:
+                P.set_tiling(*FORCED_TILING)
             P.solve()
             out[nm] = {"path_kernel_ms": P.timings()[0],
                        "path_steps": P.n * cfg["M"] * cfg["N"]}
@@ -402,6 +422,9 @@ def main():
     ap.add_argument("--euler-steps", type=int, default=0, metavar="N",
                     help="with --single-launch: Euler steps per path "
                          "instead of the workload's")
+    ap.add_argument("--set", default="", metavar="K=V,..",
+                    help="with --single-launch: replace workload fields, e.g. "
+                         "eta=2,q=1.0,vol_kind=const")
     ap.add_argument("--tiling", default="", metavar="G,P",
                     help="run every job at G workgroups per point and P paths "
                          "per lane instead of the autotuned tiling (for counter "
@@ -413,6 +436,9 @@ def main():
                          "path-kernel launch of each and print its time, nothing "
                          "else")
     args = ap.parse_args()
+    global FORCED_TILING
+    if args.tiling:
+        FORCED_TILING = tuple(int(v) for v in args.tiling.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU "
               "path (one problem's points would shard across GPUs with a "
@@ -434,7 +460,8 @@ def main():
         return
     if args.single_launch:
         print(json.dumps(single_launches(args.single_launch.split(","),
-                                         args.euler_steps or None)))
+                                         args.euler_steps or None, args.precision,
+                                         _overrides(args.set))))
         return
     if args.pipeline < 1:
         ap.error("--pipeline must be at least 1")
@@ -446,9 +473,7 @@ def main():
     # tune the path tiling of this kernel signature once; problems created
     # afterwards start with the recorded choice
     import paper_1102_4666_amd as bsde
-    global FORCED_TILING
-    if args.tiling:
-        FORCED_TILING = tuple(int(v) for v in args.tiling.split(","))
+    if FORCED_TILING is not None:
         tiling = FORCED_TILING
     else:
         with bsde.Problem(cfg) as P:

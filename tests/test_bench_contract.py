@@ -42,3 +42,10 @@ def test_traffic_table():
     assert b.traffic_bytes("fp32", 8) == (305 * 2.0 + 512 * 1.0) * 1024
     assert b.traffic_bytes("fp32", 3) is None
     assert b.traffic_bytes("bf16", 8) is None
+
+
+def test_single_launch_overrides():
+    b = _bench()
+    assert b._overrides("") == {}
+    assert b._overrides("eta=2,q=1.0,vol_kind=const") == {"eta": 2, "q": 1.0,
+                                                          "vol_kind": "const"}
