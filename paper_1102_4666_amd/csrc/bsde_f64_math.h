@@ -1,0 +1,173 @@
+// bsde_f64_math.h -- FP64 elementary functions of the FP64 path kernels,
+// specialised to the arguments the Box-Muller transform hands them.
+//
+// The angle of a Box-Muller pair is 2 pi u with u = (w + 1/2) 2^-32 for a
+// 32-bit Philox word w, so its reduction to a quarter turn is exact integer
+// arithmetic on w: with q the nearest quarter turn and the remainder
+// rho = w - q 2^30 in [-2^29, 2^29), the reduced angle is
+// x = 2 pi (rho + 1/2) 2^-32 in [-pi/4, pi/4] (one rounding), and
+// sin(2 pi u), cos(2 pi u) are sin x, cos x permuted and negated by q.  On
+// [-pi/4, pi/4] the Maclaurin series of sine to degree 17 and of cosine to
+// degree 16 leave remainders below 1e-19 and 3e-18, under a quarter of an
+// ulp of the results (|cos x| >= 0.707, |sin x| >= 0.637 |x|), so the
+// results are within a few ulps.  The general-argument library sincos
+// spends most of its instructions on a double-word reduction by pi/2 that
+// this angle does not need.
+//
+// The radius of the pair needs ln u for the same u: with v = w + 1/2 =
+// 2^e m, m in [1/sqrt 2, sqrt 2) split off the bits of v, ln u =
+// (e - 32) ln 2 + ln m and ln m = 2 atanh(s), s = (m - 1) / (m + 1),
+// |s| <= 0.1716, whose odd series 2 s (1 + s^2/3 + s^4/5 + ...) to s^19
+// leaves a remainder below 2.3e-17 of 2 s.  The quotient s takes one
+// hardware reciprocal, two Newton steps and one residual correction.
+//
+// The local volatility needs e^x for x = -y^2 <= 0: x clamped at -708
+// (e^-708 is already below the volatility's rounding), x = n ln 2 + r with
+// |r| <= ln 2 / 2 (ln 2 in two parts, so r is exact to the last bits), e^r
+// by its Maclaurin series to degree 13 (remainder below 6e-18 of e^r), and
+// the power 2^n applied to the exponent.
+//
+// Plain double and 32-bit integer arithmetic (and the hardware reciprocal
+// seed on the device), so the same code also compiles for the host: the
+// test suite checks it there against high-precision references.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define BSDE_F64_HD __host__ __device__
+#else
+#define BSDE_F64_HD
+#endif
+
+namespace bsde {
+namespace f64 {
+
+// Maclaurin coefficients (-1)^k / (2k+1)! of sine and (-1)^k / (2k)! of
+// cosine, k = 1..8
+constexpr double kS[8] = {-1.0 / 6.0,
+                          1.0 / 120.0,
+                          -1.0 / 5040.0,
+                          1.0 / 362880.0,
+                          -1.0 / 39916800.0,
+                          1.0 / 6227020800.0,
+                          -1.0 / 1307674368000.0,
+                          1.0 / 355687428096000.0};
+constexpr double kC[8] = {-1.0 / 2.0,
+                          1.0 / 24.0,
+                          -1.0 / 720.0,
+                          1.0 / 40320.0,
+                          -1.0 / 3628800.0,
+                          1.0 / 479001600.0,
+                          -1.0 / 87178291200.0,
+                          1.0 / 20922789888000.0};
+// 2 pi 2^-32 (the ulp of u in radians)
+constexpr double kTwoPiUlp = 6.283185307179586476925286766559 / 4294967296.0;
+
+// sin and cos of the angle 2 pi (w + 1/2) 2^-32 (w a 32-bit word)
+BSDE_F64_HD inline void sincos_turn(uint32_t w, double &s, double &c)
+{
+    // nearest quarter turn (mod 4) and the signed remainder; the 32-bit
+    // wrap-around of the sum gives q = 0 for the last eighth of the turn
+    const uint32_t q = (w + 0x20000000u) >> 30;
+    const int32_t rho = (int32_t)(w - (q << 30));
+    const double x = __builtin_fma((double)rho, kTwoPiUlp, 0.5 * kTwoPiUlp);
+    const double x2 = x * x;
+    double ps = kS[7], pc = kC[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) {
+        ps = __builtin_fma(ps, x2, kS[k]);
+        pc = __builtin_fma(pc, x2, kC[k]);
+    }
+    const double sx = __builtin_fma(x * x2, ps, x);
+    const double cx = __builtin_fma(x2, pc, 1.0);
+    // sin(q pi/2 + x) = sin x, cos x, -sin x, -cos x;
+    // cos(q pi/2 + x) = cos x, -sin x, -cos x, sin x
+    const bool odd = (q & 1u) != 0;
+    const double a = odd ? cx : sx;
+    const double b = odd ? sx : cx;
+    s = (q & 2u) ? -a : a;
+    c = ((q + 1u) & 2u) ? -b : b;
+}
+
+// ln 2 in two parts: kLn2Hi has 42 significant bits, so e kLn2Hi is exact
+// for |e| < 2^11
+constexpr double kLn2Hi = 0.693147180559890330187045037746429443359375;
+constexpr double kLn2Lo = 5.4979230187083711552420206887e-14;
+
+BSDE_F64_HD inline uint64_t to_bits(double x) { return __builtin_bit_cast(uint64_t, x); }
+BSDE_F64_HD inline double from_bits(uint64_t b) { return __builtin_bit_cast(double, b); }
+
+BSDE_F64_HD inline double reciprocal_seed(double d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcp(d); // v_rcp_f64
+#else
+    return 1.0 / d;
+#endif
+}
+
+// ln((w + 1/2) 2^-32) for a 32-bit word w
+BSDE_F64_HD inline double log_word(uint32_t w)
+{
+    const double v = (double)w + 0.5; // exact, in [1/2, 2^32)
+    const uint64_t b = to_bits(v);
+    const uint32_t hi = (uint32_t)(b >> 32);
+    const uint32_t frac_hi = hi & 0x000FFFFFu;
+    // mantissas at or above sqrt 2 (its top fraction bits are 0x6A09E)
+    // take the next exponent and m in [1/sqrt 2, 1)
+    const uint32_t up = frac_hi >= 0x6A09Fu ? 1u : 0u;
+    const int e = (int)(hi >> 20) - 1023 + (int)up - 32;
+    const double m = from_bits(((uint64_t)(frac_hi | ((0x3FFu - up) << 20)) << 32) |
+                               (b & 0xFFFFFFFFull));
+    const double f = m - 1.0; // exact
+    const double d = m + 1.0;
+    double y = reciprocal_seed(d);
+    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+    double sq = f * y;
+    sq = __builtin_fma(__builtin_fma(-sq, d, f), y, sq);
+    const double z = sq * sq;
+    // 2/3 + 2z/5 + ... + 2z^8/19
+    double q = 2.0 / 19.0;
+    q = __builtin_fma(q, z, 2.0 / 17.0);
+    q = __builtin_fma(q, z, 2.0 / 15.0);
+    q = __builtin_fma(q, z, 2.0 / 13.0);
+    q = __builtin_fma(q, z, 2.0 / 11.0);
+    q = __builtin_fma(q, z, 2.0 / 9.0);
+    q = __builtin_fma(q, z, 2.0 / 7.0);
+    q = __builtin_fma(q, z, 2.0 / 5.0);
+    q = __builtin_fma(q, z, 2.0 / 3.0);
+    const double ed = (double)e;
+    const double hi_part = __builtin_fma(ed, kLn2Hi, 2.0 * sq);
+    const double lo_part = __builtin_fma(ed, kLn2Lo, (sq * z) * q);
+    return hi_part + lo_part;
+}
+
+// e^x for x <= 0 (the local volatility's e^{-y^2})
+BSDE_F64_HD inline double exp_nonpos(double x)
+{
+    x = x < -708.0 ? -708.0 : x;
+    const double n = __builtin_rint(x * 1.4426950408889634073599246810019);
+    double r = __builtin_fma(-n, kLn2Hi, x);
+    r = __builtin_fma(-n, kLn2Lo, r);
+    double p = 1.0 / 6227020800.0; // 1/13!
+    p = __builtin_fma(p, r, 1.0 / 479001600.0);
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    // times 2^n, n in [-1022, 0]: exponent field of a normal number
+    return p * from_bits((uint64_t)(1023 + (int)n) << 52);
+}
+
+} // namespace f64
+} // namespace bsde

@@ -13,6 +13,7 @@
 #pragma once
 
 #include "bsde_common.h"
+#include "bsde_f64_math.h"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -55,6 +56,7 @@ struct Arith<float> {
         n1 = R * __builtin_amdgcn_sinf(ub);
     }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    static __device__ __forceinline__ float exp_nonpos(float x) { return __expf(x); }
     static __device__ __forceinline__ float sqrt(float x)
     {
         return __builtin_amdgcn_sqrtf(x); // v_sqrt_f32, no refinement
@@ -76,20 +78,26 @@ struct Arith<double> {
     {
         return -2.0 * v;
     }
-    // Box-Muller pair scaled by sqrt(v), scale = -2 v: R = sqrt(-2 v ln ua)
+    // Box-Muller pair scaled by sqrt(v), scale = -2 v: R = sqrt(-2 v ln ua);
+    // ln ua and the sine and cosine of the angle 2 pi ub from the words
+    // themselves (bsde_f64_math.h)
     static __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb,
                                                       double scale, double &n0,
                                                       double &n1, double = 0.0,
                                                       double = 0.0)
     {
-        double R = ::sqrt(scale * ::log(u01(wa)));
-        double phi = (2.0 * 3.14159265358979323846) * u01(wb);
+        double R = ::sqrt(scale * f64::log_word(wa));
         double s, c;
-        ::sincos(phi, &s, &c);
+        f64::sincos_turn(wb, s, c);
         n0 = R * c;
         n1 = R * s;
     }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    // e^x for x <= 0 (the volatilities' Gaussian factors)
+    static __device__ __forceinline__ double exp_nonpos(double x)
+    {
+        return f64::exp_nonpos(x);
+    }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double frac33(uint64_t num)
     {
@@ -127,10 +135,10 @@ __device__ __forceinline__ Real local_vol(Real level, Real level_a, Real lc,
 {
     if constexpr (VOL == kVolBump) {
         Real dx = x - lc;
-        return fma(level_a, Arith<Real>::exp(-dx * dx), level);
+        return fma(level_a, Arith<Real>::exp_nonpos(-dx * dx), level);
     } else if constexpr (VOL == kVolDupire) {
         const Real dev = Arith<Real>::exp(x + vt.rt) - spot;
-        return fma(-vt.B, Arith<Real>::exp(Real(-0.001) * dev * dev), vt.A);
+        return fma(-vt.B, Arith<Real>::exp_nonpos(Real(-0.001) * dev * dev), vt.A);
     }
     return level;
 }
@@ -163,7 +171,7 @@ struct EulerState {
             if constexpr (sizeof(Real) == 4)
                 return fmaf(level_a, __builtin_amdgcn_exp2f(-y * y), level);
             else
-                return fma(level_a, ::exp(-y * y), level);
+                return fma(level_a, f64::exp_nonpos(-y * y), level);
         } else {
             return local_vol<VOL>(level, level_a, Real(0), spot, vt, y);
         }
@@ -334,6 +342,23 @@ __device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t
     return c;
 }
 
+// The per-asset constants of a launch as a constant-address-space object
+// at the uniform address cbase of its PathParams (the kernel-argument
+// segment, or the batch's descriptor table), through an address the
+// compiler cannot see through, so that their scalar loads are issued where
+// they are used instead of being hoisted out of the loop.
+template <typename Real>
+using ConstAssets = const __attribute__((address_space(4))) AssetConsts<Real>;
+
+template <typename Real>
+__device__ __forceinline__ ConstAssets<Real> &reload_consts(uint64_t cbase)
+{
+    uint64_t a = cbase + (sizeof(Real) == 8 ? offsetof(PathParams, cd)
+                                            : offsetof(PathParams, cf));
+    asm volatile("" : "+s"(a));
+    return *(ConstAssets<Real> *)a;
+}
+
 // ---------------------------------------------------------------------------
 // The Monte Carlo path kernel.
 // Grid: n * groups workgroups of kBlock lanes; workgroup (i, g) runs the
@@ -344,8 +369,8 @@ __device__ __forceinline__ u32x4 philox_block(uint32_t c0, uint32_t c1, uint32_t
 // function and channel per path: its loads must stay scalar (SGPR) loads,
 // so GammaPtr is a global restrict pointer or a constant-address-space one.
 template <int D, int ETA, typename Real, int VOL, int Q, typename GammaPtr,
-          int OP = kOpBasis>
-__device__ __forceinline__ void run_tile(const PathParams &prm,
+          int OP = kOpBasis, bool RELOAD = false>
+__device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
                                          const double *__restrict__ pts,
                                          GammaPtr gamma, const int i,
                                          const int g, double *__restrict__ out)
@@ -395,6 +420,10 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
     // so (L G)_j = S_j + L_jj G_j with S_{j+1} = S_j + Lcol[j] G_j -- the
     // terms of sum_k L_jk G_k in the same order, O(d) instead of O(d^2)
     const AssetConsts<Real> &ac = asset_consts<Real>(prm);
+    // FP64 one-problem kernels read the per-asset constants of the Euler
+    // step again for every group of steps (RELOAD; cbase is then the
+    // address of prm in constant memory)
+    constexpr bool kReloadConsts = RELOAD && sizeof(Real) == 8;
     const Real tscale = Real(2) / T;
     const Real neg_half_hk = Real(-0.5) * ES::kappa * h;
     const Real hk = ES::kappa * h;
@@ -457,6 +486,12 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
         for (int j = 0; j < D; ++j) X[j] = ES::to((Real)row[1 + j], lc);
         const int ngroups = (prm.N + SG - 1) / SG;
         for (int grp = 0; grp < ngroups; ++grp) {
+            // FP64: the per-asset constants of the step are read again for
+            // every group of steps through an address the compiler cannot
+            // see through (scalar loads from the constant cache); held
+            // across the loop they overflow the scalar registers and come
+            // back from vector-register lanes with one vector instruction
+            // per use
             Real G[4 * NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -466,6 +501,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                 Arith<Real>::box_muller(w.z, w.w, step_scale, G[4 * b + 2],
                                         G[4 * b + 3], c32, c33);
             }
+            auto steps = [&](auto &acs) {
 #pragma unroll
             for (int ss = 0; ss < SG; ++ss) {
                 const int s = grp * SG + ss;
@@ -482,19 +518,24 @@ __device__ __forceinline__ void run_tile(const PathParams &prm,
                         // kappa sqrt(h) (L G)_j; the first row of the Cholesky
                         // factor of a correlation matrix is (1, 0, ..., 0)
                         Real lg = G[ss * D];
-                        if (j > 0) lg = fma(ac.Ldiag[j], G[ss * D + j], S);
-                        if (j + 1 < D) S = j == 0 ? ac.Lcol[0] * G[ss * D]
-                                                  : fma(ac.Lcol[j], G[ss * D + j], S);
-                        const Real sig = ES::vol(lev[j], lva[j], ac.spot[j], vt, X[j]);
+                        if (j > 0) lg = fma(acs.Ldiag[j], G[ss * D + j], S);
+                        if (j + 1 < D) S = j == 0 ? acs.Lcol[0] * G[ss * D]
+                                                  : fma(acs.Lcol[j], G[ss * D + j], S);
+                        const Real sig = ES::vol(lev[j],
+                                                 kReloadConsts ? acs.level_a[j] : lva[j],
+                                                 acs.spot[j], vt, X[j]);
                         // X += (r - delta - sigma^2/2) h + sigma sqrt(h) (L G)
                         //    = X + (r - delta) h + sigma (sqrt(h) (L G) - h sigma / 2),
                         // every term times kappa
                         const Real inner = fma(sig, fma(neg_half_hk, sig, lg), X[j]);
                         if constexpr (kVecConst) X[j] = inner + dhk[j];
-                        else X[j] = fma(ac.drift[j], hk, inner);
+                        else X[j] = fma(acs.drift[j], hk, inner);
                     }
                 }
             }
+            };
+            if constexpr (kReloadConsts) steps(reload_consts<Real>(cbase));
+            else steps(ac);
         }
 
         // frozen coefficients at the last node t_{j*} and X at tau: the
@@ -1031,8 +1072,11 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real>())) void path_kernel(
 {
     const int i = blockIdx.x / prm.groups;
     const int g = blockIdx.x - i * prm.groups;
-    run_tile<D, ETA, Real, VOL, Q, const Real *__restrict__, OP>(
-        prm, pts, gamma, i, g, partial + 2 * (size_t)blockIdx.x);
+    // prm is the first kernel argument: its copy at the start of the
+    // kernel-argument segment is the one the scalar loads read
+    run_tile<D, ETA, Real, VOL, Q, const Real *__restrict__, OP, true>(
+        prm, (uint64_t)(uintptr_t)__builtin_amdgcn_kernarg_segment_ptr(), pts,
+        gamma, i, g, partial + 2 * (size_t)blockIdx.x);
 }
 
 // Many problems of one kernel signature in one persistent launch.  Tiles
@@ -1072,7 +1116,7 @@ __global__ __launch_bounds__(kBlock, (min_waves<D, Real>())) void batch_path_ker
         const int i = (int)(local / q.prm.groups);
         const int g = (int)(local - (long long)i * q.prm.groups);
         using ConstReal = const __attribute__((address_space(4))) Real *;
-        run_tile<D, ETA, Real, VOL, Q>(q.prm, q.pts, (ConstReal)q.gamma, i, g,
+        run_tile<D, ETA, Real, VOL, Q>(q.prm, 0, q.pts, (ConstReal)q.gamma, i, g,
                                     q.partial + 2 * local);
     }
 }

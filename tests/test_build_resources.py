@@ -8,9 +8,9 @@ workgroup and reloaded once per path -- outside the Euler loop and the
 matrix-core contraction (checked on the assembly).  One wave per SIMD
 removes the spill but runs them 15-50% slower (measured for both
 volatility kinds, eta = 2, 3 and the hyperbolic set).  Likewise the FP64
-d = 5 constant-volatility kernels at two waves per SIMD (about 110 bytes)
-and the FP64 d = 2, eta = 5 ones (28 bytes), outside the Euler loop, for
-about 30% less time per launch."""
+d = 5, eta = 3 kernels at two waves per SIMD (up to 124 bytes) and the FP64
+d = 2, eta = 5 ones (28 bytes), outside the Euler loop, for about 30% less
+time per launch."""
 import os
 
 import pytest
@@ -19,8 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RES = os.path.join(ROOT, "paper_1102_4666_amd", "_build", "resources.txt")
 # kernel-name pattern -> largest spill allowed (bytes per lane)
 ALLOWED = {"path_kernelILi10E": 280, "path_kernelILi5ELi2EdLi0E": 128,
-           "path_kernelILi5ELi3EdLi0E": 128, "path_kernelILi5ELi3EdLi1E": 16,
-           "path_kernelILi2ELi5Ed": 32}
+           "path_kernelILi5ELi3EdLi0E": 128, "path_kernelILi5ELi3EdLi1E": 64,
+           "path_kernelILi5ELi3EdLi2E": 32, "path_kernelILi2ELi5Ed": 32}
 
 
 def test_path_kernels_do_not_spill():
