@@ -1,23 +1,45 @@
 """Benchmark of the BSDE solver library on one MI355X.
 
-A step is one whole pricing job of the d=1 American put workload (local
-volatility 0.2 (1 + 0.25 exp(-(log(S/100))^2)), penalty 100, 128 space x 16
-time points, M=4000 paths, N=50 Euler steps, 8 Picard iterations):
-problem set-up (grid, basis, least-squares factorisation, upload), all
-Picard iterations on the GPU (path simulation, driver, reductions,
-least-squares update), the price/delta query, and tear-down.
+A step is one whole pricing job of the d=5 American geometric-basket put
+(local volatility level_j (1 + 0.25 exp(-(log(S/100))^2)) with levels
+U[0.15, 0.35], rho = 0.2, r = 0.05, K = S0 = 100, T = 1, penalty 1;
+4096 random spatial points x 10 time nodes, total degree 3 (84 basis
+functions), M = 1000 paths, N = 50 Euler steps, 10 Picard iterations) with
+FP64 paths, sums and update: problem set-up (grid, basis matrix, device
+least-squares factorisation, upload), every Picard iteration on the GPU
+(paths, driver, reductions, least-squares update), the price/delta query
+and tear-down.  `value` is Euler path-steps per second of whole jobs.
 
-Prints one JSON line: Euler path-steps per second of whole jobs, the
-roofline of the dominant kernel (the Monte Carlo path kernel, bound by
-vector-ALU issue), per-job latency percentiles, the error of the result
-against the FP64 oracle on the same random streams, and the oracle timed on
-a bounded sample of the same workload on the host CPU.
+The one JSON line also carries:
+  roofline      of the dominant kernel (the Monte Carlo path kernel of the
+                job): algorithmic FLOP per path-step counted from the
+                kernel's arithmetic, times the path-steps of one launch,
+                over the launch's mean duration (HIP events taken by the
+                dispatch on the solve's stream), against the FP64 vector
+                peak;
+  fp32_paths    the same job with FP32 paths and FP64 sums;
+  accuracy_gate |d price|/K and |d delta| against the stored FP64 oracle
+                results of every benchmark workload, in both precisions,
+                with pass/fail against the accuracy target (penalty-100
+                workloads are labelled "Picard not converged");
+  d1_amer_put   the d=1 American put workload (128x16 points, M=4000,
+                N=50, 8 iterations) in FP32 paths, with the issue-cycle
+                model of its path kernel as a secondary roofline;
+  batched_vs_fp64_per_problem  the d=1, 2, 5 workloads at penalty 1 in
+                one batched FP32-path solve (hipGraph) against the same
+                three solved one by one in FP64;
+  serving       the request mix (d in {1,2,5,10}) at saturation and at 0.5
+                and 0.9 of it, p50/p99 with the request counts, and the
+                alone-versus-mix check on sampled requests;
+  cpu_baseline  the oracle on a bounded sample of the same job, on one core
+                and over all host cores (disjoint point ranges).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,102 +50,165 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 CUs x 4 SIMDs at 2.4 GHz.  The path kernel is bound
-# by vector-ALU issue; its roofline counts shader cycles of issue per SIMD:
-# peak = 1024 SIMDs x 2.4e9 cycles/s.
-SIMD_ISSUE_CYCLES_PEAK = 256 * 4 * 2.4e9
-FP32_VECTOR_PEAK = 157.3e12                     # FLOP/s (packed FMA)
+FP32_VECTOR_PEAK = 157.3e12   # FLOP/s, MI355X (packed FMA)
 FP64_VECTOR_PEAK = 78.6e12
-# HBM traffic of one path-kernel launch of the benchmark workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (separate runs, KiB per dispatch) by
-# tiling (workgroups per point), scaled by the plain-copy calibration
-# factors (x2.0 and x1.0).  The autotuner picks the tiling at run time;
-# a tiling missing here reports null.
-TRAFFIC_KIB = {"fp32": {1: (177, 64), 2: (305, 128), 4: (305, 256),
-                        8: (305, 512), 16: (305, 1024)},
-               "fp64": {1: (268, 64), 2: (396, 128), 4: (396, 256),
-                        8: (396, 512), 16: (398, 1024)}}
-FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+SIMD_ISSUE_CYCLES_PEAK = 256 * 4 * 2.4e9   # 256 CUs x 4 SIMDs x 2.4 GHz
+METRIC = "Euler path-steps/s + priced requests/s (p50/p99) at stated price/delta error"
+
+# Gates of the accuracy target: |d price| <= tol * K, |d delta| <= tol
+GATE = {"fp64": (1e-4, 1e-4), "fp32": (5e-4, 5e-3)}
 
 
-def traffic_bytes(precision, groups):
-    fw = TRAFFIC_KIB.get(precision, {}).get(groups)
-    if fw is None:
-        return None
-    return (fw[0] * FETCH_FACTOR + fw[1] * WRITE_FACTOR) * 1024
+# ---------------------------------------------------------------------------
+# Algorithmic work of the path kernel
+# ---------------------------------------------------------------------------
+def flop_per_path_step(d, p, C, N, vol="bump", payoff="put_geom"):
+    """Algorithmic floating-point operations per Euler path-step of the path
+    kernel (FMA = 2, add or multiply = 1, exp/log/sqrt/sin/cos = 1 each;
+    integer Philox work and compares 0), counted from the kernel's
+    arithmetic.  Returns (total, of which the basis-row x channel-table
+    contraction).
+
+    Per asset and Euler step:
+      one normal, half a Box-Muller pair: two uniform maps (FMA each), log,
+      scale, sqrt, the angle's scale, cos and sin, two radius products:
+      (4 + 3 + 1 + 2 + 2) / 2 = 6;
+      (L G)_j with the prefix sum of the uniform correlation: 2 FMAs (d > 1);
+      bump volatility: square, exp, FMA = 4;
+      Euler update: 3 FMAs = 6.
+    Per path (amortised over N):
+      U and tau: 4; bridge normals: 6 per generated normal (4 ceil(d/4));
+      state at tau per asset: back to x (2), (L G) of step j* (4), frozen
+      volatility (4), frozen drift (2), X_tau (8), bridge correlation (4);
+      Chebyshev values: (2 d + 1) variates x (map 2 + 3 per recurrence);
+      basis rows: one product per function and row, 2 (p - 1);
+      contraction: 2 p C (at tau) + 2 p (u at T);
+      generator: 2 (C - 1) + d (d + 1) (covariances);
+      payoffs at tau and T; driver, path term and FP64 sums: 12."""
+    eta_rec = 3
+    normal = 6.0
+    corr = 4.0 if d > 1 else 0.0
+    volf = 4.0 if vol == "bump" else 0.0
+    per_asset_step = normal + corr + volf + 6.0
+    bridge = 6.0 * 4 * ((d + 3) // 4)
+    at_tau = d * (2 + 4 + 4 + 2 + 8 + 4)
+    # Chebyshev degree: p = binom(d + 1 + eta, eta) for the total degree
+    eta = 0
+    from math import comb
+    while comb(d + 1 + eta, eta) < p:
+        eta += 1
+    cheb = (2 * d + 1) * (2 + eta_rec * max(0, eta - 1))
+    basis = 2 * (p - 1)
+    contraction = 2.0 * p * C
+    uT = 2.0 * p
+    gen = 2 * (C - 1) + d * (d + 1)
+    pay = 2 * ((2 * d + 3) if payoff in ("put", "call") else (d + 3))
+    per_path = 4 + bridge + at_tau + cheb + basis + contraction + uT + gen + pay + 12
+    total = d * per_asset_step + per_path / N
+    return total, contraction / N
 
 
-# Algorithmic issue cycles per Euler path-step of one wave (64 paths) for
-# the d = 1 local-volatility workload (N = 50 steps per path), derived
-# operation by operation in the design doc section 6.  Issue cost per wave64
-# instruction on gfx950, measured by paper_1102_4666_amd/probe/issue_rates.hip
-# (profiles/valu_issue_rates_gfx950.md): 32-bit adds, multiplies, fused
-# multiply-adds and logic operations (v_bitop3_b32 included) whose operands
-# are all vector registers 2 cycles at best (2.1-3.3 measured), the same
-# with a scalar or literal operand 4, 64-bit multiply-adds, 32-bit integer
-# multiplies, conversions and funnel shifts 4, transcendentals 8 (they do
-# not issue beside other vector instructions).  Each operation is priced at
-# the cheapest form that computes it, so the bound is an optimistic one.
-ISSUE_CYCLES_PER_WAVE_STEP = {
-    "fp32": {
-        # 1/4 Philox4x32-10 block (the work on the uniform counter words and
-        # on m alone done once per path or on the scalar unit): 16
-        # v_mad_u64_u32 (4), two XORs and one three-input XOR with a uniform
-        # operand (4), 15 three-input XORs (2): 106
-        "normal_philox": (16 * 4 + 3 * 4 + 15 * 2) / 4,
-        # 1/2 Box-Muller pair: conversion, funnel shift (4); log, sqrt, sin,
-        # cos (8); fused multiply-add and three multiplies (2)
-        "normal_box_muller": (2 * 4 + 4 * 8 + 4 * 2) / 2,
-        # volatility: y*y (2), exp (8), fused multiply-add (2)
-        "local_vol": 2 + 8 + 2,
-        # Euler update: two fused multiply-adds and an add (2)
-        "euler": 3 * 2,
-        # the compare that selects step j* (2)
-        "record": 2,
-        # per path over N = 50: U and bridge blocks (2 x 106), one Box-Muller
-        # pair (48), 156 other operations at 2 (j*, theta, tau, X_tau, two
-        # Chebyshev rows, the 15 x 4 contraction and u(T), driver and
-        # generator, FP64 sums)
-        "per_path": (2 * 106 + 48 + 156 * 2) / 50.0,
-    },
-    # FP64 paths use software transcendentals with no independent operation
-    # count: the measured instructions per path-step, SQ_INSTS_VALU minus
-    # SQ_INSTS_VALU_TRANS_F64 (162.7 - 1.1) at 4 cycles and 1.1 at 8
-    "fp64": {"measured": 161.6 * 4 + 1.1 * 8},
+# Secondary roofline of the d=1 FP32 path kernel: issue cycles of one wave
+# per Euler path-step, each algorithmic operation priced at the cheapest
+# instruction form that computes it with the issue costs measured on gfx950
+# (profiles/valu_issue_rates_gfx950.md): FP32 adds, multiplies and FMAs with
+# vector operands 3.2 cycles, integer and logic forms with vector operands
+# 2.25 (v_bitop3_b32 included), forms with a scalar or literal operand,
+# 64-bit integer multiply-adds, conversions and funnel shifts 4.1,
+# transcendentals 8.3.
+ISSUE_COST = {"f32v": 3.2, "intv": 2.25, "four": 4.1, "trans": 8.3}
+ISSUE_CYCLES_D1_FP32 = {
+    # 1/4 Philox4x32-10 block: 16 v_mad_u64_u32, three XORs with a uniform
+    # operand, 15 three-input XORs with vector operands
+    "normal_philox": (16 * ISSUE_COST["four"] + 3 * ISSUE_COST["four"] +
+                      15 * ISSUE_COST["intv"]) / 4,
+    # 1/2 Box-Muller pair: conversion and funnel shift, log, sqrt, sin, cos,
+    # the uniform map's FMA and three multiplies
+    "normal_box_muller": (2 * ISSUE_COST["four"] + 4 * ISSUE_COST["trans"] +
+                          4 * ISSUE_COST["f32v"]) / 2,
+    # volatility: square, exp, FMA
+    "local_vol": 2 * ISSUE_COST["f32v"] + ISSUE_COST["trans"],
+    # Euler update: two FMAs and an add
+    "euler": 3 * ISSUE_COST["f32v"],
+    # the compare that selects step j*
+    "record": ISSUE_COST["intv"],
+    # per path over N = 50: U and bridge Philox blocks, one Box-Muller pair,
+    # 156 other FP32 operations
+    "per_path": (2 * (16 * ISSUE_COST["four"] + 3 * ISSUE_COST["four"] +
+                      15 * ISSUE_COST["intv"]) +
+                 2 * (2 * ISSUE_COST["four"] + 4 * ISSUE_COST["trans"] +
+                      4 * ISSUE_COST["f32v"]) + 156 * ISSUE_COST["f32v"]) / 50.0,
 }
-FP32_FLOP_PER_PATH_STEP = 4.5 + 4 + 6 + 250 / 50.0
+
+# HBM traffic of one launch of the headline path kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (separate --pmc runs, KiB per dispatch),
+# scaled by the plain-copy calibration (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0,
+# profiles/copy_calibration.md).  Valid only for the kernel sources whose
+# hash is recorded with it and for the tiling it was taken at; otherwise
+# the line reports null.
+TRAFFIC = None   # {"sources_sha16": ..., "tiling": [g, ppl], "fetch_kib": .., "write_kib": ..}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+KERNEL_SOURCES = ("paper_1102_4666_amd/csrc/bsde_path.h",
+                  "paper_1102_4666_amd/csrc/bsde_common.h",
+                  "paper_1102_4666_amd/csrc/bsde_inst_d5.hip")
 
 
-def workload(precision: str, omega: float = 100.0):
+def kernel_sources_sha16():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(tiling):
+    if TRAFFIC is None or list(tiling) != list(TRAFFIC["tiling"]):
+        return None
+    if TRAFFIC["sources_sha16"] != kernel_sources_sha16():
+        return None
+    return (TRAFFIC["fetch_kib"] * FETCH_FACTOR +
+            TRAFFIC["write_kib"] * WRITE_FACTOR) * 1024
+
+
+# ---------------------------------------------------------------------------
+# Jobs
+# ---------------------------------------------------------------------------
+def headline_workload(precision="fp64"):
     import workloads
-    return workloads.amer_put_d1(omega=omega, precision=precision)
+    return workloads.geo_basket_d5(omega=1.0, precision=precision)
 
+
+HEADLINE_NAME = ("d=5 American geometric-basket put, penalised BSDE (penalty 1), "
+                 "bump local vol with levels U[0.15,0.35], rho=0.2, 4096 random "
+                 "spatial points x 10 times, eta=3 (p=84), M=1000, N=50, "
+                 "10 Picard iterations")
 
 # (groups per point, paths per lane) set on every job by --tiling, in place
 # of the autotuned choice
 FORCED_TILING = None
 
 
-def run_job(cfg, stream, phases=None, solve_lock=None):
-    """One pricing job; phases (if a dict) accumulates the host wall time
-    of create / solve / query / destroy in milliseconds.  With solve_lock,
-    the solve holds it (jobs of other threads create and query meanwhile)."""
+def steps_of(cfg, n=None):
+    if n is None:
+        import oracle
+        n = oracle.sizes(cfg)[0]
+    return n * cfg["M"] * cfg["N"] * cfg["K_it"]
+
+
+def run_job(cfg, stream, phases=None):
+    """One pricing job; phases (if a dict) accumulates the host wall time of
+    create / solve / query / destroy in milliseconds."""
     import paper_1102_4666_amd as bsde
     t0 = time.perf_counter()
     P = bsde.Problem(cfg)
     if FORCED_TILING is not None:
         P.set_tiling(*FORCED_TILING)
-    if solve_lock is not None:
-        solve_lock.acquire()
     t1 = time.perf_counter()
-    try:
-        P.solve(stream)
-    finally:
-        if solve_lock is not None:
-            solve_lock.release()
+    P.solve(stream)
     t2 = time.perf_counter()
     price, delta = P.price_delta()
     timings = P.timings()
+    n = P.n
     t3 = time.perf_counter()
     P.close()
     t4 = time.perf_counter()
@@ -131,93 +216,126 @@ def run_job(cfg, stream, phases=None, solve_lock=None):
         for key, dt in (("create", t1 - t0), ("solve", t2 - t1),
                         ("query", t3 - t2), ("destroy", t4 - t3)):
             phases[key] = phases.get(key, 0.0) + 1e3 * dt
-    return price[0], delta[0], timings
+    return price[0], delta[0], timings, n
 
 
-def run_jobs(cfg, n_jobs, streams):
-    """n_jobs pricing jobs of cfg over len(streams) host threads, one HIP
-    stream each: job j runs on thread j % depth.  The solves (the Picard
-    iterations) take a lock, so that path kernels of two jobs never share
-    the GPU; the set-up of a job (host work and its small device kernels)
-    and the query and release of the previous one overlap the solve of
-    another.  Returns per-job latencies (s), path-kernel ms, timings and the
-    summed phase times."""
-    import threading
-    depth = len(streams)
-    lat, path_ms, kern_ms = [0.0] * n_jobs, [0.0] * n_jobs, [None] * n_jobs
-    phases = [dict() for _ in range(depth)]
-    errors = []
-    lock = threading.Lock() if depth > 1 else None
+def timed_jobs(cfg, steps, warmup, stream, tune=True):
+    """Autotunes the path tiling of cfg's kernel signature once, runs warmup
+    untimed jobs, then times `steps` jobs between device synchronisations."""
+    import torch
 
-    def worker(w):
-        try:
-            for j in range(w, n_jobs, depth):
-                ts = time.perf_counter()
-                _, _, tim = run_job(cfg, streams[w], phases[w], lock)
-                lat[j] = time.perf_counter() - ts
-                path_ms[j] = tim[0]
-                kern_ms[j] = tim
-        except Exception as e:  # reported by the caller
-            errors.append(e)
-
-    threads = [threading.Thread(target=worker, args=(w,)) for w in range(depth)]
-    for t in threads:
-        t.start()
-    for t in threads:
-        t.join()
-    if errors:
-        raise errors[0]
-    merged = {}
-    for ph in phases:
-        for k, v in ph.items():
-            merged[k] = merged.get(k, 0.0) + v
-    return lat, path_ms, kern_ms, merged
+    import paper_1102_4666_amd as bsde
+    if FORCED_TILING is not None:
+        tiling = FORCED_TILING
+    elif tune:
+        with bsde.Problem(cfg) as P:
+            tiling = P.autotune(stream)[:2]
+    else:
+        tiling = None
+    for _ in range(warmup):
+        run_job(cfg, stream)
+    torch.cuda.synchronize()
+    lat, kern, phases = [], [], {}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        price, delta, tim, n = run_job(cfg, stream, phases)
+        lat.append(time.perf_counter() - ts)
+        kern.append(tim)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = np.array(kern)
+    return {"wall": wall, "lat": lat, "path_ms": float(np.mean(kern[:, 0])),
+            "other_ms": float(np.mean(kern[:, 1])),
+            "solve_ms": float(np.mean(kern[:, 4])),
+            "phases": {k: v / steps for k, v in phases.items()},
+            "tiling": list(tiling) if tiling is not None else None,
+            "n": n, "price": price, "delta": delta}
 
 
-def accuracy(precision: str, stream):
-    """Error against the stored FP64 oracle results of the same workload."""
-    out = {}
-    for omega in (100.0, 1.0):
-        name = "amer_put_d1_w100" if omega == 100.0 else "amer_put_d1_w1"
-        path = os.path.join(ROOT, "tests", "golden", name + ".json")
-        if not os.path.exists(path):
-            continue
-        with open(path) as f:
-            g = json.load(f)
-        price, delta, _ = run_job(workload(precision, omega), stream)
-        ref_p, ref_d = g["price"][-1], g["delta"][-1][0]
-        out["omega=%g" % omega] = {
-            "price": price, "oracle_price": ref_p,
-            "abs_price_err_over_K": abs(price - ref_p) / 100.0,
-            "rel_price_err": abs(price - ref_p) / max(1.0, abs(ref_p)),
-            "delta": float(delta[0]), "oracle_delta": ref_d,
-            "abs_delta_err": abs(float(delta[0]) - ref_d),
-        }
+def roofline(cfg, n, path_ms, tiling, precision):
+    import oracle
+    p = oracle.sizes(cfg)[1]
+    d = cfg["d"]
+    C = 2 + d + d * (d + 1) // 2
+    fl, fl_mfma = flop_per_path_step(d, p, C, cfg["N"], cfg.get("vol_kind", "bump"),
+                                     cfg.get("payoff", "put"))
+    launch_steps = n * cfg["M"] * cfg["N"]
+    t = path_ms * 1e-3
+    achieved = fl * launch_steps / t
+    peak = FP64_VECTOR_PEAK if precision == "fp64" else FP32_VECTOR_PEAK
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic_bytes(tiling) if precision == "fp64" else None,
+            "kernel": "path_kernel<d=%d, eta=%d, %s>" % (
+                d, cfg["eta"], "double" if precision == "fp64" else "float"),
+            "launch_ms": path_ms, "path_steps_per_launch": launch_steps,
+            "flop_per_path_step": fl,
+            "of_which_contraction_flop_per_path_step": fl_mfma,
+            "target_frac": 0.5}
+
+
+def gate(precision, price, delta, ref_p, ref_d, K, omega):
+    tp, td = GATE[precision]
+    dp = abs(price - ref_p)
+    dd = float(np.max(np.abs(np.asarray(delta) - np.asarray(ref_d))))
+    out = {"abs_price_err_over_K": dp / K, "max_abs_delta_err": dd,
+           "gate_price_over_K": tp, "gate_delta": td,
+           "gate_pass": bool(dp <= tp * K and dd <= td)}
+    if omega >= 100:
+        out["label"] = "Picard not converged"
+        out["price_err_over_max_K_price"] = dp / max(K, abs(ref_p))
     return out
 
 
-def batched_vs_fp64(stream, reps: int = 2):
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+ACCURACY_CASES = ("eur_put_d1", "amer_put_d1_w1", "amer_put_d1_w100",
+                  "amer_basket_d2_w1", "amer_basket_d2_w100",
+                  "geo_basket_d5_w1", "geo_basket_d5_w100",
+                  "geo_basket_d5_redraw_w1")
+
+
+def accuracy_gate(stream):
+    """Every benchmark workload in both precisions against the stored FP64
+    oracle results of the same streams."""
+    out = {}
+    for name in ACCURACY_CASES:
+        g = _golden(name)
+        if g is None:
+            continue
+        for prec in ("fp64", "fp32"):
+            cfg = dict(g["cfg"], precision=prec)
+            price, delta, _, _ = run_job(cfg, stream)
+            r = gate(prec, price, delta, g["price"][-1], g["delta"][-1],
+                     cfg["K"], cfg["omega"])
+            r.update(price=price, oracle_price=g["price"][-1])
+            out["%s/%s" % (name, prec)] = r
+    return out
+
+
+def batched_vs_fp64(stream, reps=2):
     """The batched FP32-path form against the plain FP64 per-problem form on
-    the same GPU: three problems (the d = 1, 2 and 5 workloads, penalty
-    100) solved in one bsde_solve_batch call (one persistent path launch per
-    Picard step, the schedule captured as a hipGraph), against the same
-    three solved one after the other by bsde_solve in FP64.  Both are
-    checked against the stored FP64 oracle results of the same streams."""
+    the same GPU at penalty 1, where both must pass the accuracy gate: the
+    d = 1, 2 and 5 workloads solved in one bsde_solve_batch call (one
+    persistent path launch per Picard step and signature, the schedule
+    captured as a hipGraph), against the same three solved one after the
+    other by bsde_solve in FP64."""
     import torch
 
     import paper_1102_4666_amd as bsde
     import workloads
     names = ("amer_put_d1", "amer_basket_d2", "geo_basket_d5")
-    gold = {}
-    for nm in names:
-        path = os.path.join(ROOT, "tests", "golden", nm + "_w100.json")
-        if os.path.exists(path):
-            with open(path) as f:
-                g = json.load(f)
-            gold[nm] = (g["price"][-1], g["delta"][-1])
+    gold = {nm: _golden(nm + "_w1") for nm in names}
 
     def run(prec, batched):
-        probs = [bsde.Problem(getattr(workloads, nm)(precision=prec))
+        probs = [bsde.Problem(getattr(workloads, nm)(omega=1.0, precision=prec))
                  for nm in names]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -228,20 +346,14 @@ def batched_vs_fp64(stream, reps: int = 2):
                 P.solve(stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        steps = sum(P.n * P.cfg["M"] * P.cfg["N"] * P.cfg["K_it"]
-                    for P in probs)
+        steps = sum(P.n * P.cfg["M"] * P.cfg["N"] * P.cfg["K_it"] for P in probs)
         err = {}
         for nm, P in zip(names, probs):
             price, delta = P.price_delta()
-            if nm in gold:
-                ref_p, ref_d = gold[nm]
-                # prices of the penalised problem at penalty 100 are far
-                # from K (the iteration diverges); errors relative to the
-                # oracle's own price
-                err[nm] = {"rel_price_err": abs(price[0] - ref_p) / max(1.0, abs(ref_p)),
-                           "max_rel_delta_err": float(np.max(
-                               np.abs(delta[0] - np.asarray(ref_d)) /
-                               np.maximum(1.0, np.abs(ref_d))))}
+            g = gold[nm]
+            if g is not None:
+                err[nm] = gate(prec, price[0], delta[0], g["price"][-1],
+                               g["delta"][-1], P.cfg["K"], 1.0)
             P.close()
         return dt, steps, err
 
@@ -254,39 +366,45 @@ def batched_vs_fp64(stream, reps: int = 2):
             dt, steps, err = run(prec, batched)
             best = dt if best is None else min(best, dt)
         out[key] = {"seconds": best, "path_steps": steps,
-                    "path_steps_per_s": steps / best, "error_vs_oracle": err}
-    out["problems"] = "d=1 (128x16 grid, M=4000), d=2 (32^2x16, M=2000), " \
-                      "d=5 (4096x10, M=1000); N=50, penalty 100"
+                    "path_steps_per_s": steps / best, "accuracy": err,
+                    "all_gates_pass": all(e["gate_pass"] for e in err.values())}
+    out["problems"] = ("d=1 (128x16 grid, M=4000), d=2 (32^2x16, M=2000), "
+                       "d=5 (4096x10, M=1000); N=50, penalty 1")
     out["speedup"] = out["per_problem_fp64"]["seconds"] / \
         out["batched_fp32_paths"]["seconds"]
     return out
 
 
-def cpu_baseline(cfg, seconds: float = 12.0):
-    """The oracle on a bounded sample: per-point corrections of iteration 1
-    (coefficients present, so u^k and its derivatives are evaluated on every
-    path) for the first points of the grid, single thread."""
-    import oracle
-    n, p = oracle.sizes(cfg)
-    alpha = np.zeros(p)
-    t = time.perf_counter()
-    oracle.corrections(cfg, alpha, 1, 0, 1)
-    per_point = time.perf_counter() - t
-    n_sub = int(max(1, min(n, seconds / max(per_point, 1e-6))))
-    t = time.perf_counter()
-    oracle.corrections(cfg, alpha, 1, 0, n_sub)
-    dt = time.perf_counter() - t
-    steps = n_sub * cfg["M"] * cfg["N"]
-    return {"value": steps / dt, "unit": "path-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "iteration-1 corrections of the first %d of %d points "
-                      "(M=%d, N=%d): %.3g path-steps in %.1f s" %
-                      (n_sub, n, cfg["M"], cfg["N"], steps, dt)}
+def d1_leg(steps, stream):
+    """The d=1 American put workload (penalty 1) in FP32 paths: whole-job
+    throughput and its path kernel's roofline, with the issue-cycle model."""
+    import workloads
+    cfg = workloads.amer_put_d1(omega=1.0, precision="fp32")
+    r = timed_jobs(cfg, steps, 1, stream)
+    launch_steps = r["n"] * cfg["M"] * cfg["N"]
+    cyc = sum(ISSUE_CYCLES_D1_FP32.values()) * launch_steps / 64
+    t = r["path_ms"] * 1e-3
+    return {"workload": "d=1 American put, penalty 1, bump local vol, 128x16 "
+                        "points, eta=4, M=4000, N=50, 8 Picard iterations",
+            "dtype": "f32 paths, f64 sums",
+            "path_steps_per_s": steps_of(cfg, r["n"]) * steps / r["wall"],
+            "ms_per_job": 1e3 * r["wall"] / steps, "tiling": r["tiling"],
+            "roofline": roofline(cfg, r["n"], r["path_ms"], r["tiling"], "fp32"),
+            "issue_cycle_model": {
+                "cycles_per_wave_path_step": sum(ISSUE_CYCLES_D1_FP32.values()),
+                "achieved_T_cycles_per_s": cyc / t / 1e12,
+                "peak_T_cycles_per_s": SIMD_ISSUE_CYCLES_PEAK / 1e12,
+                "frac": cyc / t / SIMD_ISSUE_CYCLES_PEAK}}
 
 
-def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
-    """Serving run: closed-loop saturation, then Poisson arrivals at 0.5 and
-    0.9 of the saturation rate; p50/p99 latency and throughput per phase."""
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+def serve(n_requests, n_sat, n_check, seed=0, dims=(1, 2, 5, 10)):
+    """Closed-loop saturation (n_sat requests submitted at once), then
+    Poisson arrivals at 0.5 and 0.9 of the saturation rate (n_requests each);
+    p50/p99 latency and throughput per phase; then n_check sampled requests
+    of the last phase solved alone and compared with their served results."""
     import torch
 
     import paper_1102_4666_amd as bsde
@@ -295,10 +413,11 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
     rng = np.random.default_rng(seed)
-    reqs = [workloads.serving_request(i, rng, dims) for i in range(n_requests)]
 
-    def run_phase(rate):
-        lat = []
+    def make(count, first):
+        return [workloads.serving_request(first + i, rng, dims) for i in range(count)]
+
+    def run_phase(reqs, rate, tag):
         with bsde.Server(budget, max_inflight=64) as S:
             t0 = time.perf_counter()
             arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs))) \
@@ -312,41 +431,126 @@ def serve(n_requests: int, seed: int = 0, dims=(1, 2, 5, 10)):
             res = []
             for j, t in enumerate(out):
                 res.append(S.poll(t))
-                if (j + 1) % 10 == 0:
-                    print("serving: %d/%d done after %.1f s" %
-                          (j + 1, len(out), time.perf_counter() - t0),
+                if (j + 1) % 25 == 0:
+                    print("serving %s: %d/%d done after %.1f s" %
+                          (tag, j + 1, len(out), time.perf_counter() - t0),
                           file=sys.stderr, flush=True)
             wall = time.perf_counter() - t0
             st = S.stats()
-        bad = [r["status"] for r in res if r["status"] != 0]
+        lat = np.array([r["latency_ms"] for r in res])
         per_d = {}
         for cfg, r in zip(reqs, res):
             per_d.setdefault(cfg["d"], []).append(r["latency_ms"])
-        return {"offered_rate": rate, "requests": len(reqs), "failed": len(bad),
+        return {"offered_rate": rate, "requests": len(reqs),
+                "failed": sum(r["status"] != 0 for r in res),
                 "wall_s": wall, "requests_per_s": st["requests_per_s"],
                 "path_steps_per_s": st["path_steps_per_s"],
-                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)),
+                "p99_sample_note": "p99 of %d requests" % len(reqs),
                 "latency_ms_by_d": {
-                    "d=%d" % d: {"n": len(v),
-                                 "p50": float(np.percentile(v, 50)),
+                    "d=%d" % d: {"n": len(v), "p50": float(np.percentile(v, 50)),
                                  "max": float(np.max(v))}
                     for d, v in sorted(per_d.items())},
-                "engine_steps": st["engine_steps"]}
+                "engine_steps": st["engine_steps"]}, res
 
-    print("serving: saturation phase", file=sys.stderr, flush=True)
-    sat = run_phase(None)
-    print("serving: %.2f requests/s at saturation" % sat["requests_per_s"],
-          file=sys.stderr, flush=True)
+    print("serving: saturation phase (%d requests)" % n_sat, file=sys.stderr, flush=True)
+    sat, _ = run_phase(make(n_sat, 0), None, "saturation")
     x_sat = sat["requests_per_s"]
-    return {"mix": "d in %s, K U[80,120], European/American 50/50, M in "
-                   "{500,1000,2000,4000} (d=10: 8192x10 random points, "
-                   "eta=3, every other request at M=500), FP32 paths"
-                   % (list(dims),),
+    print("serving: %.2f requests/s at saturation" % x_sat, file=sys.stderr, flush=True)
+    r05, _ = run_phase(make(n_requests, 10000), 0.5 * x_sat, "0.5 load")
+    reqs09 = make(n_requests, 20000)
+    r09, res09 = run_phase(reqs09, 0.9 * x_sat, "0.9 load")
+    # alone versus mix: sampled requests of the 0.9-load phase solved alone
+    pick = np.random.default_rng(seed + 1).choice(len(reqs09), min(n_check, len(reqs09)),
+                                                  replace=False)
+    same = 0
+    worst = 0.0
+    for j in pick:
+        cfg = reqs09[j]
+        with bsde.Problem(cfg) as P:
+            P.solve()
+            pr, de = P.price_delta()
+        served = res09[j]
+        dmax = float(np.max(np.abs(de[0] - served["delta"][:cfg["d"]])))
+        worst = max(worst, abs(pr[0] - served["price"]), dmax)
+        same += int(pr[0] == served["price"] and dmax == 0.0)
+    print("serving: alone-vs-mix on %d requests: %d bitwise equal" % (len(pick), same),
+          file=sys.stderr, flush=True)
+    return {"mix": "d in %s, K U[80,120], European/American (penalty 0/1) 50/50, "
+                   "M in {500,1000,2000,4000} (d=10: 8192x10 random points, eta=3, "
+                   "M=500), N=50, FP32 paths" % (list(dims),),
             "hbm_budget_bytes": budget, "saturation": sat,
-            "load_0.5": run_phase(0.5 * x_sat),
-            "load_0.9": run_phase(0.9 * x_sat)}
+            "load_0.5": r05, "load_0.9": r09,
+            "alone_vs_mix": {"checked": len(pick), "bitwise_equal": same,
+                             "max_abs_difference": worst}}
 
 
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands
+# ---------------------------------------------------------------------------
+def _cpu_chunk(args):
+    import oracle
+    cfg, alpha, a, b = args
+    t = time.perf_counter()
+    oracle.corrections(cfg, alpha, 1, a, b)
+    return time.perf_counter() - t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, seconds=10.0, max_procs=16):
+    """The oracle on a bounded sample of the headline job: the per-point
+    corrections of one Picard iteration with non-zero coefficients (the
+    least-squares fit of the payoff at the points, so u^k, its time
+    derivative, gradient and Hessian are evaluated on every path) for the
+    first points of the grid.  One core, then one process per usable core
+    (at most max_procs) over disjoint point ranges, the paper's own
+    parallel axis."""
+    import multiprocessing as mp
+
+    import oracle
+    n, p = oracle.sizes(cfg)
+    pts = oracle.points(cfg)
+    y = np.array([oracle.payoff(cfg, pts[i, 1:]) for i in range(n)])
+    alpha = oracle.fit(cfg, y)
+    t1 = _cpu_chunk((cfg, alpha, 0, 2)) / 2
+    n1 = int(max(1, min(n, seconds / max(t1, 1e-6))))
+    dt1 = _cpu_chunk((cfg, alpha, 0, n1))
+    single = n1 * cfg["M"] * cfg["N"] / dt1
+    cores = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    per = n1
+    ranges = [(cfg, alpha, (c * per) % n, min(n, (c * per) % n + per)) for c in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t = time.perf_counter()
+        pool.map(_cpu_chunk, ranges)
+        wall = time.perf_counter() - t
+    pts_done = sum(b - a for _, _, a, b in ranges)
+    allc = pts_done * cfg["M"] * cfg["N"] / wall
+    return {"value": allc, "unit": "path-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "iteration-1 corrections (coefficients of a least-squares "
+                      "fit of the payoff) of %d points per process, M=%d, N=%d, "
+                      "of the %d-point headline grid; %d processes over disjoint "
+                      "point ranges, %.3g path-steps in %.1f s"
+                      % (per, cfg["M"], cfg["N"], n, cores,
+                         pts_done * cfg["M"] * cfg["N"], wall),
+            "single_core": {"value": single, "unit": "path-steps/s",
+                            "sample": "%d points in %.1f s" % (n1, dt1)},
+            "host_cpu": cpu_model(), "nproc": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
+
+
+# ---------------------------------------------------------------------------
 def _overrides(text):
     """'k=v,k=v' -> dict, values as int, float or string."""
     out = {}
@@ -364,11 +568,10 @@ def _overrides(text):
 
 
 def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
-    """One Picard iteration (one path-kernel launch) of each named workload,
-    FP32 paths, default tiling: the runs behind the profiles of the
-    matrix-core kernels.  Names: amer_put_d1, amer_basket_d2, geo_basket_d5,
-    eur_put_d1_kernel (the kernel operator of Section 3.2), d10-serving
-    (the d=10 request shape of the serving mix at M=500),
+    """One Picard iteration (one path-kernel launch) of each named workload:
+    the runs behind the profiles.  Names: amer_put_d1, amer_basket_d2,
+    geo_basket_d5, eur_put_d1_kernel (the kernel operator of Section 3.2),
+    d10-serving (the d=10 request shape of the serving mix at M=500),
     call_basket_d10_hyperbolic (the hyperbolic-set kernel, p=221).
     euler_steps replaces N (separates per-step from per-path cost);
     overrides (a dict) replaces workload fields (eta, q, vol_kind, ...)."""
@@ -392,7 +595,6 @@ def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
             out[nm] = {"path_kernel_ms": P.timings()[0],
                        "path_steps": P.n * cfg["M"] * cfg["N"]}
             if cfg.get("kernel_bw", 0.0) > 0.0:
-                # the kernel operator weighs every (path, point) pair
                 out[nm]["kernel_pairs"] = P.n * cfg["M"] * P.n
     return out
 
@@ -400,22 +602,26 @@ def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--pipeline", type=int, default=1, metavar="DEPTH",
-                    help="pricing jobs in flight (host threads): the set-up "
-                         "of one overlaps the Picard iterations of another "
-                         "(default 1: one job after the other)")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64"],
+                    help="precision of the headline job (default fp64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the error check against stored oracle results")
-    ap.add_argument("--serve", type=int, default=24, metavar="R",
+                    help="skip the gate check against stored oracle results")
+    ap.add_argument("--serve", type=int, default=200, metavar="R",
                     help="requests per load level of the request-server "
                          "benchmark (0 = skip it)")
+    ap.add_argument("--serve-sat", type=int, default=100, metavar="R",
+                    help="requests of the closed-loop saturation phase")
+    ap.add_argument("--serve-check", type=int, default=50, metavar="R",
+                    help="served requests re-solved alone for the "
+                         "alone-versus-mix check")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-FP32 vs per-problem-FP64 comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP32-path and d=1 legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the "
                          "HBM byte counters of the profiler)")
@@ -427,14 +633,12 @@ def main():
                          "eta=2,q=1.0,vol_kind=const")
     ap.add_argument("--tiling", default="", metavar="G,P",
                     help="run every job at G workgroups per point and P paths "
-                         "per lane instead of the autotuned tiling (for counter "
-                         "runs that must see one tiling)")
+                         "per lane instead of the autotuned tiling")
     ap.add_argument("--single-launch", default="", metavar="NAMES",
                     help="comma-separated workloads (amer_put_d1, amer_basket_d2, "
                          "geo_basket_d5, eur_put_d1_kernel, d10-serving, "
-                         "call_basket_d10_hyperbolic): run one "
-                         "path-kernel launch of each and print its time, nothing "
-                         "else")
+                         "call_basket_d10_hyperbolic): run one path-kernel "
+                         "launch of each and print its time, nothing else")
     args = ap.parse_args()
     global FORCED_TILING
     if args.tiling:
@@ -444,6 +648,12 @@ def main():
               "path (one problem's points would shard across GPUs with a "
               "p-vector all-reduce per iteration; not built)", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's processes are forked before anything initialises the GPU
+    cpu = None
+    if not (args.no_cpu_baseline or args.copy_calibration or args.single_launch):
+        print("cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(headline_workload("fp64"), args.cpu_seconds)
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -455,90 +665,70 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4,
-                          "copy_bytes_written": dst.numel() * 4,
-                          "copies": 3}))
+                          "copy_bytes_written": dst.numel() * 4, "copies": 3}))
         return
     if args.single_launch:
         print(json.dumps(single_launches(args.single_launch.split(","),
                                          args.euler_steps or None, args.precision,
                                          _overrides(args.set))))
         return
-    if args.pipeline < 1:
-        ap.error("--pipeline must be at least 1")
     stream = torch.cuda.current_stream().cuda_stream
-    cfg = workload(args.precision)
-    n = cfg["n_t"] * cfg["n_x"]
-    steps_per_job = n * cfg["M"] * cfg["N"] * cfg["K_it"]
 
-    # tune the path tiling of this kernel signature once; problems created
-    # afterwards start with the recorded choice
-    import paper_1102_4666_amd as bsde
-    if FORCED_TILING is not None:
-        tiling = FORCED_TILING
-    else:
-        with bsde.Problem(cfg) as P:
-            tiling = P.autotune(stream)
-    # job pipeline: one stream per host thread (default priority)
-    streams = [stream] + [torch.cuda.Stream().cuda_stream
-                          for _ in range(args.pipeline - 1)]
-    run_jobs(cfg, args.warmup, streams)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat, path_ms, kern_ms, phases = run_jobs(cfg, args.steps, streams)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
-
-    # roofline of the path kernel: algorithmic VALU slots per launch over
-    # its mean duration (HIP events on the solve's stream)
-    t_path = float(np.mean(path_ms)) * 1e-3
-    launch_steps = n * cfg["M"] * cfg["N"]
-    cyc = sum(ISSUE_CYCLES_PER_WAVE_STEP[args.precision].values()) * launch_steps / 64
-    achieved = cyc / t_path
+    print("headline: %d warm-up and %d timed jobs" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    cfg = headline_workload(args.precision)
+    r = timed_jobs(cfg, args.steps, args.warmup, stream)
+    per_job = steps_of(cfg, r["n"])
+    g = _golden("geo_basket_d5_w1")
     line = {
-        "metric": "Euler path-steps/s + priced requests/s (p50/p99) at stated price/delta error",
-        "value": steps_per_job * args.steps / wall,
+        "metric": METRIC,
+        "value": per_job * args.steps / r["wall"],
         "unit": "path-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * r["wall"] / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 paths, f64 sums" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 paths, f64 sums",
         "data": "synthetic",
-        "config": {"workload": "d=1 American put, penalised BSDE (penalty 100), "
-                               "bump local vol, 128x16 grid, M=4000, N=50, "
-                               "8 Picard iterations, eta=4",
-                   "path_steps_per_job": steps_per_job,
-                   "jobs_in_flight": args.pipeline,
+        "config": {"workload": HEADLINE_NAME, "path_steps_per_job": per_job,
                    "precision": args.precision},
-        "requests_per_s": args.steps / wall,
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99))},
-        "path_kernel_ms": float(np.mean(path_ms)),
-        "tiling": {"groups_per_point": tiling[0], "paths_per_lane": tiling[1]},
-        "job_phase_ms": {k: v / args.steps for k, v in phases.items()},
-        "kernel_ms_per_iteration": dict(zip(
-            ["path", "reduce_project_update"],
-            [float(x) for x in np.mean(kern_ms, axis=0)[:2]])),
-        "solve_ms": float(np.mean(kern_ms, axis=0)[4]),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                     "peak": SIMD_ISSUE_CYCLES_PEAK / 1e12,
-                     "unit": "T SIMD vector-issue cycles/s (algorithmic)",
-                     "frac": achieved / SIMD_ISSUE_CYCLES_PEAK,
-                     "traffic": traffic_bytes(args.precision, tiling[0])},
+        "requests_per_s": args.steps / r["wall"],
+        "latency_ms": {"p50": 1e3 * float(np.percentile(r["lat"], 50)),
+                       "p99": 1e3 * float(np.percentile(r["lat"], 99))},
+        "path_kernel_ms": r["path_ms"], "tiling": r["tiling"],
+        "job_phase_ms": r["phases"],
+        "kernel_ms_per_iteration": {"path": r["path_ms"],
+                                    "reduce_project_update": r["other_ms"]},
+        "solve_ms": r["solve_ms"],
+        "roofline": roofline(cfg, r["n"], r["path_ms"], r["tiling"], args.precision),
     }
-    if args.precision == "fp32":
-        fl = FP32_FLOP_PER_PATH_STEP * launch_steps / t_path
-        line["fp32_vector_flops"] = {"achieved_tflops": fl / 1e12,
-                                     "peak_tflops": FP32_VECTOR_PEAK / 1e12,
-                                     "frac": fl / FP32_VECTOR_PEAK}
+    if g is not None:
+        line["headline_accuracy"] = gate(args.precision, r["price"], r["delta"],
+                                         g["price"][-1], g["delta"][-1], cfg["K"], 1.0)
+    print("headline: %.4g path-steps/s" % line["value"], file=sys.stderr, flush=True)
+    if not args.no_extra:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        c2 = headline_workload(other)
+        r2 = timed_jobs(c2, args.steps, 1, stream)
+        leg = {"dtype": "f32 paths, f64 sums" if other == "fp32" else "f64",
+               "path_steps_per_s": steps_of(c2, r2["n"]) * args.steps / r2["wall"],
+               "ms_per_job": 1e3 * r2["wall"] / args.steps, "tiling": r2["tiling"],
+               "roofline": roofline(c2, r2["n"], r2["path_ms"], r2["tiling"], other)}
+        if g is not None:
+            leg["accuracy"] = gate(other, r2["price"], r2["delta"], g["price"][-1],
+                                   g["delta"][-1], c2["K"], 1.0)
+        line["fp32_paths" if other == "fp32" else "fp64_paths"] = leg
+        line["d1_amer_put"] = d1_leg(max(5, args.steps), stream)
+        print("extra legs done", file=sys.stderr, flush=True)
     if not args.no_accuracy:
-        line["accuracy_vs_oracle"] = accuracy(args.precision, stream)
+        line["accuracy_gate"] = accuracy_gate(stream)
+        print("accuracy gate done", file=sys.stderr, flush=True)
     if not args.no_batched:
         line["batched_vs_fp64_per_problem"] = batched_vs_fp64(stream)
+        print("batched comparison done", file=sys.stderr, flush=True)
     if args.serve:
-        line["serving"] = serve(args.serve, dims=(1, 2, 5, 10))
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(workload("fp64"), args.cpu_seconds)
+        line["serving"] = serve(args.serve, args.serve_sat, args.serve_check)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -199,7 +199,13 @@ static void engine_loop(bsde_server_s *S)
                                                    std::floor(quantum / cost[j])));
         bsde_status st = run_batch(hs.data(), (int)hs.size(), S->stream, 1, false, false,
                                    nullptr, steps.data());
-        S->engine_steps += 1;
+        {
+            // engine_steps is read by bsde_server_stats under the mutex
+            std::lock_guard<std::mutex> g(S->mu);
+            S->engine_steps += 1;
+        }
+        // a request's result is read only after complete() marks it done
+        // under the mutex, after these writes
         for (Request *q : S->active) q->result.engine_steps += 1;
         std::vector<Request *> still;
         for (Request *q : S->active) {

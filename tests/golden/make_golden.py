@@ -4,6 +4,13 @@ Calls only the oracle (``oracle/``): the per-point corrections of every
 iteration are spread over worker processes with ``oracle.solve_parallel``,
 which runs the same oracle functions in the same order as ``oracle.solve``.
 
+Each case writes ``<name>.json`` (problem, price and deltas of every
+iteration, the corrections of a fixed sample of at most 2048 points, and
+whole-grid sums) and ``<name>.c.npz`` (every per-point correction of every
+iteration, FP64, array ``c`` of shape K_it x n, and the sample variance of
+the path terms of every point, FP32, array ``var``: it sets each point's
+tolerance scale).
+
     python tests/golden/make_golden.py eur_put_d1 [amer_put_d1 ...] [--workers 8]
 """
 from __future__ import annotations
@@ -78,6 +85,9 @@ def main():
         path = os.path.join(HERE, name + ".json")
         with open(path, "w") as f:
             json.dump(out, f)
+        np.savez_compressed(os.path.join(HERE, name + ".c.npz"),
+                            c=np.asarray(res["c"], dtype=np.float64),
+                            var=np.asarray(res["var"], dtype=np.float32))
         print("wrote", path, "price", prices[-1], flush=True)
 
 

@@ -24,24 +24,58 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_issue_cycle_model():
+def test_issue_cycle_model_uses_measured_costs():
     b = _bench()
-    fp32 = b.ISSUE_CYCLES_PER_WAVE_STEP["fp32"]
-    # the per-term counts of the operation-by-operation derivation
-    assert fp32["normal_philox"] == pytest.approx(106 / 4)
-    assert fp32["normal_box_muller"] == pytest.approx(24.0)
-    assert fp32["per_path"] == pytest.approx(572 / 50)
-    assert sum(fp32.values()) == pytest.approx(81.94)
-    assert sum(b.ISSUE_CYCLES_PER_WAVE_STEP["fp64"].values()) == pytest.approx(655.2)
+    c = b.ISSUE_COST
+    assert (c["f32v"], c["intv"], c["four"], c["trans"]) == (3.2, 2.25, 4.1, 8.3)
+    m = b.ISSUE_CYCLES_D1_FP32
+    philox_block = 16 * 4.1 + 3 * 4.1 + 15 * 2.25
+    assert m["normal_philox"] == pytest.approx(philox_block / 4)
+    assert m["normal_box_muller"] == pytest.approx((2 * 4.1 + 4 * 8.3 + 4 * 3.2) / 2)
+    assert m["local_vol"] == pytest.approx(2 * 3.2 + 8.3)
     assert b.SIMD_ISSUE_CYCLES_PEAK == pytest.approx(1024 * 2.4e9)
 
 
-def test_traffic_table():
+def test_flop_count_of_the_path_kernel():
     b = _bench()
-    # measured tilings report calibrated bytes; others report null
-    assert b.traffic_bytes("fp32", 8) == (305 * 2.0 + 512 * 1.0) * 1024
-    assert b.traffic_bytes("fp32", 3) is None
-    assert b.traffic_bytes("bf16", 8) is None
+    # d = 1, eta = 4 (p = 15, C = 4), N = 50, arithmetic put: 16 FLOP per
+    # asset-step plus the per-path work over 50 steps
+    tot, mf = b.flop_per_path_step(1, 15, 4, 50, "bump", "put")
+    per_path = 4 + 24 + 24 + 3 * (2 + 3 * 3) + 28 + 120 + 30 + 6 + 2 + 10 + 12
+    assert tot == pytest.approx(16 + per_path / 50)
+    assert mf == pytest.approx(120 / 50)
+    # d = 5, eta = 3 (p = 84, C = 22), geometric put: 20 per asset-step
+    tot, mf = b.flop_per_path_step(5, 84, 22, 50, "bump", "put_geom")
+    assert mf == pytest.approx(2 * 84 * 22 / 50)
+    assert 180 < tot < 195
+    # d = 10, eta = 3 (p = 364, C = 67)
+    tot, mf = b.flop_per_path_step(10, 364, 67, 50, "bump", "put")
+    assert mf == pytest.approx(2 * 364 * 67 / 50)
+    assert 1200 < tot < 1250
+
+
+def test_traffic_is_null_unless_measured_for_these_sources():
+    b = _bench()
+    saved = b.TRAFFIC
+    try:
+        b.TRAFFIC = None
+        assert b.traffic_bytes([1, 4]) is None
+        b.TRAFFIC = {"sources_sha16": b.kernel_sources_sha16(), "tiling": [1, 4],
+                     "fetch_kib": 100.0, "write_kib": 50.0}
+        assert b.traffic_bytes([1, 4]) == (100.0 * 2.0 + 50.0 * 1.0) * 1024
+        assert b.traffic_bytes([2, 2]) is None
+        b.TRAFFIC = dict(b.TRAFFIC, sources_sha16="0" * 16)
+        assert b.traffic_bytes([1, 4]) is None
+    finally:
+        b.TRAFFIC = saved
+
+
+def test_gate_labels_the_diverging_penalty():
+    b = _bench()
+    ok = b.gate("fp64", 6.8, [0.1], 6.8 + 5e-4, [0.1 + 5e-5], 100.0, 1.0)
+    assert ok["gate_pass"] and "label" not in ok
+    bad = b.gate("fp32", -5.2e8, [1.0], -5.2e8 + 77.7, [80.5], 100.0, 100.0)
+    assert not bad["gate_pass"] and bad["label"] == "Picard not converged"
 
 
 def test_single_launch_overrides():

@@ -128,8 +128,9 @@ def call_basket_d10_hyperbolic(precision: str = "fp32") -> dict:
 def serving_request(idx: int, rng: np.random.Generator,
                     dims=(1, 2, 5, 10)) -> dict:
     """One request of the serving mix: d drawn from dims, strike U[80,120],
-    European/American 50/50, M in {500,1000,2000,4000}, FP32 paths; the
-    grid and Euler sizes of the benchmark workload of that dimension."""
+    European/American 50/50, M in {500,1000,2000,4000} (d = 10: M = 500,
+    8192 random spatial points x 10 times), FP32 paths; the grid and Euler
+    sizes of the benchmark workload of that dimension."""
     d = int(rng.choice(list(dims)))
     K = float(rng.uniform(80.0, 120.0))
     american = bool(rng.integers(0, 2))
@@ -145,7 +146,7 @@ def serving_request(idx: int, rng: np.random.Generator,
                        bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, S0=100.0,
                        T=1.0, payoff="put", grid="random", n_t=10,
                        n_x=8192, eta=3, N=50, K_it=10)
-        M = 500 if M > 500 and idx % 2 else M
+        M = 500   # the d = 10 request shape of the mix is stated at M = 500
     cfg = copy.deepcopy(base)
     cfg.update(K=K, M=M, omega=(1.0 if american else 0.0), seed=1 + idx,
                precision="fp32")
