@@ -278,6 +278,29 @@ bsde_status bsde_set_timing(bsde_problem h, int level);
 bsde_status bsde_solve_batch(bsde_problem *problems, int count,
                              void *hip_stream, int flags, double *ms);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * batched solve as bsde_solve_batch without graph capture and without
+ * timing, whose descriptor tables and tile counters (the only device
+ * memory bsde_solve_batch takes beyond the problems' own buffers) live in
+ * a fixed workspace compiled into the library, 4 MiB per device, held on
+ * each device used until the process ends, instead of memory from the
+ * library's allocator.  The problems (created beforehand; their buffers
+ * are the inputs and outputs) and their results are those of
+ * bsde_solve_batch, bit for bit.  The tile counters are cleared by a fill
+ * kernel at the start of every call.  Every call on a device uses that
+ * device's one workspace: the library serialises calls of one process per
+ * device (each returns after its kernels are done); work the caller
+ * enqueues on other streams while a call runs must not depend on it.
+ * Returns after completion.
+ * Errors: BSDE_EINVAL (also when the batch's tables exceed the workspace:
+ * about 2.4 KB per problem and iteration step), BSDE_ESTATE (a problem's
+ * tiling was changed to one needing a larger per-group sum buffer than
+ * it was created with), BSDE_EUNSUPPORTED (redrawn points, the kernel
+ * operator), BSDE_EDEVICE. */
+bsde_status bsde_solve_batch_noalloc(bsde_problem *problems, int count,
+                                     void *hip_stream);
+
 void bsde_destroy(bsde_problem h);
 
 /* ------------------------------------------------------------------------

@@ -35,7 +35,7 @@ EXPORTS = [
     "bsde_problem_sizes", "bsde_get_points", "bsde_get_coefficients",
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
     "bsde_set_tiling", "bsde_autotune", "bsde_last_timings", "bsde_set_timing",
-    "bsde_solve_batch",
+    "bsde_solve_batch", "bsde_solve_batch_noalloc",
     "bsde_destroy", "bsde_status_string", "bsde_last_error",
     "bsde_server_create", "bsde_server_submit", "bsde_server_poll",
     "bsde_server_stats", "bsde_server_destroy",
@@ -122,6 +122,7 @@ def lib():
         L.bsde_autotune.argtypes = [H, C.c_void_p, _ip, _ip, _dp]
         L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
                                        C.c_int, _dp]
+        L.bsde_solve_batch_noalloc.argtypes = [C.POINTER(H), C.c_int, C.c_void_p]
         L.bsde_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int,
                                          C.POINTER(H)]
         L.bsde_server_submit.argtypes = [H, C.POINTER(Request),
@@ -291,6 +292,19 @@ def bsde_solve_batch(handles, stream=None, graph=False):
 def solve_batch(problems, stream=None, graph=False):
     """bsde_solve_batch over Problem objects."""
     return bsde_solve_batch([P.h for P in problems], stream, graph)
+
+
+def bsde_solve_batch_noalloc(handles, stream=None):
+    """The batched solve with its tables in the library's fixed workspace
+    (no device allocation)."""
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    _check(lib().bsde_solve_batch_noalloc(arr, len(handles), C.c_void_p(stream or 0)),
+           "bsde_solve_batch_noalloc")
+
+
+def solve_batch_noalloc(problems, stream=None):
+    """bsde_solve_batch_noalloc over Problem objects."""
+    bsde_solve_batch_noalloc([P.h for P in problems], stream)
 
 
 def bsde_destroy(h):

@@ -696,6 +696,13 @@ const char *bsde_status_string(bsde_status s)
 
 const char *bsde_last_error(void) { return g_last_error.c_str(); }
 
+} // extern "C"
+
+static bsde_status prepare_tiling(bsde_problem h, int &groups, int &ppl,
+                                  bool allow_alloc = true);
+
+extern "C" {
+
 bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
                                 const bsde_payoff *payoff,
                                 const bsde_grid *grid, int M, int N,
@@ -1028,6 +1035,15 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
             h->ppl = it->second.second;
         }
     }
+    // the per-group sum buffer of the tiling the problem starts with, so
+    // that solving it allocates nothing more
+    int groups0, ppl0;
+    const bsde_status tst = prepare_tiling(h, groups0, ppl0);
+    if (tst != BSDE_OK) {
+        free_device(h);
+        delete h;
+        return tst;
+    }
     *out = h;
     return BSDE_OK;
 }
@@ -1047,14 +1063,20 @@ bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
     return BSDE_OK;
 }
 
-// Tiling of a solve and the per-group sum buffer it needs.
-static bsde_status prepare_tiling(bsde_problem h, int &groups, int &ppl)
+// Tiling of a solve and the per-group sum buffer it needs (grown from the
+// pool unless allow_alloc is false: then a buffer too small is an error).
+static bsde_status prepare_tiling(bsde_problem h, int &groups, int &ppl,
+                                  bool allow_alloc)
 {
     groups = h->groups;
     ppl = h->ppl;
     if (groups == 0) auto_tiling(h, groups, ppl);
     const size_t need = (size_t)h->n * groups * 2;
     if (need > h->partial_cap) {
+        if (!allow_alloc)
+            return fail(BSDE_ESTATE, "the problem's tiling needs a larger per-group sum "
+                                     "buffer than it was created with (solve it once with "
+                                     "an allocating entry point first)");
         pool_free(h->d_partial);
         h->d_partial = nullptr;
         h->partial_cap = 0;
@@ -1252,12 +1274,13 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
 // Copies the coefficient histories back when copy_back is set.
 bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                             int steps, bool graph, bool copy_back, double *ms,
-                            const int *steps_each)
+                            const int *steps_each, void *workspace,
+                            size_t workspace_bytes)
 {
     std::vector<int> G(count), PPL(count), R(count);
     int S = 0;
     for (int q = 0; q < count; ++q) {
-        bsde_status st = prepare_tiling(probs[q], G[q], PPL[q]);
+        bsde_status st = prepare_tiling(probs[q], G[q], PPL[q], workspace == nullptr);
         if (st != BSDE_OK) return st;
         // iterations problem q runs in this call
         R[q] = std::max(0, std::min(steps_each ? steps_each[q] : steps,
@@ -1336,12 +1359,23 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     const size_t ctr_off = (blob.size() + 255) & ~(size_t)255;
     blob.resize(ctr_off + sizeof(unsigned int) * std::max(1, n_counters), 0);
 
+    // the descriptor tables and tile counters: from the pool, or in the
+    // caller's workspace
     char *dblob = nullptr;
-    HIP_TRY(pool_alloc((void **)&dblob, blob.size()));
+    if (workspace) {
+        if (blob.size() > workspace_bytes)
+            return fail(BSDE_EINVAL, "the batch's descriptor tables need " +
+                                         std::to_string(blob.size()) +
+                                         " bytes, more than the workspace of " +
+                                         std::to_string(workspace_bytes));
+        dblob = (char *)workspace;
+    } else {
+        HIP_TRY(pool_alloc((void **)&dblob, blob.size()));
+    }
     struct Release {
         char *p;
         ~Release() { pool_free(p); }
-    } release{dblob};
+    } release{workspace ? nullptr : dblob};
     HIP_TRY(hipMemcpyAsync(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
     unsigned int *counters = (unsigned int *)(dblob + ctr_off);
 
@@ -1371,10 +1405,13 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         return hipSuccess;
     };
 
-    hipEvent_t e0, e1;
-    HIP_TRY(event_get(&e0));
-    HIP_TRY(event_get(&e1));
-    HIP_TRY(hipEventRecord(e0, s));
+    // timing events only when the time is asked for
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        HIP_TRY(event_get(&e0));
+        HIP_TRY(event_get(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
     if (graph) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
@@ -1396,13 +1433,17 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     } else {
         HIP_TRY(enqueue());
     }
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
-    float t = 0.f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    event_put(e0);
-    event_put(e1);
-    if (ms) *ms = t;
+    if (ms) {
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        event_put(e0);
+        event_put(e1);
+        *ms = t;
+    } else {
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     for (int q = 0; q < count; ++q) {
         bsde_problem h = probs[q];
         h->k_done += R[q];
@@ -1488,6 +1529,52 @@ bsde_status bsde_solve_batch(bsde_problem *problems, int count,
     bsde_status st = run_batch(problems, count, s, 1 << 30, graph, true, ms);
     if (own) (void)hipStreamDestroy(own);
     return st;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// The no-allocation batched solve.  Its descriptor tables and tile counters
+// live in this fixed array, one copy per device, held until the process
+// ends.  In host code the array's name is not a device address: the
+// address of the current device's copy comes from hipGetSymbolAddress on
+// the first call on that device and is used everywhere after.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = size_t(4) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;            // one call per device at a time
+std::map<int, void *> g_scratch;    // device -> address of its copy
+} // namespace
+
+extern "C" {
+
+bsde_status bsde_solve_batch_noalloc(bsde_problem *problems, int count,
+                                     void *hip_stream)
+{
+    if (!problems || count < 1) return fail(BSDE_EINVAL, "no problems");
+    for (int q = 0; q < count; ++q) {
+        if (!problems[q]) return fail(BSDE_EINVAL, "null handle in batch");
+        for (int r = 0; r < q; ++r)
+            if (problems[r] == problems[q]) return fail(BSDE_EINVAL, "duplicate handle in batch");
+        if (problems[q]->redraw)
+            return fail(BSDE_EUNSUPPORTED, "points redrawn every iteration: use bsde_solve");
+        if (problems[q]->kop)
+            return fail(BSDE_EUNSUPPORTED, "the kernel operator: use bsde_solve");
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(BSDE_EDEVICE, std::string("workspace address: ") + hipGetErrorString(e));
+        it = g_scratch.emplace(dev, ptr).first;
+    }
+    return run_batch(problems, count, (hipStream_t)hip_stream, 1 << 30, false, true,
+                     nullptr, nullptr, it->second, kNoAllocBytes);
 }
 
 bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,

@@ -55,10 +55,14 @@ namespace bsde {
 bsde_status fail(bsde_status s, const std::string &msg);
 // runs `steps` Picard iterations (steps_each[q] for problem q when given;
 // at most the remaining ones) of every problem with the batched kernels;
-// copies coefficient histories back when copy_back is set
+// copies coefficient histories back when copy_back is set; the descriptor
+// tables and tile counters go to workspace (device memory of
+// workspace_bytes) when given, else to memory from the library's pool;
+// ms (may be null) receives the GPU time
 bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s, int steps,
                       bool graph, bool copy_back, double *ms,
-                      const int *steps_each = nullptr);
+                      const int *steps_each = nullptr, void *workspace = nullptr,
+                      size_t workspace_bytes = 0);
 // copies the latest coefficients of a finished problem back to the host
 bsde_status fetch_coefficients(bsde_problem h);
 // device bytes a problem with these parameters allocates (pool size classes)
