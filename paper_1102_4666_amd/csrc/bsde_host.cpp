@@ -172,6 +172,62 @@ void event_put(hipEvent_t e)
     std::lock_guard<std::mutex> g(g_ev_mu);
     g_events.push_back(e);
 }
+
+// Side streams of a device for the parallel branches of a batched solve
+// (default priority, non-blocking), with the events that fork them from and
+// join them back to the caller's stream.  Created once per device; the
+// batched solves of one device take turns on them.
+struct SideStreams {
+    static constexpr int kCount = 3; // with the caller's stream, four queues
+    hipStream_t s[kCount] = {};
+    hipEvent_t fork = nullptr, join[kCount] = {};
+    std::mutex mu;
+};
+std::mutex g_side_mu;
+std::map<int, SideStreams *> g_side;
+hipError_t side_streams(SideStreams **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(g_side_mu);
+    auto it = g_side.find(dev);
+    if (it != g_side.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    auto *ss = new SideStreams(); // kept until the process ends
+    for (int k = 0; k < SideStreams::kCount && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&ss->s[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming);
+    if (e != hipSuccess) return e; // (the partial set is not reused)
+    g_side[dev] = ss;
+    *out = ss;
+    return hipSuccess;
+}
+
+// The instantiated graph of the last captured batched solve of a device,
+// with the descriptor tables it reads and the launch plan it was captured
+// from (a later batch with the same tables and plan replays it).
+struct GraphCache {
+    std::vector<char> blob;
+    std::vector<long long> launches;
+    char *dblob = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        pool_free(dblob);
+        dblob = nullptr;
+        blob.clear();
+        launches.clear();
+    }
+};
+std::mutex g_graph_mu;
+std::map<int, GraphCache> g_graph_cache;
 } // namespace
 
 bsde_status bsde::fail(bsde_status s, const std::string &msg)
@@ -1379,6 +1435,22 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     HIP_TRY(hipMemcpyAsync(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
     unsigned int *counters = (unsigned int *)(dblob + ctr_off);
 
+    // Launches of different kernel signatures in one step run as parallel
+    // branches: the first on s, the others on the library's side streams of
+    // this device (forked from s and joined back before the step's update),
+    // so that the tiles of one signature fill the tail of another's launch.
+    // The no-allocation form keeps everything on s.
+    const bool parallel = workspace == nullptr;
+    SideStreams *side = nullptr;
+    std::unique_lock<std::mutex> side_lock; // held until the batch is done
+    if (parallel) {
+        bool fork_any = false;
+        for (int step = 0; step < S; ++step) fork_any |= plan[step].paths.size() > 1;
+        if (fork_any) {
+            HIP_TRY(side_streams(&side));
+            side_lock = std::unique_lock<std::mutex>(side->mu);
+        }
+    }
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = launch_reset_counters(counters, std::max(1, n_counters), s);
         if (e != hipSuccess) return e;
@@ -1386,15 +1458,30 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                                   (const BatchUpdateDesc *)(dblob + init_off));
         if (e != hipSuccess) return e;
         for (int step = 0; step < S; ++step) {
-            for (const PathLaunch &pl : plan[step].paths) {
+            const int nl = (int)plan[step].paths.size();
+            const int nside = side ? std::min(nl - 1, SideStreams::kCount) : 0;
+            if (nside > 0) {
+                e = hipEventRecord(side->fork, s);
+                for (int k = 0; k < nside && e == hipSuccess; ++k)
+                    e = hipStreamWaitEvent(side->s[k], side->fork, 0);
+                if (e != hipSuccess) return e;
+            }
+            for (int j = 0; j < nl; ++j) {
+                const PathLaunch &pl = plan[step].paths[j];
+                hipStream_t ls = (j == 0 || nside == 0) ? s : side->s[(j - 1) % nside];
                 const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta, pl.sig.q10,
                                                             pl.sig.fp32, pl.sig.vol));
                 const long long cap = (long long)occ * num_cus();
                 const int blocks = (int)std::max(1LL, std::min(pl.tiles, cap));
-                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.q10, pl.sig.fp32, pl.sig.vol, blocks, s,
+                e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.q10, pl.sig.fp32, pl.sig.vol, blocks, ls,
                                  (const BatchTileDesc *)(dblob + pl.desc_off), pl.nprob,
                                  (const long long *)(dblob + pl.begin_off),
                                  counters + pl.counter);
+                if (e != hipSuccess) return e;
+            }
+            for (int k = 0; k < nside; ++k) {
+                e = hipEventRecord(side->join[k], side->s[k]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s, side->join[k], 0);
                 if (e != hipSuccess) return e;
             }
             e = launch_batch_update(plan[step].nact, plan[step].max_n, plan[step].max_p,
@@ -1413,23 +1500,63 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         HIP_TRY(hipEventRecord(e0, s));
     }
     if (graph) {
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t le = enqueue();
-        hipError_t ce = hipStreamEndCapture(s, &g);
-        if (le != hipSuccess || ce != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(BSDE_EDEVICE, std::string("graph capture: ") +
-                                          hipGetErrorString(le != hipSuccess ? le : ce));
+        // The instantiated graph of the last captured batch on this device
+        // is kept with its descriptor tables; a batch whose tables and
+        // launch plan are byte for byte the same (the same problems, from
+        // the same iteration) replays it instead of capturing again.  The
+        // tables hold every address and parameter the kernels read, so
+        // equal tables mean the same work.
+        std::vector<long long> launches;
+        for (int step = 0; step < S; ++step) {
+            for (const PathLaunch &pl : plan[step].paths)
+                launches.insert(launches.end(), {pl.sig.d, pl.sig.eta, pl.sig.q10, pl.sig.fp32,
+                                                 pl.sig.vol, (long long)pl.desc_off,
+                                                 (long long)pl.begin_off, pl.nprob, pl.tiles,
+                                                 pl.counter});
+            launches.insert(launches.end(), {-1, (long long)plan[step].upd_off, plan[step].nact,
+                                             plan[step].max_n, plan[step].max_p,
+                                             plan[step].max_C});
         }
-        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
+        launches.insert(launches.end(), {count, max_C_all, (long long)init_off, n_counters,
+                                         (long long)(side != nullptr)});
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> gl(g_graph_mu);
+        GraphCache &gc = g_graph_cache[dev];
+        const bool hit = gc.exec && gc.blob == blob && gc.launches == launches;
+        if (!hit) {
+            gc.release();
+            // the cached graph owns its descriptor tables: move them out of
+            // this call's release
+            gc.dblob = dblob;
+            release.p = nullptr;
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t le = enqueue();
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                gc.release();
+                return fail(BSDE_EDEVICE, std::string("graph capture: ") +
+                                              hipGetErrorString(le != hipSuccess ? le : ce));
+            }
+            hipError_t ie = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                gc.exec = nullptr;
+                gc.release();
+                return fail(BSDE_EDEVICE, std::string("graph instantiate: ") +
+                                              hipGetErrorString(ie));
+            }
+            gc.blob = blob;
+            gc.launches = launches;
+        }
+        hipError_t ie = hipGraphLaunch(gc.exec, s);
         if (ie == hipSuccess) ie = hipStreamSynchronize(s);
-        if (ge) (void)hipGraphExecDestroy(ge);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess)
+        if (ie != hipSuccess) {
+            gc.release();
             return fail(BSDE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
+        }
     } else {
         HIP_TRY(enqueue());
     }
