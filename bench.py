@@ -599,6 +599,49 @@ def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
     return out
 
 
+# The paper's d = 10 benchmark (Section 6.2.1): European call basket,
+# Black-Scholes sigma = 0.2, rho = 0.2, K = S0 = 100, T = 1, r = 0.05,
+# n = 1000 points redrawn every iteration, M = 30,000, N = 10, 10 Picard
+# iterations; benchmark price 7.0207, CI (7.0125, 7.0288).
+D10_BENCHMARK = 7.0207
+D10_SETS = ((2, 1.0), (3, 1.0), (5, 0.5), (5, 0.6), (5, 0.7))
+
+
+def d10_sparsity_study(seeds=8):
+    """Bias against sparsity of the index set: the paper's d = 10 call
+    basket on the total-degree sets eta = 2, 3 and the hyperbolic sets
+    eta = 5, q = 0.5, 0.6, 0.7, each over `seeds` seeds; mean, seed spread
+    and the difference from the benchmark price."""
+    import paper_1102_4666_amd as bsde
+    import workloads
+    out = []
+    for eta, q in D10_SETS:
+        cfg = workloads.call_basket_d10_hyperbolic()
+        cfg.update(eta=eta, q=q)
+        prices, ms = [], []
+        p = None
+        for seed in range(seeds):
+            t = time.perf_counter()
+            with bsde.Problem(dict(cfg, seed=seed)) as P:
+                P.solve()
+                prices.append(float(P.price_delta()[0][0]))
+                p = P.p if q == 1.0 else None
+            ms.append(1e3 * (time.perf_counter() - t))
+        if p is None:
+            import oracle
+            p = len(oracle.index_set(11, eta, q))
+        m, sd = float(np.mean(prices)), float(np.std(prices, ddof=1))
+        out.append({"eta": eta, "q": q, "p": p, "mean_price": m, "seed_std": sd,
+                    "std_of_mean": sd / np.sqrt(seeds), "bias": m - D10_BENCHMARK,
+                    "ms_per_solve": float(np.mean(ms))})
+        print("d=10 eta=%d q=%g p=%d: %.4f +- %.4f" % (eta, q, p, m, sd),
+              file=sys.stderr, flush=True)
+    return {"workload": "d=10 European call basket (Section 6.2.1), n=1000 uniform "
+                        "points redrawn every iteration, domain +-1 sd, M=30000, "
+                        "N=10, 10 Picard iterations, FP32 paths",
+            "benchmark": D10_BENCHMARK, "seeds": seeds, "sets": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -639,6 +682,11 @@ def main():
                          "geo_basket_d5, eur_put_d1_kernel, d10-serving, "
                          "call_basket_d10_hyperbolic): run one path-kernel "
                          "launch of each and print its time, nothing else")
+    ap.add_argument("--study", default="", choices=["", "d10-sparsity"],
+                    help="run a study instead of the benchmark: d10-sparsity = "
+                         "price of the paper's d=10 call basket against the "
+                         "index set (total degree 2, 3; hyperbolic eta=5, "
+                         "q=0.5, 0.6, 0.7)")
     args = ap.parse_args()
     global FORCED_TILING
     if args.tiling:
@@ -651,7 +699,8 @@ def main():
 
     # the oracle's processes are forked before anything initialises the GPU
     cpu = None
-    if not (args.no_cpu_baseline or args.copy_calibration or args.single_launch):
+    if not (args.no_cpu_baseline or args.copy_calibration or args.single_launch
+            or args.study):
         print("cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(headline_workload("fp64"), args.cpu_seconds)
 
@@ -666,6 +715,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4,
                           "copy_bytes_written": dst.numel() * 4, "copies": 3}))
+        return
+    if args.study == "d10-sparsity":
+        print(json.dumps(d10_sparsity_study()))
         return
     if args.single_launch:
         print(json.dumps(single_launches(args.single_launch.split(","),

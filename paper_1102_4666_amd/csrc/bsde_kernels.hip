@@ -291,6 +291,8 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
     int batch_occupancy_d##D(int eta, int q10, bool fp32, int vol);            \
     bool has_variant_d##D(int eta, int q10, bool fp32, int vol);
 BSDE_DIMS(DECL)
+// the hyperbolic-set kernels of d = 10 (their own translation unit)
+DECL(10h)
 #undef DECL
 hipError_t launch_kernel_path_d1(bool fp32, int blocks, hipStream_t s,
                                  const PathParams &prm, const double *pts,
@@ -322,6 +324,10 @@ hipError_t launch_kernel_path(int d, bool fp32, int blocks, hipStream_t s,
 
 int index_table(int d, int eta, int q10, int8_t *nu, int cap)
 {
+    if (d == 10) {
+        const int p = index_table_d10h(eta, q10, nu, cap);
+        if (p > 0) return p;
+    }
 #define X(D)                                                                   \
     if (d == D) return index_table_d##D(eta, q10, nu, cap);
     BSDE_DIMS(X)
@@ -336,6 +342,7 @@ bool kernel_exists(int d, int eta, int q10)
 
 bool variant_exists(int d, int eta, int q10, bool fp32, int vol)
 {
+    if (d == 10 && has_variant_d10h(eta, q10, fp32, vol)) return true;
 #define X(D)                                                                   \
     if (d == D) return has_variant_d##D(eta, q10, fp32, vol);
     BSDE_DIMS(X)
@@ -348,6 +355,9 @@ hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream
                        const void *gamma, double *partial, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
+    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
+        return launch_path_d10h(eta, q10, fp32, blocks, s, prm, pts, gamma, partial,
+                                ev0, ev1);
 #define X(D)                                                                   \
     if (d == D)                                                                \
         return launch_path_d##D(eta, q10, fp32, blocks, s, prm, pts, gamma,    \
@@ -361,6 +371,9 @@ hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter)
 {
+    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
+        return launch_batch_d10h(eta, q10, fp32, vol, blocks, s, probs, nprob,
+                                 tile_begin, counter);
 #define X(D)                                                                   \
     if (d == D)                                                                \
         return launch_batch_d##D(eta, q10, fp32, vol, blocks, s, probs, nprob, \
@@ -372,6 +385,8 @@ hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
 
 int batch_occupancy(int d, int eta, int q10, bool fp32, int vol)
 {
+    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
+        return batch_occupancy_d10h(eta, q10, fp32, vol);
 #define X(D)                                                                   \
     if (d == D) return batch_occupancy_d##D(eta, q10, fp32, vol);
     BSDE_DIMS(X)

@@ -1186,8 +1186,11 @@ int copy_index_table(int8_t *nu, int cap)
             });                                                                \
     }
 
-#define BSDE_DEFINE_DIMENSION(D, SETS)                                         \
-    hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,       \
+#define BSDE_DEFINE_DIMENSION(D, SETS) BSDE_DEFINE_DIMENSION_NAMED(D, D, SETS)
+// the same for a second group of sets of dimension D in a translation unit
+// of its own: the functions are named with NAME (launch_path_dNAME, ...)
+#define BSDE_DEFINE_DIMENSION_NAMED(D, NAME, SETS)                             \
+    hipError_t launch_path_d##NAME(int eta, int q10, bool fp32, int blocks,    \
                                 hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial,            \
@@ -1197,13 +1200,13 @@ int copy_index_table(int8_t *nu, int cap)
         SETS(BSDE_PATH_SET)                                                    \
         return hipErrorInvalidValue;                                           \
     }                                                                          \
-    int index_table_d##D(int eta, int q10, int8_t *nu, int cap)                \
+    int index_table_d##NAME(int eta, int q10, int8_t *nu, int cap)                \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         SETS(BSDE_TABLE_SET)                                                   \
         return 0;                                                              \
     }                                                                          \
-    hipError_t launch_batch_d##D(int eta, int q10, bool fp32, int vol,         \
+    hipError_t launch_batch_d##NAME(int eta, int q10, bool fp32, int vol,         \
                                  int blocks,                                   \
                                  hipStream_t s, const BatchTileDesc *probs,    \
                                  int nprob, const long long *tile_begin,       \
@@ -1213,14 +1216,14 @@ int copy_index_table(int8_t *nu, int cap)
         SETS(BSDE_BATCH_SET)                                                   \
         return hipErrorInvalidValue;                                           \
     }                                                                          \
-    int batch_occupancy_d##D(int eta, int q10, bool fp32, int vol)             \
+    int batch_occupancy_d##NAME(int eta, int q10, bool fp32, int vol)             \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         int nb = 0;                                                            \
         SETS(BSDE_OCC_SET)                                                     \
         return nb;                                                             \
     }                                                                          \
-    bool has_variant_d##D(int eta, int q10, bool fp32, int vol)                \
+    bool has_variant_d##NAME(int eta, int q10, bool fp32, int vol)                \
     {                                                                          \
         constexpr int D_ = D;                                                  \
         SETS(BSDE_HAS_SET)                                                     \
