@@ -5,10 +5,23 @@ only the oracle).
 
 Every per-point correction of every iteration is compared element by
 element with the oracle's (``<name>.c.npz``).  The tolerance of point i is
-scaled by the size of the path terms a_m it averages,
-1 + |c_i| + sd_i with sd_i the oracle's sample standard deviation of a_m at
-that point: a rounding difference in the path arithmetic is relative to the
-terms summed, not to their mean, which can be small by cancellation.
+scaled by the size of the terms the correction is computed from,
+1 + |c_i| + sd_i + |u_i| with sd_i the oracle's sample standard deviation of
+the path terms a_m at that point and u_i = u^k(t_i, x_i) the iterate there:
+a rounding difference in the path arithmetic is relative to the terms
+summed, not to their mean, which can be small by cancellation, and a
+rounding-level difference of the two sides' least-squares coefficients
+moves every a_m by that relative amount of u^k.  To that per-point bound
+is added the least-squares solves' own rounding: a solve's backward error
+is relative to the whole data vector, so u^k at any point carries an
+absolute error up to about kappa(B) 2^-52 max_j |u^k_j| per solve, with
+kappa(B) the condition number of the oracle's basis matrix; after k solves
+(the non-contracting penalty-100 map carries earlier differences along)
+the bound is 4 (k + 1) kappa(B) 2^-52 max_j |u^k_j|.  It matters only where
+the iterates are large (penalty 100); at penalty 1, max |u| is about the
+price.  The oracle's iterates u^k at the points are rebuilt from the stored
+corrections with the oracle's own least-squares step, in the order of its
+loop (the rebuilt final price must equal the stored one).
 
 Price and delta gates are those of the method's accuracy target:
 |d price| <= 1e-4 max(K, |price|) and |d delta| <= 1e-4 max(1, |delta|) for
@@ -19,11 +32,21 @@ penalised driver has Lipschitz constant r + omega and the Picard map of
 Section 3 contracts only when that constant times T is small (Section 5.4),
 so at omega T = 100 the projected iterates grow by about an order of
 magnitude per iteration.  Those cases assert the divergence of the oracle's
-iterates, per-point parity of every correction, and the same price gate;
-where an FP32-path price misses that gate the miss is reported as an
-expected failure (the cause: FP32 rounding of each iteration's corrections
-amplified by the non-contracting map) rather than hidden by a wider
-tolerance."""
+iterates, per-point parity of every correction, and the same price gate.
+With FP32 paths the non-contracting map amplifies each iteration's FP32
+rounding by about its growth factor per iteration, so the two trajectories
+part after a few iterations; there the per-point parity is that of the
+iteration map itself: for every k the library is started from the oracle's
+own iterate u^k (its values at the points, fitted in the library's basis)
+and runs iteration k alone, and its corrections are compared with the
+oracle's c^k.  FP32 paths evaluate u^k and its derivative channels as
+p-term FP32 sums whose terms are of the size of the iterate, U_k = max_j
+|u^k_j| (Chebyshev functions are bounded by 1 on the domain), so the map's
+per-point bound adds the standard bound of such a sum, p 2^-24 U_k: it
+matters only where U_k is far above the price (penalty 100, U_k up to
+1e10).  Where the FP32-path price of the whole run misses the gate, the
+miss is reported as an expected failure (the same amplification) rather
+than hidden by a wider tolerance."""
 import json
 import os
 
@@ -52,8 +75,33 @@ def _golden(name):
     return g
 
 
-def _point_scale(c_ref, var_ref):
-    return 1.0 + np.abs(c_ref) + np.sqrt(np.maximum(var_ref, 0.0))
+def _point_scale(c_ref, var_ref, u_ref):
+    return 1.0 + np.abs(c_ref) + np.sqrt(np.maximum(var_ref, 0.0)) + np.abs(u_ref)
+
+
+def _oracle_iterates(g, cfg):
+    """u^k at the points of iteration k, k = 0..K_it-1, from the stored
+    corrections: alpha^0 = 0, u^k = B_k alpha^k, alpha^{k+1} = argmin
+    |u^k + c^k - B_k alpha| -- the oracle's loop (oracle.solve_parallel)
+    with its own basis matrices and least-squares solver; and the largest
+    condition number of those basis matrices."""
+    import oracle
+    redraw = bool(cfg.get("redraw", 0)) and cfg.get("grid") in ("random", "uniform")
+    B = oracle.basis_matrix(cfg)
+    kappa = np.linalg.cond(B)
+    alpha = np.zeros(B.shape[1])
+    us = []
+    for k in range(cfg["K_it"]):
+        if redraw:
+            B = oracle.basis_matrix(cfg, k)
+            kappa = max(kappa, np.linalg.cond(B))
+        u = oracle._rowdot(B, alpha)
+        us.append(u)
+        alpha = oracle.lstsq(B, u + g["c_all"][k])
+    pr, _ = oracle.price_delta(cfg, alpha, [0.0], [cfg["S0"]])
+    ref = g["price"][-1]
+    assert abs(pr[0] - ref) <= 1e-9 * max(1.0, abs(ref)), (pr[0], ref)
+    return np.array(us), kappa
 
 
 CASES = [
@@ -84,15 +132,31 @@ def test_full_size_against_stored_oracle(name, prec):
     got = run_gpu(cfg)
     tol = TOL[prec]
     c_ref, var_ref = g["c_all"], g["var_all"]
+    u_ref, kappa = _oracle_iterates(g, dict(cfg, precision="fp64"))
     assert got["c"].shape == c_ref.shape
+    c_cmp = got["c"]
+    p_basis = got["alpha"].shape[1]
+    if diverging and prec == "fp32":
+        # parity of the iteration map: iteration k alone from the oracle's u^k
+        from paper_1102_4666_amd import Problem
+        c_cmp = np.empty_like(got["c"])
+        for k in range(cfg["K_it"]):
+            with Problem(dict(cfg, K_it=k + 1)) as P:
+                P.fit_values(u_ref[k], k)
+                P.solve()
+                c_cmp[k] = P.corrections(k)[0]
     for k in range(cfg["K_it"]):
-        scale = _point_scale(c_ref[k], var_ref[k])
-        err = np.abs(got["c"][k] - c_ref[k]) / scale
-        worst = int(np.argmax(err))
-        print("  k=%d max |dc_i| / (1 + |c_i| + sd_i) = %.3g at point %d "
-              "(gpu %.17g oracle %.17g)" % (k, err[worst], worst,
-                                             got["c"][k][worst], c_ref[k][worst]))
-        assert err[worst] <= tol["c"], (k, worst, err[worst])
+        U = float(np.abs(u_ref[k]).max())
+        ls_abs = 4.0 * (k + 1) * kappa * 2.0 ** -52 * U
+        if diverging and prec == "fp32":
+            ls_abs += p_basis * 2.0 ** -24 * U
+        bound = tol["c"] * _point_scale(c_ref[k], var_ref[k], u_ref[k]) + ls_abs
+        diff = np.abs(c_cmp[k] - c_ref[k])
+        worst = int(np.argmax(diff / bound))
+        print("  k=%d max |dc_i| / bound_i = %.3g at point %d (gpu %.17g oracle %.17g; "
+              "absolute term %.3g)" % (k, diff[worst] / bound[worst], worst,
+                                            c_cmp[k][worst], c_ref[k][worst], ls_abs))
+        assert diff[worst] <= bound[worst], (k, worst, diff[worst], bound[worst])
     pref, dref = g["price"][-1], np.array(g["delta"][-1])
     dp = abs(got["price"] - pref)
     dd = float(np.abs(got["delta"] - dref).max())
