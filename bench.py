@@ -146,7 +146,18 @@ ISSUE_CYCLES_D1_FP32 = {
 # profiles/copy_calibration.md).  Valid only for the kernel sources whose
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
-TRAFFIC = None   # {"sources_sha16": ..., "tiling": [g, ppl], "fetch_kib": .., "write_kib": ..}
+TRAFFIC = {"sources_sha16": "bcc971886b277878", "tiling": [4, 1],
+           "fetch_kib": 18890.0, "write_kib": 11260.0,
+           "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
+# Counter-derived figures of the same kernel (same profile, same guard):
+# VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
+# busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
+# issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
+COUNTERS = {"sources_sha16": "bcc971886b277878", "tiling": [4, 1],
+            "valu_issue": 0.786, "mfma_busy": 0.092,
+            "fp64_vector_flop_per_launch": 1.026e12,
+            "fp64_matrix_flop_per_launch": 2.58e11,
+            "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 KERNEL_SOURCES = ("paper_1102_4666_amd/csrc/bsde_path.h",
                   "paper_1102_4666_amd/csrc/bsde_common.h",
@@ -161,13 +172,30 @@ def kernel_sources_sha16():
     return h.hexdigest()[:16]
 
 
+def _measured_for(rec, tiling):
+    return (rec is not None and tiling is not None and list(tiling) == list(rec["tiling"])
+            and rec["sources_sha16"] == kernel_sources_sha16())
+
+
 def traffic_bytes(tiling):
-    if TRAFFIC is None or list(tiling) != list(TRAFFIC["tiling"]):
-        return None
-    if TRAFFIC["sources_sha16"] != kernel_sources_sha16():
+    if not _measured_for(TRAFFIC, tiling):
         return None
     return (TRAFFIC["fetch_kib"] * FETCH_FACTOR +
             TRAFFIC["write_kib"] * WRITE_FACTOR) * 1024
+
+
+def counter_figures(tiling, path_ms):
+    """The profile's counter-derived figures when the kernel and tiling are
+    the profiled ones (the FLOP rates over this run's launch time)."""
+    if not _measured_for(COUNTERS, tiling):
+        return None
+    t = path_ms * 1e-3
+    return {"valu_issue": COUNTERS["valu_issue"], "mfma_busy": COUNTERS["mfma_busy"],
+            "fp64_vector_tflops_issued": COUNTERS["fp64_vector_flop_per_launch"] / t / 1e12,
+            "fp64_vector_frac_issued": COUNTERS["fp64_vector_flop_per_launch"] / t /
+            FP64_VECTOR_PEAK,
+            "fp64_matrix_tflops_issued": COUNTERS["fp64_matrix_flop_per_launch"] / t / 1e12,
+            "profile": COUNTERS["profile"]}
 
 
 # ---------------------------------------------------------------------------
@@ -272,7 +300,8 @@ def roofline(cfg, n, path_ms, tiling, precision):
             "launch_ms": path_ms, "path_steps_per_launch": launch_steps,
             "flop_per_path_step": fl,
             "of_which_contraction_flop_per_path_step": fl_mfma,
-            "target_frac": 0.5}
+            "target_frac": 0.5,
+            "counters": counter_figures(tiling, path_ms) if precision == "fp64" else None}
 
 
 def gate(precision, price, delta, ref_p, ref_d, K, omega):

@@ -70,6 +70,23 @@ def test_traffic_is_null_unless_measured_for_these_sources():
         b.TRAFFIC = saved
 
 
+
+def test_counter_figures_follow_the_recorded_profile():
+    b = _bench()
+    saved = b.COUNTERS
+    try:
+        b.COUNTERS = dict(saved, sources_sha16=b.kernel_sources_sha16(), tiling=[4, 1])
+        c = b.counter_figures([4, 1], 36.9)
+        assert 0 < c["valu_issue"] <= 1 and 0 < c["mfma_busy"] <= 1
+        assert c["fp64_vector_tflops_issued"] == pytest.approx(
+            saved["fp64_vector_flop_per_launch"] / 36.9e-3 / 1e12)
+        assert b.counter_figures([2, 2], 36.9) is None
+        b.COUNTERS = dict(b.COUNTERS, sources_sha16="0" * 16)
+        assert b.counter_figures([4, 1], 36.9) is None
+    finally:
+        b.COUNTERS = saved
+
+
 def test_gate_labels_the_diverging_penalty():
     b = _bench()
     ok = b.gate("fp64", 6.8, [0.1], 6.8 + 5e-4, [0.1 + 5e-5], 100.0, 1.0)
