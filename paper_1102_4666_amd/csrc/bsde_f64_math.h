@@ -27,9 +27,13 @@
 // by its Maclaurin series to degree 13 (remainder below 6e-18 of e^r), and
 // the power 2^n applied to the exponent.
 //
+// The radius takes the square root from the hardware reciprocal square
+// root and Newton steps (sqrt_nonneg).
+//
 // Plain double and 32-bit integer arithmetic (and the hardware reciprocal
-// seed on the device), so the same code also compiles for the host: the
-// test suite checks it there against high-precision references.
+// and reciprocal-square-root seeds on the device), so the same code also
+// compiles for the host: the test suite checks it there against
+// high-precision references.
 #pragma once
 
 #include <stdint.h>
@@ -98,13 +102,44 @@ constexpr double kLn2Lo = 5.4979230187083711552420206887e-14;
 BSDE_F64_HD inline uint64_t to_bits(double x) { return __builtin_bit_cast(uint64_t, x); }
 BSDE_F64_HD inline double from_bits(uint64_t b) { return __builtin_bit_cast(double, b); }
 
+// Hardware seeds: v_rcp_f64 and v_rsq_f64 on the device.  The host build
+// (tests only) takes seeds of single-precision accuracy, no better than the
+// hardware's, so that the refinement steps below are tested as the device
+// needs them.
 BSDE_F64_HD inline double reciprocal_seed(double d)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rcp(d); // v_rcp_f64
+    return __builtin_amdgcn_rcp(d);
 #else
-    return 1.0 / d;
+    return (double)(1.0f / (float)d);
 #endif
+}
+BSDE_F64_HD inline double rsqrt_seed(double a)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsq(a);
+#else
+    return (double)(1.0f / __builtin_sqrtf((float)a));
+#endif
+}
+
+// sqrt(a) for a >= 0 that is zero or a normal number (the Box-Muller radius
+// sqrt(-2 v ln u)): from the reciprocal square root seed y, two coupled
+// Newton steps on g ~ sqrt(a), h ~ 1/(2 sqrt(a)) (each squares the relative
+// error: 2^-23 -> 2^-46 -> 2^-92) and one residual correction
+// g + (a - g^2) h; zero for a = 0.
+BSDE_F64_HD inline double sqrt_nonneg(double a)
+{
+    const double y = rsqrt_seed(a);
+    double g = a * y, h = 0.5 * y;
+    double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    g = __builtin_fma(__builtin_fma(-g, g, a), h, g);
+    return a > 0.0 ? g : 0.0;
 }
 
 // ln((w + 1/2) 2^-32) for a 32-bit word w

@@ -86,7 +86,7 @@ struct Arith<double> {
                                                       double &n1, double = 0.0,
                                                       double = 0.0)
     {
-        double R = ::sqrt(scale * f64::log_word(wa));
+        double R = f64::sqrt_nonneg(scale * f64::log_word(wa));
         double s, c;
         f64::sincos_turn(wb, s, c);
         n0 = R * c;
@@ -386,7 +386,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
     constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
     constexpr int NB = SG * D / 4;
     constexpr int NBB = (D + 3) / 4; // bridge blocks
-    constexpr bool kXor3 = sizeof(Real) == 4 && D < 10; // Philox XOR form
+    constexpr bool kXor3 = (sizeof(Real) == 4 && D < 10) || (sizeof(Real) == 8 && D == 5); // Philox XOR form
     // FP32 round keys in vector registers (16 of them): at d = 1, and at
     // d = 2 from eta = 5 on, where the kernel's own registers already hold
     // it to four waves per SIMD and the keys still fit (below, they would

@@ -1,8 +1,10 @@
 """The FP64 elementary functions of the FP64 path kernels
 (paper_1102_4666_amd/csrc/bsde_f64_math.h), compiled for the host with g++
 and checked against 120-bit references (mpmath): the logarithm and the
-quarter-turn sine/cosine of the Box-Muller words, and the exponential of
-non-positive arguments of the local volatility.  No GPU needed."""
+quarter-turn sine/cosine of the Box-Muller words, the square root of the
+Box-Muller radius, and the exponential of non-positive arguments of the
+local volatility.  The host build refines seeds of single-precision
+accuracy, no better than the device's hardware seeds.  No GPU needed."""
 import os
 import subprocess
 import tempfile
@@ -24,6 +26,9 @@ int main() {
         if (kind[0] == 'l') {
             unsigned w; if (std::scanf("%u", &w) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::log_word(w));
+        } else if (kind[0] == 'q') {
+            double x; if (std::scanf("%lf", &x) != 1) return 1;
+            std::printf("%.17g\n", bsde::f64::sqrt_nonneg(x));
         } else if (kind[0] == 'e') {
             double x; if (std::scanf("%lf", &x) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::exp_nonpos(x));
@@ -106,3 +111,17 @@ def test_exp_of_non_positive_arguments(driver):
     tail = _run(driver, ["e -709", "e -1e10"])
     for v in tail:
         assert float(v) == pytest.approx(float(mpmath.exp(-708)), rel=1e-15)
+
+
+def test_square_root_of_the_radius(driver):
+    mpmath.mp.prec = 120
+    rng = np.random.default_rng(5)
+    # -2 v ln u for the step and bridge scales and every u: from 1e-12 to ~50,
+    # plus other magnitudes (within single-precision range, where the host's
+    # emulated seed lives) and exact squares
+    xs = list(10.0 ** rng.uniform(-12, 2, 3000)) + list(rng.uniform(0, 50, 1000))
+    xs += [1e-30, 0.25, 1.0, 2.0, 4.0, 49.0, 1e30]
+    out = _run(driver, ["q %.17g" % x for x in xs])
+    worst = max(_ulps(float(v), mpmath.sqrt(mpmath.mpf(x))) for x, v in zip(xs, out))
+    assert worst <= 1.0, worst
+    assert float(_run(driver, ["q 0"])[0]) == 0.0
