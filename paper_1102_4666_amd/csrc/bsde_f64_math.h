@@ -36,6 +36,7 @@
 // high-precision references.
 #pragma once
 
+#include <math.h>
 #include <stdint.h>
 
 #if defined(__HIPCC__)
@@ -68,6 +69,32 @@ constexpr double kC[8] = {-1.0 / 2.0,
 // 2 pi 2^-32 (the ulp of u in radians)
 constexpr double kTwoPiUlp = 6.283185307179586476925286766559 / 4294967296.0;
 
+// sin x and cos x for |x| <= pi/4 (Maclaurin series to degrees 17 and 16)
+BSDE_F64_HD inline void sincos_reduced(double x, double &s, double &c)
+{
+    const double x2 = x * x;
+    double ps = kS[7], pc = kC[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) {
+        ps = __builtin_fma(ps, x2, kS[k]);
+        pc = __builtin_fma(pc, x2, kC[k]);
+    }
+    s = __builtin_fma(x * x2, ps, x);
+    c = __builtin_fma(x2, pc, 1.0);
+}
+
+// sin and cos of q pi/2 + x from sx = sin x, cx = cos x:
+// sin(q pi/2 + x) = sin x, cos x, -sin x, -cos x;
+// cos(q pi/2 + x) = cos x, -sin x, -cos x, sin x
+BSDE_F64_HD inline void rotate_quarters(uint32_t q, double sx, double cx, double &s, double &c)
+{
+    const bool odd = (q & 1u) != 0;
+    const double a = odd ? cx : sx;
+    const double b = odd ? sx : cx;
+    s = (q & 2u) ? -a : a;
+    c = ((q + 1u) & 2u) ? -b : b;
+}
+
 // sin and cos of the angle 2 pi (w + 1/2) 2^-32 (w a 32-bit word)
 BSDE_F64_HD inline void sincos_turn(uint32_t w, double &s, double &c)
 {
@@ -76,22 +103,9 @@ BSDE_F64_HD inline void sincos_turn(uint32_t w, double &s, double &c)
     const uint32_t q = (w + 0x20000000u) >> 30;
     const int32_t rho = (int32_t)(w - (q << 30));
     const double x = __builtin_fma((double)rho, kTwoPiUlp, 0.5 * kTwoPiUlp);
-    const double x2 = x * x;
-    double ps = kS[7], pc = kC[7];
-#pragma unroll
-    for (int k = 6; k >= 0; --k) {
-        ps = __builtin_fma(ps, x2, kS[k]);
-        pc = __builtin_fma(pc, x2, kC[k]);
-    }
-    const double sx = __builtin_fma(x * x2, ps, x);
-    const double cx = __builtin_fma(x2, pc, 1.0);
-    // sin(q pi/2 + x) = sin x, cos x, -sin x, -cos x;
-    // cos(q pi/2 + x) = cos x, -sin x, -cos x, sin x
-    const bool odd = (q & 1u) != 0;
-    const double a = odd ? cx : sx;
-    const double b = odd ? sx : cx;
-    s = (q & 2u) ? -a : a;
-    c = ((q + 1u) & 2u) ? -b : b;
+    double sx, cx;
+    sincos_reduced(x, sx, cx);
+    rotate_quarters(q, sx, cx, s, c);
 }
 
 // ln 2 in two parts: kLn2Hi has 42 significant bits, so e kLn2Hi is exact
@@ -202,6 +216,85 @@ BSDE_F64_HD inline double exp_nonpos(double x)
     p = __builtin_fma(p, r, 1.0);
     // times 2^n, n in [-1022, 0]: exponent field of a normal number
     return p * from_bits((uint64_t)(1023 + (int)n) << 52);
+}
+
+// ---------------------------------------------------------------------------
+// Table-driven forms for the FP64 path kernels, with the tables in LDS
+// (filled by each workgroup at the start of a tile):
+//  - sine and cosine of the Box-Muller angle: the turn in 256 sectors
+//    centred at j/256 turns (the axes are centres, so results near zero
+//    keep their relative accuracy); the word's remainder rho = w - j 2^24
+//    is exact, r = 2 pi (rho + 1/2) 2^-32 lies in [-pi/256, pi/256], where
+//    sin r and cos r to degrees 7 and 6 leave remainders below 2e-23 and
+//    2e-20; then the angle-addition formulas with the table's sine and
+//    cosine of 2 pi j / 256;
+//  - e^x for x <= 0: x = (64 n + j) ln 2 / 64 + r, |r| <= ln 2 / 128, e^r
+//    to degree 5 (remainder below 4e-17 of e^r), times the table entry
+//    2^(j/64) and 2^n.
+// ---------------------------------------------------------------------------
+constexpr int kSinCosBins = 256;
+constexpr int kExpBins = 64;
+struct Tables {
+    double sc[kSinCosBins][2]; // sin, cos of 2 pi j / 256
+    double ex[kExpBins];       // 2^(j/64)
+};
+// ln 2 / 64 in two parts: the first has 36 significant bits, so n kLn2_64Hi
+// is exact for |n| < 2^17
+constexpr double kLn2_64Hi = 0.010830424696223417;
+constexpr double kLn2_64Lo = 2.572804622327669e-14;
+
+// entries first, first + stride, ... of both tables
+BSDE_F64_HD inline void fill_tables(Tables &T, int first, int stride)
+{
+    for (int t = first; t < kSinCosBins + kExpBins; t += stride) {
+        if (t < kSinCosBins) {
+            // j/256 turns = q/4 + f/256, f in [-32, 32)
+            const uint32_t q = ((uint32_t)(t + 32) >> 6) & 3u;
+            const int f = t - (int)(((uint32_t)(t + 32) >> 6) << 6);
+            double sx, cx;
+            sincos_reduced((double)f * (6.283185307179586476925286766559 / 256.0), sx, cx);
+            rotate_quarters(q, sx, cx, T.sc[t][0], T.sc[t][1]);
+        } else {
+            T.ex[t - kSinCosBins] = exp2((double)(t - kSinCosBins) / (double)kExpBins);
+        }
+    }
+}
+
+BSDE_F64_HD inline void sincos_turn_tab(uint32_t w, const Tables &T, double &s, double &c)
+{
+    // nearest sector centre j 2^24 (mod 2^32) and the signed remainder
+    const uint32_t j = (w + 0x00800000u) >> 24;
+    const int32_t rho = (int32_t)(w - (j << 24));
+    const double r = __builtin_fma((double)rho, kTwoPiUlp, 0.5 * kTwoPiUlp);
+    const double r2 = r * r;
+    // sin r = r + r^3 (-1/6 + r^2 (1/120 - r^2/5040)), cos r = 1 + r^2 (-1/2 +
+    // r^2 (1/24 - r^2/720))
+    double ps = __builtin_fma(r2, kS[2], kS[1]);
+    ps = __builtin_fma(ps, r2, kS[0]);
+    double pc = __builtin_fma(r2, kC[2], kC[1]);
+    pc = __builtin_fma(pc, r2, kC[0]);
+    const double sr = __builtin_fma(r * r2, ps, r);
+    const double cr = __builtin_fma(r2, pc, 1.0);
+    const double sa = T.sc[j & (kSinCosBins - 1)][0], ca = T.sc[j & (kSinCosBins - 1)][1];
+    s = __builtin_fma(sa, cr, ca * sr);
+    c = __builtin_fma(ca, cr, -(sa * sr));
+}
+
+BSDE_F64_HD inline double exp_nonpos_tab(double x, const Tables &T)
+{
+    x = x < -708.0 ? -708.0 : x;
+    const double N = __builtin_rint(x * 92.332482616893656811); // 64 / ln 2
+    double r = __builtin_fma(-N, kLn2_64Hi, x);
+    r = __builtin_fma(-N, kLn2_64Lo, r);
+    // e^r - 1 = r + r^2 (1/2 + r (1/6 + r (1/24 + r / 120)))
+    double q = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = __builtin_fma(q, r, 1.0 / 6.0);
+    q = __builtin_fma(q, r, 0.5);
+    const double em1 = __builtin_fma(q * r, r, r);
+    const int Ni = (int)N;
+    const double t = T.ex[Ni & (kExpBins - 1)];
+    // times 2^n, n = floor(N / 64) in [-704, 0]: exponent field of a normal
+    return __builtin_fma(t, em1, t) * from_bits((uint64_t)(1023 + (Ni >> 6)) << 52);
 }
 
 } // namespace f64

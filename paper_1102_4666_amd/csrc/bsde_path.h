@@ -20,6 +20,11 @@
 
 namespace bsde {
 
+// The FP64 kernels' tables of sines, cosines and powers of two
+// (bsde_f64_math.h), one copy per workgroup, filled at the start of each
+// tile (run_tile).
+static __shared__ f64::Tables f64_tables;
+
 // ---------------------------------------------------------------------------
 // Precision-specific arithmetic.  FP32: hardware transcendentals (v_log_f32
 // is log2, v_sin/v_cos take revolutions); FP64: the device math library.
@@ -88,7 +93,7 @@ struct Arith<double> {
     {
         double R = f64::sqrt_nonneg(scale * f64::log_word(wa));
         double s, c;
-        f64::sincos_turn(wb, s, c);
+        f64::sincos_turn_tab(wb, f64_tables, s, c);
         n0 = R * c;
         n1 = R * s;
     }
@@ -96,7 +101,7 @@ struct Arith<double> {
     // e^x for x <= 0 (the volatilities' Gaussian factors)
     static __device__ __forceinline__ double exp_nonpos(double x)
     {
-        return f64::exp_nonpos(x);
+        return f64::exp_nonpos_tab(x, f64_tables);
     }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double frac33(uint64_t num)
@@ -171,7 +176,7 @@ struct EulerState {
             if constexpr (sizeof(Real) == 4)
                 return fmaf(level_a, __builtin_amdgcn_exp2f(-y * y), level);
             else
-                return fma(level_a, f64::exp_nonpos(-y * y), level);
+                return fma(level_a, f64::exp_nonpos_tab(-y * y, f64_tables), level);
         } else {
             return local_vol<VOL>(level, level_a, Real(0), spot, vt, y);
         }
@@ -460,6 +465,11 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
         Real y, g;
     };
     __shared__ Rec rec[D][kBlock];
+
+    if constexpr (sizeof(Real) == 8) {
+        f64::fill_tables(f64_tables, (int)threadIdx.x, kBlock);
+        __syncthreads();
+    }
 
     double sum = 0.0, sumsq = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {

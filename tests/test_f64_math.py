@@ -3,8 +3,10 @@
 and checked against 120-bit references (mpmath): the logarithm and the
 quarter-turn sine/cosine of the Box-Muller words, the square root of the
 Box-Muller radius, and the exponential of non-positive arguments of the
-local volatility.  The host build refines seeds of single-precision
-accuracy, no better than the device's hardware seeds.  No GPU needed."""
+local volatility -- the series forms and the forms from the kernels'
+tables (256 sectors of the turn, 64 powers 2^(j/64)).  The host build
+refines seeds of single-precision accuracy, no better than the device's
+hardware seeds.  No GPU needed."""
 import os
 import subprocess
 import tempfile
@@ -21,6 +23,8 @@ DRIVER = r"""
 #include "bsde_f64_math.h"
 #include <cstdio>
 int main() {
+    static bsde::f64::Tables T;
+    bsde::f64::fill_tables(T, 0, 1);
     char kind[8];
     while (std::scanf("%7s", kind) == 1) {
         if (kind[0] == 'l') {
@@ -29,6 +33,13 @@ int main() {
         } else if (kind[0] == 'q') {
             double x; if (std::scanf("%lf", &x) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::sqrt_nonneg(x));
+        } else if (kind[0] == 'E') {
+            double x; if (std::scanf("%lf", &x) != 1) return 1;
+            std::printf("%.17g\n", bsde::f64::exp_nonpos_tab(x, T));
+        } else if (kind[0] == 'S') {
+            unsigned w; if (std::scanf("%u", &w) != 1) return 1;
+            double s, c; bsde::f64::sincos_turn_tab(w, T, s, c);
+            std::printf("%.17g %.17g\n", s, c);
         } else if (kind[0] == 'e') {
             double x; if (std::scanf("%lf", &x) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::exp_nonpos(x));
@@ -98,17 +109,33 @@ def test_quarter_turn_sine_and_cosine(driver):
     assert worst <= 2.0, worst
 
 
-def test_exp_of_non_positive_arguments(driver):
+@pytest.mark.parametrize("form", ["s", "S"])
+def test_sector_sine_and_cosine(driver, form):
+    # "s": quarter turns and series; "S": 256 sectors from the LDS table
+    mpmath.mp.prec = 120
+    ws = _words() + [(j * 2 ** 24 + o) % 2 ** 32 for j in range(257)
+                     for o in (-2 ** 23 - 1, -2 ** 23, -1, 0, 1, 2 ** 23 - 1)]
+    out = _run(driver, ["%s %d" % (form, w) for w in ws])
+    worst = 0.0
+    for w, ln in zip(ws, out):
+        s, c = map(float, ln.split())
+        a = 2 * mpmath.pi * (mpmath.mpf(w) + mpmath.mpf(0.5)) / 2 ** 32
+        worst = max(worst, _ulps(s, mpmath.sin(a)), _ulps(c, mpmath.cos(a)))
+    assert worst <= 2.0, worst
+
+
+@pytest.mark.parametrize("form", ["e", "E"])
+def test_exp_of_non_positive_arguments(driver, form):
     mpmath.mp.prec = 120
     rng = np.random.default_rng(4)
     xs = list(-rng.uniform(0, 1, 2000) ** 2 * 40) + list(-rng.uniform(0, 708, 1000))
     xs += [0.0, -0.0, -1e-300, -1e-20, -0.3465735902799726, -0.34657359027997264,
            -707.9, -708.0]
-    out = _run(driver, ["e %.17g" % x for x in xs])
+    out = _run(driver, ["%s %.17g" % (form, x) for x in xs])
     worst = max(_ulps(float(v), mpmath.exp(mpmath.mpf(x))) for x, v in zip(xs, out))
     assert worst <= 1.5, worst
     # below the clamp the value is e^-708, far under the volatility's rounding
-    tail = _run(driver, ["e -709", "e -1e10"])
+    tail = _run(driver, ["%s -709" % form, "%s -1e10" % form])
     for v in tail:
         assert float(v) == pytest.approx(float(mpmath.exp(-708)), rel=1e-15)
 
