@@ -146,16 +146,16 @@ ISSUE_CYCLES_D1_FP32 = {
 # profiles/copy_calibration.md).  Valid only for the kernel sources whose
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
-TRAFFIC = {"sources_sha16": "bcc971886b277878", "tiling": [4, 1],
-           "fetch_kib": 18890.0, "write_kib": 11260.0,
+TRAFFIC = {"sources_sha16": "0801638cf8ff6a34", "tiling": [4, 1],
+           "fetch_kib": 15780.0, "write_kib": 5120.0,
            "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 # Counter-derived figures of the same kernel (same profile, same guard):
 # VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
-COUNTERS = {"sources_sha16": "bcc971886b277878", "tiling": [4, 1],
-            "valu_issue": 0.786, "mfma_busy": 0.092,
-            "fp64_vector_flop_per_launch": 1.026e12,
+COUNTERS = {"sources_sha16": "0801638cf8ff6a34", "tiling": [4, 1],
+            "valu_issue": 0.719, "mfma_busy": 0.117,
+            "fp64_vector_flop_per_launch": 7.80e11,
             "fp64_matrix_flop_per_launch": 2.58e11,
             "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0

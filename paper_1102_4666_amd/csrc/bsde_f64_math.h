@@ -19,7 +19,7 @@
 // (e - 32) ln 2 + ln m and ln m = 2 atanh(s), s = (m - 1) / (m + 1),
 // |s| <= 0.1716, whose odd series 2 s (1 + s^2/3 + s^4/5 + ...) to s^19
 // leaves a remainder below 2.3e-17 of 2 s.  The quotient s takes one
-// hardware reciprocal, two Newton steps and one residual correction.
+// hardware reciprocal and two residual corrections.
 //
 // The local volatility needs e^x for x = -y^2 <= 0: x clamped at -708
 // (e^-708 is already below the volatility's rounding), x = n ln 2 + r with
@@ -125,7 +125,7 @@ BSDE_F64_HD inline double reciprocal_seed(double d)
 #if defined(__HIP_DEVICE_COMPILE__)
     return __builtin_amdgcn_rcp(d);
 #else
-    return (double)(1.0f / (float)d);
+    return (1.0 / d) * (1.0 - 0x1p-24); // single-precision accuracy
 #endif
 }
 BSDE_F64_HD inline double rsqrt_seed(double a)
@@ -133,18 +133,21 @@ BSDE_F64_HD inline double rsqrt_seed(double a)
 #if defined(__HIP_DEVICE_COMPILE__)
     return __builtin_amdgcn_rsq(a);
 #else
-    return (double)(1.0f / __builtin_sqrtf((float)a));
+    // single-precision accuracy, also below the single-precision range
+    const double y = 1.0 / __builtin_sqrt(a);
+    return y * (1.0 + 0x1p-24);
 #endif
 }
 
-// sqrt(a) for a >= 0 that is zero or a normal number (the Box-Muller radius
-// sqrt(-2 v ln u)): from the reciprocal square root seed y, two coupled
-// Newton steps on g ~ sqrt(a), h ~ 1/(2 sqrt(a)) (each squares the relative
-// error: 2^-23 -> 2^-46 -> 2^-92) and one residual correction
-// g + (a - g^2) h; zero for a = 0.
+// sqrt(a) for a = 0 or a normal number above 2^-900 (the Box-Muller radius
+// sqrt(-2 v ln u), whose argument is zero or above 1e-25): from the
+// reciprocal square root seed y of a + 2^-1000 (which is a itself unless a
+// is zero, where y stays finite and g comes out 0), two coupled Newton steps
+// on g ~ sqrt(a), h ~ 1/(2 sqrt(a)) (each squares the relative error:
+// 2^-23 -> 2^-46 -> 2^-92) and one residual correction g + (a - g^2) h.
 BSDE_F64_HD inline double sqrt_nonneg(double a)
 {
-    const double y = rsqrt_seed(a);
+    const double y = rsqrt_seed(a + 0x1p-1000);
     double g = a * y, h = 0.5 * y;
     double r = __builtin_fma(-g, h, 0.5);
     g = __builtin_fma(g, r, g);
@@ -152,8 +155,7 @@ BSDE_F64_HD inline double sqrt_nonneg(double a)
     r = __builtin_fma(-g, h, 0.5);
     g = __builtin_fma(g, r, g);
     h = __builtin_fma(h, r, h);
-    g = __builtin_fma(__builtin_fma(-g, g, a), h, g);
-    return a > 0.0 ? g : 0.0;
+    return __builtin_fma(__builtin_fma(-g, g, a), h, g);
 }
 
 // ln((w + 1/2) 2^-32) for a 32-bit word w
@@ -171,10 +173,11 @@ BSDE_F64_HD inline double log_word(uint32_t w)
                                (b & 0xFFFFFFFFull));
     const double f = m - 1.0; // exact
     const double d = m + 1.0;
-    double y = reciprocal_seed(d);
-    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
-    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+    // s = f / d from the reciprocal seed y and two residual corrections
+    // s += (f - s d) y (each squares the relative error)
+    const double y = reciprocal_seed(d);
     double sq = f * y;
+    sq = __builtin_fma(__builtin_fma(-sq, d, f), y, sq);
     sq = __builtin_fma(__builtin_fma(-sq, d, f), y, sq);
     const double z = sq * sq;
     // 2/3 + 2z/5 + ... + 2z^8/19
@@ -196,7 +199,7 @@ BSDE_F64_HD inline double log_word(uint32_t w)
 // e^x for x <= 0 (the local volatility's e^{-y^2})
 BSDE_F64_HD inline double exp_nonpos(double x)
 {
-    x = x < -708.0 ? -708.0 : x;
+    x = __builtin_fmax(x, -708.0);
     const double n = __builtin_rint(x * 1.4426950408889634073599246810019);
     double r = __builtin_fma(-n, kLn2Hi, x);
     r = __builtin_fma(-n, kLn2Lo, r);
@@ -282,7 +285,7 @@ BSDE_F64_HD inline void sincos_turn_tab(uint32_t w, const Tables &T, double &s, 
 
 BSDE_F64_HD inline double exp_nonpos_tab(double x, const Tables &T)
 {
-    x = x < -708.0 ? -708.0 : x;
+    x = __builtin_fmax(x, -708.0);
     const double N = __builtin_rint(x * 92.332482616893656811); // 64 / ln 2
     double r = __builtin_fma(-N, kLn2_64Hi, x);
     r = __builtin_fma(-N, kLn2_64Lo, r);
@@ -293,8 +296,8 @@ BSDE_F64_HD inline double exp_nonpos_tab(double x, const Tables &T)
     const double em1 = __builtin_fma(q * r, r, r);
     const int Ni = (int)N;
     const double t = T.ex[Ni & (kExpBins - 1)];
-    // times 2^n, n = floor(N / 64) in [-704, 0]: exponent field of a normal
-    return __builtin_fma(t, em1, t) * from_bits((uint64_t)(1023 + (Ni >> 6)) << 52);
+    // times 2^n, n = floor(N / 64) in [-704, 0] (the result stays normal)
+    return __builtin_ldexp(__builtin_fma(t, em1, t), Ni >> 6);
 }
 
 } // namespace f64

@@ -20,8 +20,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RES = os.path.join(ROOT, "paper_1102_4666_amd", "_build", "resources.txt")
 # kernel-name pattern -> largest spill allowed (bytes per lane)
 ALLOWED = {"path_kernelILi10E": 280, "path_kernelILi10ELi5EfLi0ELi7E": 352, "path_kernelILi5ELi2EdLi0E": 128,
-           "path_kernelILi5ELi3EdLi0E": 128, "path_kernelILi5ELi3EdLi1E": 72,
-           "path_kernelILi5ELi3EdLi2E": 48, "path_kernelILi2ELi5Ed": 32}
+           "path_kernelILi5ELi3EdLi0E": 128, "path_kernelILi5ELi3EdLi1E": 128,
+           "path_kernelILi5ELi3EdLi2E": 128, "path_kernelILi2ELi5Ed": 32}
 
 
 def test_path_kernels_do_not_spill():

@@ -143,11 +143,10 @@ def test_exp_of_non_positive_arguments(driver, form):
 def test_square_root_of_the_radius(driver):
     mpmath.mp.prec = 120
     rng = np.random.default_rng(5)
-    # -2 v ln u for the step and bridge scales and every u: from 1e-12 to ~50,
-    # plus other magnitudes (within single-precision range, where the host's
-    # emulated seed lives) and exact squares
+    # -2 v ln u for the step and bridge scales and every u: from 1e-25 to ~50,
+    # plus other magnitudes and exact squares
     xs = list(10.0 ** rng.uniform(-12, 2, 3000)) + list(rng.uniform(0, 50, 1000))
-    xs += [1e-30, 0.25, 1.0, 2.0, 4.0, 49.0, 1e30]
+    xs += [2.0 ** -899, 1e-100, 1e-25, 1e-30, 0.25, 1.0, 2.0, 4.0, 49.0, 1e30]
     out = _run(driver, ["q %.17g" % x for x in xs])
     worst = max(_ulps(float(v), mpmath.sqrt(mpmath.mpf(x))) for x, v in zip(xs, out))
     assert worst <= 1.0, worst
