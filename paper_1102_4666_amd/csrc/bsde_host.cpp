@@ -1331,7 +1331,8 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
 bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                             int steps, bool graph, bool copy_back, double *ms,
                             const int *steps_each, void *workspace,
-                            size_t workspace_bytes)
+                            size_t workspace_bytes, bool parallel_branches,
+                            int cu_reserve)
 {
     std::vector<int> G(count), PPL(count), R(count);
     int S = 0;
@@ -1439,8 +1440,8 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     // branches: the first on s, the others on the library's side streams of
     // this device (forked from s and joined back before the step's update),
     // so that the tiles of one signature fill the tail of another's launch.
-    // The no-allocation form keeps everything on s.
-    const bool parallel = workspace == nullptr;
+    // The no-allocation form (and a caller that asks) keeps everything on s.
+    const bool parallel = workspace == nullptr && parallel_branches;
     SideStreams *side = nullptr;
     std::unique_lock<std::mutex> side_lock; // held until the batch is done
     if (parallel) {
@@ -1471,7 +1472,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                 hipStream_t ls = (j == 0 || nside == 0) ? s : side->s[(j - 1) % nside];
                 const int occ = std::max(1, batch_occupancy(pl.sig.d, pl.sig.eta, pl.sig.q10,
                                                             pl.sig.fp32, pl.sig.vol));
-                const long long cap = (long long)occ * num_cus();
+                const long long cap = (long long)occ * std::max(1, num_cus() - cu_reserve);
                 const int blocks = (int)std::max(1LL, std::min(pl.tiles, cap));
                 e = launch_batch(pl.sig.d, pl.sig.eta, pl.sig.q10, pl.sig.fp32, pl.sig.vol, blocks, ls,
                                  (const BatchTileDesc *)(dblob + pl.desc_off), pl.nprob,

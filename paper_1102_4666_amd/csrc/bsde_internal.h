@@ -58,11 +58,15 @@ bsde_status fail(bsde_status s, const std::string &msg);
 // copies coefficient histories back when copy_back is set; the descriptor
 // tables and tile counters go to workspace (device memory of
 // workspace_bytes) when given, else to memory from the library's pool;
-// ms (may be null) receives the GPU time
+// ms (may be null) receives the GPU time; with parallel, launches of
+// different kernel signatures in a step run on the library's side streams
+// (parallel branches), else all on s; the persistent grids leave
+// cu_reserve compute units' worth of workgroup slots free for other work
 bsde_status run_batch(bsde_problem *probs, int count, hipStream_t s, int steps,
                       bool graph, bool copy_back, double *ms,
                       const int *steps_each = nullptr, void *workspace = nullptr,
-                      size_t workspace_bytes = 0);
+                      size_t workspace_bytes = 0, bool parallel = true,
+                      int cu_reserve = 0);
 // copies the latest coefficients of a finished problem back to the host
 bsde_status fetch_coefficients(bsde_problem h);
 // device bytes a problem with these parameters allocates (pool size classes)

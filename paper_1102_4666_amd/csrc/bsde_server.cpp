@@ -3,11 +3,14 @@
 // Requests (a pricing problem plus a query point) are admitted while their
 // device footprint fits the server's HBM budget and the number in flight is
 // below the limit.  Set-up threads build admitted problems (host set-up and
-// upload) while the GPU works on others.  One engine thread advances every
-// in-flight problem by one Picard iteration per step with the batched
-// persistent kernels; problems that arrive while others are on the GPU join
-// at the next step, finished ones leave, release their memory and complete
-// their tickets.  Each problem keeps its coefficients and channel tables
+// upload) while the GPU works on others.  Two engine lanes, each a thread
+// with a stream of its own, advance the in-flight problems with the batched
+// persistent kernels: the light lane the problems whose Picard iteration is
+// cheap (a few milliseconds of GPU time), the heavy lane the others, so
+// that a cheap request never waits for a step of the heaviest problems;
+// their launches share the GPU.  In each lane, problems that arrive while
+// others are on the GPU join at the next step, finished ones leave,
+// release their memory and complete their tickets.  Each problem keeps its coefficients and channel tables
 // resident on the device across iterations.  A problem's result does not
 // depend on what else is in flight: its tiles and reductions are those of a
 // solve alone.
@@ -52,20 +55,29 @@ struct Request {
 };
 } // namespace
 
+// One engine lane: its thread and stream, the problems built for it and
+// not yet joined, and those it advances.
+struct EngineLane {
+    hipStream_t stream = nullptr;
+    std::condition_variable cv;
+    std::deque<Request *> ready;
+    std::vector<Request *> active;
+    std::thread thread;
+};
+constexpr int kLight = 0, kHeavy = 1, kLanes = 2;
+
 struct bsde_server_s {
     size_t budget = 0, reserved = 0;
     int max_inflight = 0, inflight = 0; // inflight: in set-up, ready or active
     int device = 0;
-    hipStream_t stream = nullptr;
     std::mutex mu;
-    std::condition_variable cv_admit, cv_engine, cv_done;
-    std::deque<Request *> pending, ready;
-    std::vector<Request *> active;
+    std::condition_variable cv_admit, cv_done;
+    std::deque<Request *> pending;
+    EngineLane lanes[kLanes];
     std::map<unsigned long long, Request *> tickets;
     unsigned long long next_ticket = 1;
     bool stop = false;
     std::vector<std::thread> setup_threads;
-    std::thread engine;
     // statistics
     std::vector<double> latencies;
     double steps_done = 0;
@@ -88,6 +100,23 @@ static void complete(bsde_server_s *S, Request *q, int status)
         S->t_last = q->t_done;
     }
 }
+
+// Relative GPU cost of one Picard iteration of a problem: its path-steps
+// over the path-kernel rate of its dimension (path-steps/s measured on
+// MI355X with FP32 paths; FP64 paths are about 6x slower).  Used only to
+// group iterations into engine steps.
+static double iteration_cost(const bsde_problem_s *h)
+{
+    double rate = h->d <= 1 ? 9e11 : h->d <= 2 ? 4e11 : h->d <= 3 ? 3e11
+                : h->d <= 5 ? 1.8e11 : 5e10;
+    if (h->precision != BSDE_FP32_PATHS) rate /= 6.0;
+    return (double)h->n * h->M * h->N / rate + 2e-5; // + launch overheads
+}
+
+// problems whose iteration costs less than this go to the light lane
+static constexpr double kLightIteration = 5e-3; // seconds
+// compute units whose workgroup slots the heavy lane's grids leave free
+static constexpr int kLightCUs = 16;
 
 static void setup_loop(bsde_server_s *S)
 {
@@ -125,8 +154,9 @@ static void setup_loop(bsde_server_s *S)
             continue;
         }
         q->h = h;
-        S->ready.push_back(q);
-        S->cv_engine.notify_one();
+        EngineLane &L = S->lanes[iteration_cost(h) < kLightIteration ? kLight : kHeavy];
+        L.ready.push_back(q);
+        L.cv.notify_one();
     }
 }
 
@@ -150,34 +180,23 @@ static void finish(bsde_server_s *S, Request *q)
     S->cv_admit.notify_all();
 }
 
-// Relative GPU cost of one Picard iteration of a problem: its path-steps
-// over the path-kernel rate of its dimension (path-steps/s measured on
-// MI355X with FP32 paths; FP64 paths are about 6x slower).  Used only to
-// group iterations into engine steps.
-static double iteration_cost(const bsde_problem_s *h)
-{
-    double rate = h->d <= 1 ? 9e11 : h->d <= 2 ? 4e11 : h->d <= 3 ? 3e11
-                : h->d <= 5 ? 1.8e11 : 5e10;
-    if (h->precision != BSDE_FP32_PATHS) rate /= 6.0;
-    return (double)h->n * h->M * h->N / rate + 2e-5; // + launch overheads
-}
-
 // most iterations of one problem chained into one engine step
 static constexpr int kMaxChain = 16;
 
-static void engine_loop(bsde_server_s *S)
+static void engine_loop(bsde_server_s *S, int lane)
 {
     (void)hipSetDevice(S->device);
+    EngineLane &L = S->lanes[lane];
     for (;;) {
         {
             std::unique_lock<std::mutex> g(S->mu);
-            S->cv_engine.wait(g, [&] {
-                return S->stop || !S->ready.empty() || !S->active.empty();
+            L.cv.wait(g, [&] {
+                return S->stop || !L.ready.empty() || !L.active.empty();
             });
-            if (S->stop && S->ready.empty() && S->active.empty()) return;
-            while (!S->ready.empty()) { // continuous batching: join now
-                S->active.push_back(S->ready.front());
-                S->ready.pop_front();
+            if (S->stop && L.ready.empty() && L.active.empty()) return;
+            while (!L.ready.empty()) { // continuous batching: join now
+                L.active.push_back(L.ready.front());
+                L.ready.pop_front();
             }
         }
         // One engine step lasts about one iteration of its most expensive
@@ -188,7 +207,7 @@ static void engine_loop(bsde_server_s *S)
         std::vector<bsde_problem> hs;
         std::vector<double> cost;
         double quantum = 0.0;
-        for (Request *q : S->active) {
+        for (Request *q : L.active) {
             hs.push_back(q->h);
             cost.push_back(iteration_cost(q->h));
             quantum = std::max(quantum, cost.back());
@@ -197,8 +216,15 @@ static void engine_loop(bsde_server_s *S)
         for (size_t j = 0; j < hs.size(); ++j)
             steps[j] = (int)std::max(1.0, std::min((double)kMaxChain,
                                                    std::floor(quantum / cost[j])));
-        bsde_status st = run_batch(hs.data(), (int)hs.size(), S->stream, 1, false, false,
-                                   nullptr, steps.data());
+        // the heavy lane's signatures run as parallel branches on the
+        // library's side streams, and its persistent grids leave the slots
+        // of kLightCUs compute units free, so that the light lane's
+        // workgroups find room beside them instead of waiting for the
+        // heavy kernels to drain; the light lane's small launches stay on
+        // its own stream
+        bsde_status st = run_batch(hs.data(), (int)hs.size(), L.stream, 1, false, false,
+                                   nullptr, steps.data(), nullptr, 0, lane == kHeavy,
+                                   lane == kHeavy ? kLightCUs : 0);
         {
             // engine_steps is read by bsde_server_stats under the mutex
             std::lock_guard<std::mutex> g(S->mu);
@@ -206,9 +232,9 @@ static void engine_loop(bsde_server_s *S)
         }
         // a request's result is read only after complete() marks it done
         // under the mutex, after these writes
-        for (Request *q : S->active) q->result.engine_steps += 1;
+        for (Request *q : L.active) q->result.engine_steps += 1;
         std::vector<Request *> still;
-        for (Request *q : S->active) {
+        for (Request *q : L.active) {
             if (st != BSDE_OK) {
                 bsde_destroy(q->h);
                 q->h = nullptr;
@@ -224,7 +250,7 @@ static void engine_loop(bsde_server_s *S)
                 still.push_back(q);
             }
         }
-        S->active.swap(still);
+        L.active.swap(still);
     }
 }
 
@@ -242,14 +268,17 @@ bsde_status bsde_server_create(size_t hbm_budget_bytes, int max_inflight,
     S->budget = hbm_budget_bytes;
     S->max_inflight = max_inflight;
     hipError_t e = hipGetDevice(&S->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l)
+        e = hipStreamCreateWithFlags(&S->lanes[l].stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        for (int l = 0; l < kLanes; ++l)
+            if (S->lanes[l].stream) (void)hipStreamDestroy(S->lanes[l].stream);
         delete S;
         return fail(BSDE_EDEVICE, std::string("server stream: ") + hipGetErrorString(e));
     }
     const int nthreads = setup_threads > 0 ? setup_threads : 4;
     for (int t = 0; t < nthreads; ++t) S->setup_threads.emplace_back(setup_loop, S);
-    S->engine = std::thread(engine_loop, S);
+    for (int l = 0; l < kLanes; ++l) S->lanes[l].thread = std::thread(engine_loop, S, l);
     *out = S;
     return BSDE_OK;
 }
@@ -375,17 +404,23 @@ void bsde_server_destroy(bsde_server S)
     }
     S->cv_admit.notify_all();
     for (auto &t : S->setup_threads) t.join();
-    // the engine finishes what is in flight, then stops
-    S->cv_engine.notify_all();
-    S->engine.join();
-    for (Request *q : S->ready) {
-        bsde_destroy(q->h);
-        delete q;
+    // the engines finish what is in flight, then stop
+    for (int l = 0; l < kLanes; ++l) {
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->lanes[l].cv.notify_all();
+        }
+        S->lanes[l].thread.join();
     }
+    for (int l = 0; l < kLanes; ++l)
+        for (Request *q : S->lanes[l].ready) {
+            bsde_destroy(q->h);
+            delete q;
+        }
     for (Request *q : S->pending) delete q;
     for (auto &kv : S->tickets)
         if (kv.second->done) delete kv.second;
-    (void)hipStreamDestroy(S->stream);
+    for (int l = 0; l < kLanes; ++l) (void)hipStreamDestroy(S->lanes[l].stream);
     delete S;
 }
 

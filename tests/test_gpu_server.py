@@ -139,3 +139,26 @@ def test_cheap_requests_chain_iterations_beside_a_heavy_one():
     assert rc["engine_steps"] <= 2, rc["engine_steps"]
     assert rc["price"] == alone["price"]
     np.testing.assert_array_equal(rc["delta"], alone["delta"])
+
+
+def test_light_requests_do_not_wait_for_heavy_steps():
+    # iterations of a few milliseconds go to the light engine lane, so a
+    # cheap request arriving beside a heavy problem (d = 5, ~10 ms per
+    # iteration) finishes long before it, with the result it gets alone
+    heavy = problem(d=5, vol_kind="bump", vol_level=[0.15, 0.2, 0.25, 0.3, 0.35],
+                    bump_a=0.25, rho=0.2, payoff="put_geom", S0=100.0,
+                    grid="random", n_t=10, n_x=4096, eta=3, M=1000, N=50,
+                    K_it=10, omega=1.0, precision="fp32", seed=903)
+    cheap = problem(d=1, vol_kind="bump", bump_a=0.25, n_t=6, n_x=20, eta=4,
+                    M=256, N=10, K_it=8, omega=1.0, precision="fp32", seed=904)
+    with bsde.Server(4 * GIB) as S:
+        alone = S.poll(S.submit(cheap))
+    with bsde.Server(4 * GIB) as S:
+        th = S.submit(heavy)
+        time.sleep(0.03)        # the heavy request is on the GPU by now
+        tc = S.submit(cheap)
+        rc, rh = S.poll(tc), S.poll(th)
+    assert rh["status"] == 0 and rc["status"] == 0
+    assert rc["latency_ms"] < 0.5 * rh["latency_ms"], (rc["latency_ms"], rh["latency_ms"])
+    assert rc["price"] == alone["price"]
+    np.testing.assert_array_equal(rc["delta"], alone["delta"])
