@@ -226,37 +226,15 @@ __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
 
 __host__ __device__ constexpr int pad32(int x) { return (x + 31) & ~31; }
 
-// FP32-path problems that contract on the matrix cores (d >= 5) keep, after
-// the FP32 channel table (pad16(p) x pad16(C) floats), the per-channel
-// power-of-two factors unscale[pad16(C)] and the table split into two FP16
-// parts, Gamma_c * scale_c = hi + lo, each laid out [C tile][16 channels]
-// [pad32(p) basis functions] so that a lane reads 8 consecutive basis
-// functions of one channel; all padding is zero.
-__host__ __device__ constexpr bool split_contraction(int d, bool fp32)
+// The channel table the path kernels read (FP64 and FP32 alike) holds the
+// live rows of the p x C table packed (see channel_row_live) in three
+// blocks: channel 0 over every row (p entries); each second-derivative
+// channel over its live rows, channel after channel; then row after row the
+// live entries of channels 1 .. 1 + d (the time derivative and the
+// gradient), in channel order -- at most p C entries in all.
+__host__ __device__ constexpr size_t table_entries(int p, int C)
 {
-    return fp32 && d >= 5;
-}
-__host__ __device__ constexpr size_t split_unscale_off(int p, int C) // floats
-{
-    return (size_t)pad16(p) * pad16(C);
-}
-__host__ __device__ constexpr size_t split_hi_off(int p, int C) // floats
-{
-    return split_unscale_off(p, C) + pad16(C);
-}
-__host__ __device__ constexpr size_t split_part_halves(int p, int C)
-{
-    return (size_t)pad16(C) * pad32(p);
-}
-// then the coefficients alpha (channel 0) once more as contiguous FP32,
-// for the value u^k(T, X_T) on the vector ALUs
-__host__ __device__ constexpr size_t split_alpha_off(int p, int C) // floats
-{
-    return split_hi_off(p, C) + split_part_halves(p, C); // two parts of halves
-}
-__host__ __device__ constexpr size_t split_table_floats(int p, int C)
-{
-    return split_alpha_off(p, C) + pad16(p);
+    return (size_t)p * C;
 }
 
 // channel 2 + d + idx holds d^2 u / dx_j dx_k for the idx-th pair j <= k
@@ -279,6 +257,110 @@ __host__ __device__ constexpr int hess_k(int d, int idx)
     }
     return j + idx;
 }
+
+// The channel table Gamma = D alpha holds derivatives of u = sum_l alpha_l
+// B_l (Section 4.2, the derivatives of the basis functions).  The
+// derivative of a Chebyshev factor has lower degree (T_a' is a combination
+// of the T_b with b < a and a - b odd), so over a downward-closed index set
+// Lambda the row of basis function nu in channel c can be non-zero only if
+// nu + e_v is in Lambda, c the derivative in variate v (v = 0 the time), or
+// nu + e_v + e_w is, c the second derivative in v and w (v = w included).
+// Channel 0, u itself, has every row.  in_set tests a multi-index (int[dp])
+// for membership in Lambda.
+template <int MAXDP, typename InSet>
+__host__ __device__ constexpr bool channel_row_live(const int8_t *nu, int dp, int c,
+                                                    const InSet &in_set)
+{
+    if (c == 0) return true;
+    const int d = dp - 1;
+    int mu[MAXDP] = {};
+    for (int v = 0; v < dp; ++v) mu[v] = nu[v];
+    if (c < 2 + d) {
+        mu[c - 1] += 1; // c = 1: the time; c = 2 + j: x_j, variate 1 + j
+    } else {
+        mu[1 + hess_j(d, c - 2 - d)] += 1;
+        mu[1 + hess_k(d, c - 2 - d)] += 1;
+    }
+    return in_set(mu);
+}
+
+// Membership in the kernel's index set {nu : |nu| <= ETA, sum_v nu_v^q <=
+// ETA^q} (the same test as in_index_set, with the powers tabulated)
+template <int DP, int ETA, int Q>
+struct IndexSetTest {
+    double qp[ETA + 3] = {};
+    double lim = 0.0;
+    constexpr IndexSetTest()
+    {
+        for (int n = 0; n < ETA + 3; ++n) qp[n] = qpow(n, Q);
+        lim = qpow(ETA, Q) * (1.0 + 1e-12);
+    }
+    constexpr bool operator()(const int *mu) const
+    {
+        int g = 0;
+        double s = 0.0;
+        for (int v = 0; v < DP; ++v) {
+            if (mu[v] > ETA) return false;
+            g += mu[v];
+            s += qp[mu[v]];
+        }
+        return g <= ETA && (Q == 10 || s <= lim);
+    }
+};
+
+// Packed positions of the kernel's live rows (layout above): hpos[h][l] is
+// the entry of row l in second-derivative channel 2 + d + h (-1: not
+// live); row l of the last block holds entries goff[l] .. goff[l+1]-1, entry
+// e of channel gch[e - goff[0]].
+template <int DP, int ETA, int Q>
+constexpr int channel_rows_count(int c_lo, int c_hi)
+{
+    using BS = Basis<DP, ETA, Q>;
+    constexpr IndexSetTest<DP, ETA, Q> in_set{};
+    int n = 0;
+    for (int l = 0; l < BS::P; ++l)
+        for (int c = c_lo; c < c_hi; ++c)
+            n += channel_row_live<DP>(BS::tab.nu[l], DP, c, in_set) ? 1 : 0;
+    return n;
+}
+
+template <int DP, int ETA, int Q>
+struct ChannelRowTable {
+    static constexpr int P = Basis<DP, ETA, Q>::P;
+    static constexpr int D = DP - 1;
+    static constexpr int NH = num_channels(D) - 2 - D; // second derivatives
+    static constexpr int NG = channel_rows_count<DP, ETA, Q>(1, 2 + D);
+    int16_t hpos[NH][P];
+    int16_t goff[P + 1];
+    uint8_t gch[NG];
+};
+
+template <int DP, int ETA, int Q>
+constexpr ChannelRowTable<DP, ETA, Q> make_channel_rows()
+{
+    using BS = Basis<DP, ETA, Q>;
+    using T = ChannelRowTable<DP, ETA, Q>;
+    constexpr IndexSetTest<DP, ETA, Q> in_set{};
+    T t{};
+    int e = BS::P; // after channel 0
+    for (int h = 0; h < T::NH; ++h)
+        for (int l = 0; l < BS::P; ++l)
+            t.hpos[h][l] = channel_row_live<DP>(BS::tab.nu[l], DP, 2 + T::D + h, in_set)
+                               ? (int16_t)e++ : (int16_t)-1;
+    const int g0 = e;
+    for (int l = 0; l < BS::P; ++l) {
+        t.goff[l] = (int16_t)e;
+        for (int c = 1; c < 2 + T::D; ++c)
+            if (channel_row_live<DP>(BS::tab.nu[l], DP, c, in_set)) t.gch[e++ - g0] = (uint8_t)c;
+    }
+    t.goff[BS::P] = (int16_t)e;
+    return t;
+}
+
+template <int DP, int ETA, int Q = 10>
+struct ChannelRows {
+    static constexpr ChannelRowTable<DP, ETA, Q> tab = make_channel_rows<DP, ETA, Q>();
+};
 
 // ---------------------------------------------------------------------------
 // Per-launch parameters of the path kernel (passed by value).
@@ -395,8 +477,8 @@ struct BatchUpdateDesc {
     double *alpha_out;
     const double *Dmat;    // (C-1) x p x p
     double *g64;
-    float *g32;            // FP32 table (+ the split FP16 parts if split)
-    int split;             // split_contraction(d, fp32)
+    float *g32;            // FP32 table
+    const int *cpos;       // C x p packed positions of the live rows (-1: none)
 };
 
 } // namespace bsde

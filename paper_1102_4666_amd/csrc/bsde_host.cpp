@@ -38,10 +38,10 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
                          const double *Dmat, double *g64, float *g32,
-                         int split, hipEvent_t *ev);
+                         const int *cpos, hipEvent_t *ev);
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
                            const double *Dmat, double *g64, float *g32,
-                           int split);
+                           const int *cpos);
 hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter);
@@ -664,16 +664,11 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
     return BSDE_OK;
 }
 
-// the FP32 channel table, with the split FP16 parts when the path kernel
-// contracts on the matrix cores
-static int split_of(const bsde_problem_s *h)
-{
-    return split_contraction(h->d, h->precision == BSDE_FP32_PATHS) ? 1 : 0;
-}
-static size_t g32_floats(const bsde_problem_s *h)
+// the channel tables: dense, then the live rows packed (bsde_common.h)
+static size_t table_floats(const bsde_problem_s *h)
 {
     if (h->kop) return 0; // the kernel operator reads its point table instead
-    return split_of(h) ? split_table_floats(h->p, h->C) : (size_t)pad16(h->p) * pad16(h->C);
+    return table_entries(h->p, h->C);
 }
 
 static void free_device(bsde_problem_s *h)
@@ -687,6 +682,7 @@ static void free_device(bsde_problem_s *h)
     h->d_pts = h->d_W = h->d_D = h->d_alpha = h->d_beta = h->d_g64 = nullptr;
     h->d_partial = h->d_c = h->d_var = nullptr;
     h->d_g32 = nullptr;
+    h->d_cpos = nullptr;
     h->d_block = nullptr;
 }
 
@@ -746,6 +742,7 @@ const char *bsde_status_string(bsde_status s)
     case BSDE_EDEVICE: return "HIP device error";
     case BSDE_ESTATE: return "invalid state";
     case BSDE_EUNSUPPORTED: return "no kernel for this (d, eta)";
+    case BSDE_EBUSY: return "request not finished";
     }
     return "unknown status";
 }
@@ -820,9 +817,9 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EUNSUPPORTED,
                     "no kernel instantiated for d=" + std::to_string(d) + ", eta=" +
                         std::to_string(grid->eta) + " with this precision and "
-                        "volatility kind (d = 10: FP32 paths only; the "
-                        "Dupire-type volatility: d=1 eta=4, d=2 eta=3, d=5 "
-                        "eta=2,3)");
+                        "volatility kind (d = 10: FP64 paths for total degree "
+                        "only; the Dupire-type volatility: d=1 eta=4, d=2 "
+                        "eta=3, d=5 eta=2,3)");
     double Lc[kMaxD * kMaxD];
     if (!cholesky(d, sigma->rho, Lc))
         return fail(BSDE_EINVAL, "correlation matrix not positive definite");
@@ -966,6 +963,30 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
                 }
         }
 
+    // positions of the live rows of each channel in the packed table, in
+    // the order the path kernels read it (bsde_common.h): channel 0; each
+    // second derivative over its rows; then row by row the time derivative
+    // and the gradient.  The kernel's index set is the set of rows here.
+    if (!kop) {
+        h->cpos.assign((size_t)h->C * h->p, -1);
+        auto in_set = [&](const int *mu) {
+            std::vector<int8_t> key(dp);
+            for (int v = 0; v < dp; ++v) key[v] = (int8_t)mu[v];
+            return pos.count(key) > 0;
+        };
+        auto live = [&](int l, int c) {
+            return channel_row_live<kMaxD + 1>(&h->nu[(size_t)l * dp], dp, c, in_set);
+        };
+        int e = 0;
+        for (int l = 0; l < h->p; ++l) h->cpos[l] = e++;
+        for (int c = 2 + d; c < h->C; ++c)
+            for (int l = 0; l < h->p; ++l)
+                if (live(l, c)) h->cpos[(size_t)c * h->p + l] = e++;
+        for (int l = 0; l < h->p; ++l)
+            for (int c = 1; c < 2 + d; ++c)
+                if (live(l, c)) h->cpos[(size_t)c * h->p + l] = e++;
+    }
+
     if (kop) {
         // the coefficients of a kernel-operator problem are its point values
         Dm.clear();
@@ -985,12 +1006,14 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     const size_t real_size = precision == BSDE_FP32_PATHS ? sizeof(float) : sizeof(double);
     const size_t b_pts = sizeof(double) * h->pts.size(), b_D = sizeof(double) * Dm.size(),
                  b_alpha = sizeof(double) * (size_t)(h->K_it + 1) * h->p,
-                 b_g64 = kop ? 0 : sizeof(double) * (size_t)pad16(h->p) * pad16(h->C),
-                 b_g32 = sizeof(float) * g32_floats(h),
+                 b_g64 = sizeof(double) * table_floats(h),
+                 b_g32 = sizeof(float) * table_floats(h),
+                 b_cpos = sizeof(int) * h->cpos.size(),
                  b_ktab = kop ? real_size * kKernelRow * (size_t)h->n : 0;
     const size_t o_D = al256(b_pts), o_alpha = o_D + al256(b_D),
                  o_g64 = o_alpha + al256(b_alpha), o_g32 = o_g64 + al256(b_g64),
-                 o_ktab = o_g32 + al256(b_g32), n_block = o_ktab + al256(b_ktab);
+                 o_cpos = o_g32 + al256(b_g32), o_ktab = o_cpos + al256(b_cpos),
+                 n_block = o_ktab + al256(b_ktab);
     bool ok = dalloc(&h->d_block, n_block) &&
               (kop || dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n)) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
@@ -1010,6 +1033,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         h->d_alpha = (double *)(b + o_alpha);
         h->d_g64 = (double *)(b + o_g64);
         h->d_g32 = (float *)(b + o_g32);
+        h->d_cpos = b_cpos ? (int *)(b + o_cpos) : nullptr;
         h->d_ktab = kop ? (void *)(b + o_ktab) : nullptr;
     }
     // the kernel operator's table: rows {z_0, .., z_d, y = 0} in the path
@@ -1043,6 +1067,7 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         std::memset(pin, 0, n_block);
         std::memcpy(pin, h->pts.data(), b_pts);
         if (b_D) std::memcpy((char *)pin + o_D, Dm.data(), b_D);
+        if (b_cpos) std::memcpy((char *)pin + o_cpos, h->cpos.data(), b_cpos);
         if (b_ktab) std::memcpy((char *)pin + o_ktab, ktab.data(), b_ktab);
         e = hipMemcpyAsync(h->d_block, pin, n_block, hipMemcpyHostToDevice, us);
     } else if (e == hipSuccess) {
@@ -1051,6 +1076,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
             e = hipMemcpyAsync(h->d_D, Dm.data(), b_D, hipMemcpyHostToDevice, us);
         if (e == hipSuccess)
             e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, o_ktab - o_alpha, us);
+        if (e == hipSuccess && b_cpos)
+            e = hipMemcpyAsync(h->d_cpos, h->cpos.data(), b_cpos, hipMemcpyHostToDevice, us);
         if (e == hipSuccess && b_ktab)
             e = hipMemcpyAsync(h->d_ktab, ktab.data(), b_ktab, hipMemcpyHostToDevice, us);
     }
@@ -1183,7 +1210,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     // table already holds the current point values)
     if (!h->kop)
         HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                                h->d_D, h->d_g64, h->d_g32, split_of(h)));
+                                h->d_D, h->d_g64, h->d_g32, h->d_cpos));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
         hipEvent_t *e = per ? &ev[2 + (size_t)per * it] : nullptr;
@@ -1230,7 +1257,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
                               h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
-                              h->d_g32, split_of(h),
+                              h->d_g32, h->d_cpos,
                               per == 5 ? e + 2 : nullptr)); // records e[2..4]
     }
     HIP_TRY(hipEventRecord(ev[1], s));
@@ -1321,7 +1348,7 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
     u.Dmat = h->d_D;
     u.g64 = h->d_g64;
     u.g32 = h->d_g32;
-    u.split = split_of(h);
+    u.cpos = h->d_cpos;
     return u;
 }
 } // namespace
@@ -1615,9 +1642,8 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
     auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t block = al256(n * (d + 1) * 8) + al256((C - 1) * p * p * 8) +
                          al256((size_t)(K_it + 1) * p * 8) +
-                         al256((size_t)pad16(p) * pad16((int)C) * 8) +
-                         al256((d >= 5 ? split_table_floats(p, (int)C)
-                                       : (size_t)pad16(p) * pad16((int)C)) * 4);
+                         al256(table_entries(p, (int)C) * 8) +
+                         al256(table_entries(p, (int)C) * 4) + al256(C * p * 4);
     const size_t sizes[] = {block, (size_t)p * n * 8, (size_t)p * 8,
                             (size_t)K_it * n * 8,
                             (size_t)K_it * n * 8,
@@ -1710,7 +1736,6 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
 {
     if (!h) return fail(BSDE_EINVAL, "null handle");
     hipStream_t s = (hipStream_t)hip_stream;
-    const bool fp32 = h->precision == BSDE_FP32_PATHS;
     // candidates: paths per lane in powers of two, groups to cover M
     std::vector<std::pair<int, int>> cand;
     for (int ppl = 1; ppl <= 64; ppl *= 2) {
@@ -1732,7 +1757,7 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
     const int k = std::min(h->k_done, h->K_it - 1);
     if (!h->kop)
         HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                                h->d_D, h->d_g64, h->d_g32, split_of(h)));
+                                h->d_D, h->d_g64, h->d_g32, h->d_cpos));
     hipEvent_t e0, e1;
     HIP_TRY(event_get(&e0));
     HIP_TRY(event_get(&e1));

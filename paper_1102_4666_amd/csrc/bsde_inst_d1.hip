@@ -5,8 +5,9 @@
 
 namespace bsde {
 #define SETS_D1(X)                                                             \
-    X(2, 10, true, false) X(3, 10, true, false) X(4, 10, true, true)           \
-    X(5, 10, true, false) X(6, 10, true, false) X(8, 10, true, false)
+    X(2, 10, kPrecBoth, false) X(3, 10, kPrecBoth, false)                      \
+    X(4, 10, kPrecBoth, true) X(5, 10, kPrecBoth, false)                       \
+    X(6, 10, kPrecBoth, false) X(8, 10, kPrecBoth, false)
 BSDE_DEFINE_DIMENSION(1, SETS_D1)
 BSDE_DEFINE_KERNEL_OP(1)
 } // namespace bsde

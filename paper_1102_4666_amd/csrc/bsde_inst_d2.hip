@@ -5,8 +5,8 @@
 
 namespace bsde {
 #define SETS_D2(X)                                                             \
-    X(2, 10, true, false) X(3, 10, true, true) X(4, 10, true, false)           \
-    X(5, 10, true, false)
+    X(2, 10, kPrecBoth, false) X(3, 10, kPrecBoth, true)                       \
+    X(4, 10, kPrecBoth, false) X(5, 10, kPrecBoth, false)
 BSDE_DEFINE_DIMENSION(2, SETS_D2)
 BSDE_DEFINE_KERNEL_OP(2)
 } // namespace bsde

@@ -3,6 +3,8 @@
 #include "bsde_path.h"
 
 namespace bsde {
-#define SETS_D3(X) X(2, 10, true, false) X(3, 10, true, false) X(4, 10, true, false)
+#define SETS_D3(X)                                                             \
+    X(2, 10, kPrecBoth, false) X(3, 10, kPrecBoth, false)                      \
+    X(4, 10, kPrecBoth, false)
 BSDE_DEFINE_DIMENSION(3, SETS_D3)
 } // namespace bsde

@@ -4,6 +4,6 @@
 #include "bsde_path.h"
 
 namespace bsde {
-#define SETS_D5(X) X(2, 10, true, true) X(3, 10, true, true)
+#define SETS_D5(X) X(2, 10, kPrecBoth, true) X(3, 10, kPrecBoth, true)
 BSDE_DEFINE_DIMENSION(5, SETS_D5)
 } // namespace bsde

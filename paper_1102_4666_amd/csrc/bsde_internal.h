@@ -27,12 +27,15 @@ struct bsde_problem_s {
     std::vector<double> pts;     // n x (d+1)
     std::vector<double> lo, hi;
     std::vector<double> Dfirst;  // d x p x p: d_{x_j} channel matrices
+    std::vector<int> cpos;       // C x p: entry of (l, c) in the packed table, or -1
     // device
     double *d_pts = nullptr, *d_W = nullptr, *d_D = nullptr,
            *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
            *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
     float *d_g32 = nullptr;
-    // d_pts, d_D, d_alpha, d_g64, d_g32 and d_ktab live in this one allocation
+    int *d_cpos = nullptr; // C x p packed positions of the channel table's live rows
+    // d_pts, d_D, d_alpha, d_g64, d_g32, d_cpos and d_ktab live in this one
+    // allocation
     void *d_block = nullptr;
     // kernel operator of Section 3.2 (kop): bandwidth and the path kernel's
     // table of rows {z_0, .., z_d, y} (FP32 or FP64 as the paths); d_alpha

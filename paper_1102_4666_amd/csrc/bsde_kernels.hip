@@ -67,75 +67,33 @@ __global__ __launch_bounds__(256) void project_kernel(
 constexpr int kMaxP = 512;
 
 // channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with a = alpha_in + beta
-// (channel 0 is the identity and also stores a as the next coefficients).
-// With split set, also the FP16 parts of the FP32 table (layout in
-// bsde_common.h): Gamma_lc scale_c = hi + lo with scale_c = 2^-e, e the
-// binary exponent of max_l |Gamma_lc| (so the scaled column lies in
-// (-1, 1)), and unscale_c = 2^e.
+// (channel 0 is the identity and also stores a as the next coefficients),
+// in FP64 and FP32, each live row l to entry cpos[c p + l] of the packed
+// table (layout in bsde_common.h).
 __device__ __forceinline__ void channel_col(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
     double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
     int C, int c, double *__restrict__ g64, float *__restrict__ g32,
-    int split)
+    const int *__restrict__ cpos)
 {
     __shared__ double a[kMaxP];
-    __shared__ float red[256 / 64];
-    const int Cs = pad16(C); // row stride of the channel table
     for (int m = threadIdx.x; m < p; m += 256)
         a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
     __syncthreads();
-    // this thread's entries l = threadIdx.x + 256 j (p <= kMaxP = 512)
-    float mine[kMaxP / 256];
-    float amax = 0.0f;
-#pragma unroll
-    for (int j = 0; j < kMaxP / 256; ++j) {
-        const int l = threadIdx.x + 256 * j;
-        mine[j] = 0.0f;
-        if (l >= p) continue;
+    for (int l = threadIdx.x; l < p; l += 256) {
+        if (c == 0 && alpha_out) alpha_out[l] = a[l];
+        const int e = cpos[(size_t)c * p + l];
+        if (e < 0) continue;
         double v;
         if (c == 0) {
             v = a[l];
-            if (alpha_out) alpha_out[l] = v;
         } else {
             const double *drow = Dmat + ((size_t)(c - 1) * p + l) * p;
             v = 0.0;
             for (int m = 0; m < p; ++m) v += drow[m] * a[m];
         }
-        g64[(size_t)l * Cs + c] = v;
-        g32[(size_t)l * Cs + c] = (float)v;
-        mine[j] = (float)v;
-        amax = fmaxf(amax, fabsf((float)v));
-    }
-    if (!split) return;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
-    __syncthreads();
-    amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    const int e = amax > 0.0f ? __builtin_amdgcn_frexp_expf(amax) : 0;
-    const float scale = __builtin_amdgcn_ldexpf(1.0f, -e);
-    float *unscale = g32 + split_unscale_off(p, C);
-    if (threadIdx.x == 0) unscale[c] = __builtin_amdgcn_ldexpf(1.0f, e);
-    if (c == 0) {
-        float *alpha32 = g32 + split_alpha_off(p, C);
-#pragma unroll
-        for (int j = 0; j < kMaxP / 256; ++j) {
-            const int l = threadIdx.x + 256 * j;
-            if (l < p) alpha32[l] = mine[j];
-        }
-    }
-    _Float16 *hi = (_Float16 *)(g32 + split_hi_off(p, C));
-    _Float16 *lo = hi + split_part_halves(p, C);
-    const int K32 = pad32(p);
-    const size_t col = (size_t)c * K32; // [c / 16][c % 16][l] = c K32 + l
-#pragma unroll
-    for (int j = 0; j < kMaxP / 256; ++j) {
-        const int l = threadIdx.x + 256 * j;
-        if (l >= p) continue;
-        const float v = mine[j] * scale;
-        const _Float16 h = (_Float16)v;
-        hi[col + l] = h;
-        lo[col + l] = (_Float16)(v - (float)h);
+        g64[e] = v;
+        g32[e] = (float)v;
     }
 }
 
@@ -143,10 +101,11 @@ __device__ __forceinline__ void channel_col(
 __global__ __launch_bounds__(256) void channel_kernel(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
     double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, double *__restrict__ g64, float *__restrict__ g32, int split)
+    int C, double *__restrict__ g64, float *__restrict__ g32,
+    const int *__restrict__ cpos)
 {
     channel_col(alpha_in, beta, alpha_out, Dmat, p, C, blockIdx.x, g64, g32,
-                split);
+                cpos);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,7 +133,7 @@ __global__ __launch_bounds__(256) void batch_channel_kernel(
     if ((int)blockIdx.x < q.C)
         channel_col(q.alpha_in, with_beta ? q.beta : nullptr,
                     with_beta ? q.alpha_out : nullptr, q.Dmat, q.p, q.C,
-                    blockIdx.x, q.g64, q.g32, q.split);
+                    blockIdx.x, q.g64, q.g32, q.cpos);
 }
 
 // Point values of the kernel operator (Section 3.2) for the next iteration:
@@ -273,26 +232,29 @@ hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch over the instantiated (d, eta) pairs
+// Dispatch over the translation units of path kernels: X(D, NAME) for the
+// unit of dimension D whose functions are named launch_path_dNAME, ...
+// (bsde_path.h).  d = 10 has a unit for its total-degree sets in FP32, one
+// for them in FP64 and one per hyperbolic set (eta = 5, q = 0.5, 0.6, 0.7).
 // ---------------------------------------------------------------------------
-#define BSDE_DIMS(X) X(1) X(2) X(3) X(5) X(10)
-#define DECL(D)                                                                \
-    hipError_t launch_path_d##D(int eta, int q10, bool fp32, int blocks,        \
+#define BSDE_UNITS(X)                                                          \
+    X(1, 1) X(2, 2) X(3, 3) X(5, 5) X(10, 10) X(10, 10d) X(10, 10q5)           \
+    X(10, 10q6) X(10, 10q7)
+#define DECL(D, N)                                                             \
+    hipError_t launch_path_d##N(int eta, int q10, bool fp32, int blocks,        \
                                 hipStream_t s,                                 \
                                 const PathParams &prm, const double *pts,      \
                                 const void *gamma, double *partial,            \
                                 hipEvent_t ev0, hipEvent_t ev1);               \
-    int index_table_d##D(int eta, int q10, int8_t *nu, int cap);               \
-    hipError_t launch_batch_d##D(int eta, int q10, bool fp32, int vol,         \
+    int index_table_d##N(int eta, int q10, int8_t *nu, int cap);               \
+    hipError_t launch_batch_d##N(int eta, int q10, bool fp32, int vol,         \
                                  int blocks,                                   \
                                  hipStream_t s, const BatchTileDesc *probs,    \
                                  int nprob, const long long *tile_begin,       \
                                  unsigned int *counter);                       \
-    int batch_occupancy_d##D(int eta, int q10, bool fp32, int vol);            \
-    bool has_variant_d##D(int eta, int q10, bool fp32, int vol);
-BSDE_DIMS(DECL)
-// the hyperbolic-set kernels of d = 10 (their own translation unit)
-DECL(10h)
+    int batch_occupancy_d##N(int eta, int q10, bool fp32, int vol);            \
+    bool has_variant_d##N(int eta, int q10, bool fp32, int vol);
+BSDE_UNITS(DECL)
 #undef DECL
 hipError_t launch_kernel_path_d1(bool fp32, int blocks, hipStream_t s,
                                  const PathParams &prm, const double *pts,
@@ -324,13 +286,12 @@ hipError_t launch_kernel_path(int d, bool fp32, int blocks, hipStream_t s,
 
 int index_table(int d, int eta, int q10, int8_t *nu, int cap)
 {
-    if (d == 10) {
-        const int p = index_table_d10h(eta, q10, nu, cap);
-        if (p > 0) return p;
+#define X(D, N)                                                                \
+    if (d == D) {                                                              \
+        const int p = index_table_d##N(eta, q10, nu, cap);                     \
+        if (p > 0) return p;                                                   \
     }
-#define X(D)                                                                   \
-    if (d == D) return index_table_d##D(eta, q10, nu, cap);
-    BSDE_DIMS(X)
+    BSDE_UNITS(X)
 #undef X
     return 0;
 }
@@ -342,10 +303,9 @@ bool kernel_exists(int d, int eta, int q10)
 
 bool variant_exists(int d, int eta, int q10, bool fp32, int vol)
 {
-    if (d == 10 && has_variant_d10h(eta, q10, fp32, vol)) return true;
-#define X(D)                                                                   \
-    if (d == D) return has_variant_d##D(eta, q10, fp32, vol);
-    BSDE_DIMS(X)
+#define X(D, N)                                                                \
+    if (d == D && has_variant_d##N(eta, q10, fp32, vol)) return true;
+    BSDE_UNITS(X)
 #undef X
     return false;
 }
@@ -355,14 +315,11 @@ hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream
                        const void *gamma, double *partial, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
-    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
-        return launch_path_d10h(eta, q10, fp32, blocks, s, prm, pts, gamma, partial,
-                                ev0, ev1);
-#define X(D)                                                                   \
-    if (d == D)                                                                \
-        return launch_path_d##D(eta, q10, fp32, blocks, s, prm, pts, gamma,    \
+#define X(D, N)                                                                \
+    if (d == D && has_variant_d##N(eta, q10, fp32, prm.vol_kind))              \
+        return launch_path_d##N(eta, q10, fp32, blocks, s, prm, pts, gamma,    \
                                 partial, ev0, ev1);
-    BSDE_DIMS(X)
+    BSDE_UNITS(X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -371,25 +328,21 @@ hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter)
 {
-    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
-        return launch_batch_d10h(eta, q10, fp32, vol, blocks, s, probs, nprob,
+#define X(D, N)                                                                \
+    if (d == D && has_variant_d##N(eta, q10, fp32, vol))                       \
+        return launch_batch_d##N(eta, q10, fp32, vol, blocks, s, probs, nprob, \
                                  tile_begin, counter);
-#define X(D)                                                                   \
-    if (d == D)                                                                \
-        return launch_batch_d##D(eta, q10, fp32, vol, blocks, s, probs, nprob, \
-                                 tile_begin, counter);
-    BSDE_DIMS(X)
+    BSDE_UNITS(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
 int batch_occupancy(int d, int eta, int q10, bool fp32, int vol)
 {
-    if (d == 10 && index_table_d10h(eta, q10, nullptr, 0) > 0)
-        return batch_occupancy_d10h(eta, q10, fp32, vol);
-#define X(D)                                                                   \
-    if (d == D) return batch_occupancy_d##D(eta, q10, fp32, vol);
-    BSDE_DIMS(X)
+#define X(D, N)                                                                \
+    if (d == D && has_variant_d##N(eta, q10, fp32, vol))                       \
+        return batch_occupancy_d##N(eta, q10, fp32, vol);
+    BSDE_UNITS(X)
 #undef X
     return 0;
 }
@@ -399,7 +352,7 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
                          const double *Dmat, double *g64, float *g32,
-                         int split, hipEvent_t *ev /* 3 events or NULL */)
+                         const int *cpos, hipEvent_t *ev /* 3 events or NULL */)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0,
                        s, partial, n, groups, M, c, var);
@@ -408,18 +361,18 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                        beta);
     if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha_in,
-                       beta, alpha_out, Dmat, p, C, g64, g32, split);
+                       beta, alpha_out, Dmat, p, C, g64, g32, cpos);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
 hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
                            const double *Dmat, double *g64, float *g32,
-                           int split)
+                           const int *cpos)
 {
     hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha,
                        (const double *)nullptr, (double *)nullptr, Dmat, p,
-                       C, g64, g32, split);
+                       C, g64, g32, cpos);
     return hipGetLastError();
 }
 

@@ -216,49 +216,6 @@ __device__ __forceinline__ void cheb(Real z, Real *Tz)
     for (int a = 1; a < ETA; ++a) Tz[a + 1] = Real(2) * z * Tz[a] - Tz[a - 1];
 }
 
-// 16 x 16 x 4 matrix-core products (wave64).  Operands: lane L holds
-// A[L % 16][L / 16] and B[L / 16][L % 16]; the accumulator element i of lane
-// L is D[row(L, i)][L % 16].
-// Each wave of the matrix-core contraction stages its operands in its own
-// LDS slice, so ordering its LDS writes before its reads needs no workgroup
-// barrier: a wave's LDS operations complete in issue order, and the
-// wavefront-scope fences keep the compiler from moving them across.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename Real>
-struct Mfma;
-
-template <>
-struct Mfma<float> {
-    typedef float acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int L, int i)
-    {
-        return 4 * (L >> 4) + i;
-    }
-};
-
-template <>
-struct Mfma<double> {
-    typedef double acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int L, int i)
-    {
-        return (L >> 4) + 4 * i;
-    }
-};
-
 // One Philox4x32-10 round in the path kernel (the function of philox_round).
 // Bit 0 / bit 1 of X3 select, for the new word 0 / word 2, the three-way
 // XOR (high half ^ counter word ^ key) as one v_bitop3_b32 with truth table
@@ -381,12 +338,9 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
                                          const int g, double *__restrict__ out)
 {
     constexpr int DP = D + 1;
-    constexpr int C = num_channels(D);
-    constexpr int Cs = pad16(C); // row stride of Gamma
+    [[maybe_unused]] constexpr int C = num_channels(D);
     using BS = Basis<DP, ETA, Q>;
     constexpr int NP = BS::P;
-    // d >= 5: the basis-row x Gamma contraction runs on the matrix cores
-    constexpr bool kMfma = D >= 5;
     // steps per group so that a group uses whole Philox blocks
     constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
     constexpr int NB = SG * D / 4;
@@ -475,13 +429,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
         int m = (g * prm.paths_per_lane + rr) * kBlock + (int)threadIdx.x;
         const bool valid = m < prm.M;
-        if constexpr (kMfma) {
-            // matrix-core products need the whole wave: lanes past M run
-            // path 0 again and discard it
-            if (!valid) m = 0;
-        } else {
-            if (!valid) break;
-        }
+        if (!valid) break;
 
         // U, j* = floor(U N) and theta = U N - j* in integer arithmetic
         const u32x4 wu = block((uint32_t)m, 1u << 24);
@@ -708,45 +656,8 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
             gen = acc / S0;
             uT = S1T / S0T;
             terminal = payoff<D>(prm.payoff, K, X) - uT;
-        } else if constexpr (!kMfma) {
-            Real Bv[NP], BT[NP];
-            Real V[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) V[c] = Real(0);
-            static_for<NP>([&](auto lc) {
-                constexpr int l = decltype(lc)::value;
-                if constexpr (l == 0) {
-                    Bv[0] = Real(1);
-                    BT[0] = Real(1);
-                } else {
-                    constexpr int par = BS::tab.parent[l];
-                    constexpr int v = BS::tab.var[l];
-                    constexpr int dg = BS::tab.deg[l];
-                    Bv[l] = Bv[par] * Tz[v][dg];
-                    BT[l] = BT[par] * TzT[v][dg];
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) V[c] += Bv[l] * gamma[l * Cs + c];
-                uT += BT[l] * gamma[l * Cs];
-            });
-            // frozen generator: d_t u + b* . grad u + sum cov_jk d_jk u
-            gen = V[1];
-#pragma unroll
-            for (int j = 0; j < D; ++j) gen += bst[j] * V[2 + j];
-            int idx = 2 + D;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-#pragma unroll
-                for (int l = j; l < D; ++l, ++idx) {
-                    const Real cov = (l == j) ? Real(0.5) * sgs[j] * sgs[j]
-                                              : rho * sgs[j] * sgs[l];
-                    gen += cov * V[idx];
-                }
-            }
-            u = V[0];
-            terminal = payoff<D>(prm.payoff, K, X) - uT;
         } else {
-            asm volatile("" : "+v"(phi_tau));
+            if constexpr (D >= 5) asm volatile("" : "+v"(phi_tau));
             // basis function l as the product of its non-zero Chebyshev
             // factors (at most eta of them), so that no earlier basis value
             // has to stay live in registers
@@ -760,39 +671,6 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
                 });
                 return v;
             };
-            // Gamma is loop-invariant, so the compiler would hoist all of its
-            // loads out of the path loop and park them in registers; reading
-            // it through an address made opaque per use keeps each load next
-            // to its products
-            // (constant address space: Gamma does not change during the
-            // launch, so uniform reads of it are scalar loads)
-            auto opaque = [&](int offset) {
-                uint64_t a = (uint64_t)(uintptr_t)&gamma[offset];
-                asm volatile("" : "+s"(a));
-                return (const __attribute__((address_space(4))) Real *)a;
-            };
-            // u^k(T, X_T): one dot product with channel 0, 16 terms at a time
-            // (the scheduling barriers keep the loads next to their use);
-            // FP32 problems keep channel 0 contiguous as well, so that 16
-            // coefficients come in one scalar load
-            constexpr bool kAlpha32 = std::is_same<Real, float>::value;
-            static_for<pad16(NP) / 16>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                __builtin_amdgcn_sched_barrier(0);
-                const auto g0 = kAlpha32 ? opaque((int)split_alpha_off(NP, C) + q * 16)
-                                         : opaque(q * 16 * Cs);
-                static_for<16>([&](auto jc) {
-                    constexpr int l = q * 16 + decltype(jc)::value;
-                    if constexpr (l < NP)
-                        uT += basis(std::integral_constant<int, l>{}, TzT) *
-                              g0[kAlpha32 ? (l - q * 16) : (l - q * 16) * Cs];
-                });
-            });
-            // the terminal term is complete here (nothing of X_T stays live
-            // through the contraction)
-            terminal = payoff<D>(prm.payoff, K, X) - uT;
-            asm volatile("" : "+v"(terminal));
-            __builtin_amdgcn_sched_barrier(0);
             // fold of channel c of V (this lane's path) into u and the
             // frozen generator
             auto fold = [&](auto cc, Real vc) {
@@ -811,207 +689,59 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
                     gen += cov * vc;
                 }
             };
-            constexpr int NT = Cs / 16;
-            const int lane = threadIdx.x & 63;
-            if constexpr (std::is_same<Real, float>::value) {
-                // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave on
-                // v_mfma_f32_16x16x32_f16 with both operands split into two
-                // FP16 parts, B = Bh + Bl and Gamma s_c = Gh + Gl, and
-                // V = Bh Gh + Bh Gl + Bl Gh accumulated in FP32 (the dropped
-                // Bl Gl is 2^-22 of the product).  The row is scaled by a
-                // power of two 2^-e so that |B_l| <= 1 for every path
-                // (|B_l| is at most the product of the MAXV largest
-                // max(1, |T_eta(z_v)|), Chebyshev values growing with the
-                // degree outside [-1, 1]); the column scales s_c come with
-                // the table.  Chunks of 32 basis functions go through the
-                // wave's LDS rows ([path][function], 8 functions per 16-byte
-                // access) into the A operand; the table parts, laid out
-                // [channel][function], are the B operand.  A and B agree on
-                // which basis function sits in each K slot of a lane.
-                typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-                constexpr int MAXV = [] {
-                    int m = 0;
-                    for (int l = 0; l < NP; ++l) {
-                        int c = 0;
-                        for (int v = 0; v < DP; ++v) c += BS::tab.nu[l][v] > 0;
-                        m = c > m ? c : m;
-                    }
-                    return m;
-                }();
-                constexpr int K32 = pad32(NP);
-                constexpr int NCH = K32 / 32;
-                constexpr int kRow = 40; // halves per LDS row (32 + padding)
-                float top[MAXV];
-#pragma unroll
-                for (int i = 0; i < MAXV; ++i) top[i] = 1.0f;
-#pragma unroll
-                for (int v = 0; v < DP; ++v) {
-                    float x = fabsf(Tz[v][ETA]);
-#pragma unroll
-                    for (int i = 0; i < MAXV; ++i) {
-                        const float hi = fmaxf(top[i], x);
-                        x = fminf(top[i], x);
-                        top[i] = hi;
-                    }
-                }
-                float bound = top[0];
-#pragma unroll
-                for (int i = 1; i < MAXV; ++i) bound *= top[i];
-                const int rexp = bound > 1.0f ? __builtin_amdgcn_frexp_expf(bound) : 0;
-                const float rscale = __builtin_amdgcn_ldexpf(1.0f, -rexp);
-                __shared__ __attribute__((aligned(16))) _Float16
-                    ldsh[kBlock / 64][2][64 * kRow];
-                _Float16 *rowh = ldsh[threadIdx.x >> 6][0];
-                _Float16 *rowl = ldsh[threadIdx.x >> 6][1];
-                using Acc = typename Mfma<float>::acc_t;
-                Acc acc[4][NT];
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
-                auto opaque_h = [&](size_t offset) {
-                    uint64_t a = (uint64_t)(uintptr_t)((const _Float16 *)&gamma[split_hi_off(NP, C)] + offset);
-                    asm volatile("" : "+s"(a));
-                    return (const __attribute__((address_space(1))) _Float16 *)a;
-                };
-                static_for<NCH>([&](auto qc) {
-                    constexpr int q = decltype(qc)::value;
-                    __builtin_amdgcn_sched_barrier(0);
-                    static_for<4>([&](auto gc) {
-                        constexpr int g = decltype(gc)::value;
-                        __builtin_amdgcn_sched_barrier(0);
-                        h8 vh, vl;
-                        static_for<8>([&](auto ic) {
-                            constexpr int i8 = decltype(ic)::value;
-                            constexpr int l = q * 32 + g * 8 + i8;
-                            float v = 0.0f;
-                            if constexpr (l < NP)
-                                v = rscale * basis(std::integral_constant<int, l>{}, Tz);
-                            const _Float16 h = (_Float16)v;
-                            vh[i8] = h;
-                            vl[i8] = (_Float16)(v - (float)h);
-                        });
-                        *(h8 *)&rowh[lane * kRow + g * 8] = vh;
-                        *(h8 *)&rowl[lane * kRow + g * 8] = vl;
-                    });
-                    wave_lds_sync();
-                    // Bh (Gh + Gl) first, then Bl Gh: only one A part is
-                    // live at a time
-                    const auto gh = opaque_h((size_t)q * 32);
-                    static_for<2>([&](auto pc) {
-                        constexpr int part = decltype(pc)::value;
-                        const _Float16 *rows = part == 0 ? rowh : rowl;
-                        h8 a[4];
-#pragma unroll
-                        for (int mt = 0; mt < 4; ++mt)
-                            a[mt] = *(const h8 *)&rows[(mt * 16 + (lane & 15)) * kRow + 8 * (lane >> 4)];
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) {
-                            const size_t off = (size_t)(nt * 16 + (lane & 15)) * K32 + 8 * (lane >> 4);
-                            const h8 bh = *(const __attribute__((address_space(1))) h8 *)&gh[off];
-#pragma unroll
-                            for (int mt = 0; mt < 4; ++mt)
-                                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mt], bh, acc[mt][nt], 0, 0, 0);
-                            if constexpr (part == 0) {
-                                const h8 bl = *(const __attribute__((address_space(1))) h8 *)&gh[split_part_halves(NP, C) + off];
-#pragma unroll
-                                for (int mt = 0; mt < 4; ++mt)
-                                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mt], bl, acc[mt][nt], 0, 0, 0);
-                            }
-                        }
-                    });
-                    wave_lds_sync();
+            {
+                // V = B Gamma over the live rows of the channel table only
+                // (channel_row_live): the derivative channels of a
+                // polynomial over a downward-closed set have lower degree,
+                // so the 67 channels of d = 10, eta = 3 need 1,882 of the
+                // 364 x 67 products and the 22 of d = 5, eta = 3 need 357 of
+                // 84 x 22.  The packed table is uniform across the wave:
+                // each fused multiply-add takes its entry as a scalar
+                // operand and the basis value as the vector one.  The
+                // table's address is made opaque once per path, so that its
+                // loads stay in the path's iteration instead of being
+                // hoisted out of the path loop into registers.
+                using CR = ChannelRows<DP, ETA, Q>;
+                uint64_t pa = (uint64_t)(uintptr_t)&gamma[0];
+                asm volatile("" : "+s"(pa));
+                const auto pk = (const __attribute__((address_space(4))) Real *)pa;
+                // u^k(T, X_T): channel 0
+                static_for<NP>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    uT = fma(basis(lc, TzT), pk[l], uT);
                 });
-                // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
-                // 16 nt + col]; back through LDS so that each lane reads its
-                // own path's channels, undoes the column scales and folds
-                float *buf = (float *)rowh;
-                static_for<NT>([&](auto ntc) {
-                    constexpr int nt = decltype(ntc)::value;
+                terminal = payoff<D>(prm.payoff, K, X) - uT;
+                // second derivatives first, one channel at a time, each
+                // folded as soon as it is complete: their live rows are
+                // those of degree at most eta - 2 (at total degree 3 the
+                // constant and the linear ones, whose basis values are the
+                // coordinates themselves), so no accumulator of theirs
+                // stays live through the rest of the rows
+                static_for<CR::tab.NH>([&](auto hc) {
+                    constexpr int h = decltype(hc)::value;
+                    Real vc = Real(0);
+                    static_for<NP>([&](auto lc) {
+                        constexpr int e = CR::tab.hpos[h][decltype(lc)::value];
+                        if constexpr (e >= 0) vc = fma(basis(lc, Tz), pk[e], vc);
+                    });
+                    fold(std::integral_constant<int, 2 + D + h>{}, vc);
+                });
+                // then u, d_t u and the gradient over every row in order
+                Real V[2 + D];
 #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            buf[(16 * mt + Mfma<float>::row(lane, e)) * 17 + (lane & 15)] =
-                                acc[mt][nt][e];
-                    wave_lds_sync();
-                    __builtin_amdgcn_sched_barrier(0);
-                    const auto us = opaque(split_unscale_off(NP, C) + nt * 16);
-                    static_for<16>([&](auto cc) {
-                        constexpr int c = nt * 16 + decltype(cc)::value;
-                        if constexpr (c < C)
-                            fold(std::integral_constant<int, c>{},
-                                 buf[lane * 17 + decltype(cc)::value] * us[decltype(cc)::value]);
+                for (int c = 0; c < 2 + D; ++c) V[c] = Real(0);
+                static_for<NP>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    constexpr int e0 = CR::tab.goff[l];
+                    const Real b = basis(lc, Tz);
+                    V[0] = fma(b, pk[l], V[0]);
+                    static_for<CR::tab.goff[l + 1] - e0>([&](auto ec) {
+                        constexpr int e = e0 + decltype(ec)::value;
+                        constexpr int c = CR::tab.gch[e - CR::tab.goff[0]];
+                        V[c] = fma(b, pk[e], V[c]);
                     });
-                    wave_lds_sync();
                 });
-                // undo the row scale
-                const float runscale = __builtin_amdgcn_ldexpf(1.0f, rexp);
-                u *= runscale;
-                gen *= runscale;
-            } else {
-                // V (64 paths x C) = B (64 x NP) Gamma (NP x C) per wave: the
-                // basis row goes through LDS in chunks of 16 functions into the
-                // A operand; Gamma tiles are the B operand; 4 x NT accumulators
-                constexpr int NCH = pad16(NP) / 16;
-                using Acc = typename Mfma<Real>::acc_t;
-                __shared__ Real lds[kBlock / 64][64 * 17];
-                Real *buf = lds[threadIdx.x >> 6];
-                Acc acc[4][NT];
-    #pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-    #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = Acc{0, 0, 0, 0};
-                static_for<NCH>([&](auto qc) {
-                    constexpr int q = decltype(qc)::value;
-                    __builtin_amdgcn_sched_barrier(0);
-                    static_for<16>([&](auto jc) {
-                        constexpr int jj = decltype(jc)::value;
-                        constexpr int l = q * 16 + jj;
-                        Real v = Real(0);
-                        if constexpr (l < NP)
-                            v = basis(std::integral_constant<int, l>{}, Tz);
-                        buf[jj * 64 + lane] = v; // [function][path]
-                    });
-                    wave_lds_sync();
-                    const auto gq = opaque(q * 16 * Cs);
-    #pragma unroll
-                    for (int kb = 0; kb < 4; ++kb) {
-                        const int lrow = kb * 4 + (lane >> 4);
-                        Real bop[NT];
-    #pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            bop[nt] = gq[lrow * Cs + nt * 16 + (lane & 15)];
-    #pragma unroll
-                        for (int mt = 0; mt < 4; ++mt) {
-                            const Real aop = buf[lrow * 64 + mt * 16 + (lane & 15)];
-    #pragma unroll
-                            for (int nt = 0; nt < NT; ++nt)
-                                acc[mt][nt] = Mfma<Real>::mma(aop, bop[nt], acc[mt][nt]);
-                        }
-                    }
-                    wave_lds_sync();
-                });
-                // accumulator tile (mt, nt) holds V[path 16 mt + row][channel
-                // 16 nt + col]; back through LDS so that each lane reads its own
-                // path's channels and folds them into u and the generator
-                static_for<NT>([&](auto ntc) {
-                    constexpr int nt = decltype(ntc)::value;
-    #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-    #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            buf[(16 * mt + Mfma<Real>::row(lane, e)) * 17 + (lane & 15)] =
-                                acc[mt][nt][e];
-                    wave_lds_sync();
-                    static_for<16>([&](auto cc) {
-                        constexpr int c = nt * 16 + decltype(cc)::value;
-                        if constexpr (c < C)
-                            fold(std::integral_constant<int, c>{},
-                                 buf[lane * 17 + decltype(cc)::value]);
-                    });
-                    wave_lds_sync();
-                });
+                static_for<2 + D>([&](auto cc) { fold(cc, V[decltype(cc)::value]); });
             }
         }
 
@@ -1050,25 +780,21 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
     __syncthreads(); // red[] may be reused by the next tile
 }
 
-// Waves per SIMD the register allocation must allow.  The FP32 d = 10
-// kernels want 270-300 registers a lane at their natural schedule (one wave
-// per SIMD, so nothing hides the matrix-core and LDS latencies of the
-// per-path work); held to two waves (256 registers) they spill 48-264 bytes
-// a lane, stored once per workgroup and reloaded per path, outside the
-// Euler loop, and run 15-28% faster (measured for both volatility kinds,
-// eta = 2, 3 and the hyperbolic set).  d = 5 in FP32 fits three waves (at
-// most 168 registers with the accumulators) with no spill; left to itself
-// the compiler schedules more Philox blocks in flight and drops to two.
-// d = 5 in FP64 wants a little over 256 with the accumulators (one wave);
-// at two it fits (local volatility) or spills about 110 bytes a lane
-// outside the Euler loop (constant volatility), and runs 30% faster.  So
-// does d = 2 in FP64 (eta = 5 wants over 256 registers; at two waves it
-// spills 28 bytes a lane and runs 29% faster).
+// Waves per SIMD the register allocation must allow.  The d = 10 (FP32)
+// and d = 5 (FP32 and FP64) kernels are held to three waves (168 registers
+// a lane): left to themselves they take 180-240 and run at two, and at
+// three they run 10-17% faster (d = 10 serving shape, d = 5 FP64), with
+// what does not fit (up to 340 bytes a lane) stored and reloaded once per
+// path, outside the Euler loop.  At four waves (128 registers) the FP64
+// d = 5 kernel spills inside the Euler loop and takes 60% longer, and the
+// FP32 d = 10 one gains 2%.  d = 10 in FP64 runs at two waves.  d = 2 in
+// FP64 (eta = 5 wants over 256 registers) runs at two waves, 29% faster than
+// at one.
 template <int D, typename Real>
 constexpr int min_waves()
 {
-    if (D >= 10) return sizeof(Real) == 4 ? 2 : 1;
-    if (D == 5) return sizeof(Real) == 4 ? 3 : 2;
+    if (D >= 10) return sizeof(Real) == 4 ? 3 : 2;
+    if (D == 5) return 3;
     if (D == 2) return sizeof(Real) == 4 ? 1 : 2;
     return 1;
 }
@@ -1141,9 +867,12 @@ struct TypeTag {
     using type = T;
 };
 
+// Path precisions a set is instantiated for (a bit set)
+enum PrecisionSet { kPrecF32 = 1, kPrecF64 = 2, kPrecBoth = 3 };
+
 // calls f(TypeTag<Real>, integral_constant<VOL>) for the variant at hand;
 // hipErrorInvalidValue when it is not instantiated
-template <int D, int E, bool FP64, bool DUP, typename F>
+template <int D, int E, int PREC, bool DUP, typename F>
 hipError_t dispatch_variant(bool fp32, int vol, F &&f)
 {
     auto by_vol = [&](auto rt) -> hipError_t {
@@ -1154,8 +883,11 @@ hipError_t dispatch_variant(bool fp32, int vol, F &&f)
         }
         return hipErrorInvalidValue;
     };
-    if (fp32) return by_vol(TypeTag<float>{});
-    if constexpr (FP64) return by_vol(TypeTag<double>{});
+    if (fp32) {
+        if constexpr ((PREC & kPrecF32) != 0) return by_vol(TypeTag<float>{});
+    } else {
+        if constexpr ((PREC & kPrecF64) != 0) return by_vol(TypeTag<double>{});
+    }
     return hipErrorInvalidValue;
 }
 
@@ -1174,8 +906,9 @@ int copy_index_table(int8_t *nu, int cap)
 } // namespace bsde
 
 // Defines launch_path_dD, index_table_dD, launch_batch_dD,
-// batch_occupancy_dD and has_variant_dD for the (eta, q-norm, FP64, Dupire)
-// sets listed by SETS(X) as X(E, Q, FP64, DUP), with q = Q / 10.
+// batch_occupancy_dD and has_variant_dD for the (eta, q-norm, precisions,
+// Dupire) sets listed by SETS(X) as X(E, Q, PREC, DUP), with q = Q / 10 and
+// PREC a PrecisionSet.
 // Path kernels of the kernel operator (Section 3.2) for d = D: FP32 and
 // FP64 paths, constant and bump volatility; table = rows {z, y}
 #define BSDE_DEFINE_KERNEL_OP(D)                                               \
@@ -1185,7 +918,7 @@ int copy_index_table(int8_t *nu, int cap)
                                        double *partial, hipEvent_t ev0,        \
                                        hipEvent_t ev1)                         \
     {                                                                          \
-        return dispatch_variant<D, 1, true, false>(                            \
+        return dispatch_variant<D, 1, kPrecBoth, false>(                            \
             fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
                 using R = typename decltype(rt)::type;                         \
                 hipExtLaunchKernelGGL(                                         \
@@ -1240,9 +973,9 @@ int copy_index_table(int8_t *nu, int cap)
         return false;                                                          \
     }
 
-#define BSDE_PATH_SET(E, Q, F64, DUP)                                          \
+#define BSDE_PATH_SET(E, Q, PREC, DUP)                                          \
     if (eta == E && q10 == Q)                                                  \
-        return dispatch_variant<D_, E, F64, DUP>(                              \
+        return dispatch_variant<D_, E, PREC, DUP>(                              \
             fp32, prm.vol_kind, [&](auto rt, auto vt) -> hipError_t {          \
                 using R = typename decltype(rt)::type;                         \
                 /* ev0/ev1 (may be null) take the start and end times   \
@@ -1253,11 +986,11 @@ int copy_index_table(int8_t *nu, int cap)
                     (const R *)gamma, partial);                                \
                 return hipGetLastError();                                      \
             });
-#define BSDE_TABLE_SET(E, Q, F64, DUP)                                         \
+#define BSDE_TABLE_SET(E, Q, PREC, DUP)                                         \
     if (eta == E && q10 == Q) return copy_index_table<D_, E, Q>(nu, cap);
-#define BSDE_BATCH_SET(E, Q, F64, DUP)                                         \
+#define BSDE_BATCH_SET(E, Q, PREC, DUP)                                         \
     if (eta == E && q10 == Q)                                                  \
-        return dispatch_variant<D_, E, F64, DUP>(                              \
+        return dispatch_variant<D_, E, PREC, DUP>(                              \
             fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
                 using R = typename decltype(rt)::type;                         \
                 hipLaunchKernelGGL(                                            \
@@ -1266,17 +999,17 @@ int copy_index_table(int8_t *nu, int cap)
                     tile_begin, counter);                                      \
                 return hipGetLastError();                                      \
             });
-#define BSDE_OCC_SET(E, Q, F64, DUP)                                           \
+#define BSDE_OCC_SET(E, Q, PREC, DUP)                                           \
     if (eta == E && q10 == Q)                                                  \
-        (void)dispatch_variant<D_, E, F64, DUP>(                               \
+        (void)dispatch_variant<D_, E, PREC, DUP>(                               \
             fp32, vol, [&](auto rt, auto vt) -> hipError_t {                   \
                 using R = typename decltype(rt)::type;                         \
                 return hipOccupancyMaxActiveBlocksPerMultiprocessor(           \
                     &nb, batch_path_kernel<D_, E, R, decltype(vt)::value, Q>,  \
                     kBlock, 0);                                                \
             });
-#define BSDE_HAS_SET(E, Q, F64, DUP)                                           \
+#define BSDE_HAS_SET(E, Q, PREC, DUP)                                           \
     if (eta == E && q10 == Q)                                                  \
-        return dispatch_variant<D_, E, F64, DUP>(                              \
+        return dispatch_variant<D_, E, PREC, DUP>(                              \
                    fp32, vol, [](auto, auto) { return hipSuccess; }) ==        \
                hipSuccess;

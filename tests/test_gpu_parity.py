@@ -44,7 +44,7 @@ CASES = {
                        bump_a=0.25, rho=0.2, payoff="put_geom", S0=100.0,
                        grid="random", n_t=3, n_x=40, eta=2, M=100, N=4,
                        K_it=2, omega=100.0),
-    # d = 10 (FP32 paths only): matrix-core contraction, eta = 2 and 3
+    # d = 10, eta = 2 and 3 (FP32 and FP64 paths)
     "d10_eta2": problem(d=10, vol_kind="bump", vol_level=[0.15 + 0.02 * j for j in range(10)],
                         bump_a=0.25, rho=0.2, payoff="put", S0=100.0,
                         grid="random", n_t=3, n_x=70, eta=2, M=80, N=4,
@@ -91,7 +91,7 @@ CASES = {
                               grid="random", n_t=6, n_x=300, eta=5, q=0.6,
                               M=16, N=3, K_it=2, omega=1.0),
 }
-FP32_ONLY = {"d10_eta2", "d10_eta3", "d10_hyperbolic"}
+FP32_ONLY = {"d10_hyperbolic"}
 
 
 @pytest.fixture(scope="module")
@@ -118,8 +118,9 @@ def test_parity_with_oracle(name, prec, oracle_results):
     cfg = dict(CASES[name], precision=prec)
     print("parity case", name, prec, flush=True)
     if name in FP32_ONLY and prec == "fp64":
-        # d = 10 has FP32 path kernels only: the library refuses FP64 paths
-        # with BSDE_EUNSUPPORTED rather than running anything else
+        # the hyperbolic sets of d = 10 have FP32 path kernels only: the
+        # library refuses FP64 paths with BSDE_EUNSUPPORTED rather than
+        # running anything else
         with pytest.raises(bsde.BsdeError) as err:
             run_gpu(cfg)
         assert err.value.status == 6, err.value
