@@ -62,12 +62,50 @@ GATE = {"fp64": (1e-4, 1e-4), "fp32": (5e-4, 5e-3)}
 # ---------------------------------------------------------------------------
 # Algorithmic work of the path kernel
 # ---------------------------------------------------------------------------
-def flop_per_path_step(d, p, C, N, vol="bump", payoff="put_geom"):
+def index_set(d, eta, q=1.0):
+    """The multi-indices (t, x_1, .., x_d) of the basis: total degree <= eta
+    and, for q < 1, sum_v nu_v^q <= eta^q (Section 4.2, eq. hyper_set)."""
+    out = []
+
+    def rec(prefix, left):
+        if len(prefix) == d + 1:
+            if q >= 1.0 or sum(v ** q for v in prefix) <= eta ** q * (1 + 1e-12):
+                out.append(tuple(prefix))
+            return
+        for a in range(left + 1):
+            rec(prefix + [a], left - a)
+
+    rec([], eta)
+    return out
+
+
+def live_channel_entries(d, eta, q=1.0):
+    """(p, entries of the channel table the path kernel multiplies): every
+    basis function for u; for a first derivative in variate v the functions
+    nu with nu + e_v in the set, for a second derivative in x_j, x_k those
+    with nu + e_j + e_k in it (differentiation lowers a Chebyshev factor's
+    degree, so the other rows of those channels are zero)."""
+    S = set(index_set(d, eta, q))
+
+    def has(nu, *vs):
+        m = list(nu)
+        for v in vs:
+            m[v] += 1
+        return tuple(m) in S
+
+    first = sum(has(nu, v) for nu in S for v in range(d + 1))
+    second = sum(has(nu, 1 + j, 1 + k) for nu in S for j in range(d)
+                 for k in range(j, d))
+    return len(S), len(S) + first + second
+
+
+def flop_per_path_step(d, p, C, live, N, vol="bump", payoff="put_geom"):
     """Algorithmic floating-point operations per Euler path-step of the path
     kernel (FMA = 2, add or multiply = 1, exp/log/sqrt/sin/cos = 1 each;
     integer Philox work and compares 0), counted from the kernel's
     arithmetic.  Returns (total, of which the basis-row x channel-table
-    contraction).
+    contraction).  live is the number of entries of the p x C channel table
+    the contraction multiplies (live_channel_entries; p C for a dense one).
 
     Per asset and Euler step:
       one normal, half a Box-Muller pair: two uniform maps (FMA each), log,
@@ -82,7 +120,7 @@ def flop_per_path_step(d, p, C, N, vol="bump", payoff="put_geom"):
       volatility (4), frozen drift (2), X_tau (8), bridge correlation (4);
       Chebyshev values: (2 d + 1) variates x (map 2 + 3 per recurrence);
       basis rows: one product per function and row, 2 (p - 1);
-      contraction: 2 p C (at tau) + 2 p (u at T);
+      contraction: 2 live (at tau) + 2 p (u at T);
       generator: 2 (C - 1) + d (d + 1) (covariances);
       payoffs at tau and T; driver, path term and FP64 sums: 12."""
     eta_rec = 3
@@ -99,7 +137,7 @@ def flop_per_path_step(d, p, C, N, vol="bump", payoff="put_geom"):
         eta += 1
     cheb = (2 * d + 1) * (2 + eta_rec * max(0, eta - 1))
     basis = 2 * (p - 1)
-    contraction = 2.0 * p * C
+    contraction = 2.0 * live
     uT = 2.0 * p
     gen = 2 * (C - 1) + d * (d + 1)
     pay = 2 * ((2 * d + 3) if payoff in ("put", "call") else (d + 3))
@@ -146,21 +184,22 @@ ISSUE_CYCLES_D1_FP32 = {
 # profiles/copy_calibration.md).  Valid only for the kernel sources whose
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
-TRAFFIC = {"sources_sha16": "0801638cf8ff6a34", "tiling": [4, 1],
-           "fetch_kib": 15780.0, "write_kib": 5120.0,
+TRAFFIC = {"sources_sha16": "be075b9fe4249ea8", "tiling": [4, 1],
+           "fetch_kib": 27960.0, "write_kib": 5177000.0,
            "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 # Counter-derived figures of the same kernel (same profile, same guard):
 # VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
-COUNTERS = {"sources_sha16": "0801638cf8ff6a34", "tiling": [4, 1],
-            "valu_issue": 0.719, "mfma_busy": 0.117,
-            "fp64_vector_flop_per_launch": 7.80e11,
-            "fp64_matrix_flop_per_launch": 2.58e11,
+COUNTERS = {"sources_sha16": "be075b9fe4249ea8", "tiling": [4, 1],
+            "valu_issue": 0.914, "mfma_busy": 0.0,
+            "fp64_vector_flop_per_launch": 8.09e11,
+            "fp64_matrix_flop_per_launch": 0.0,
             "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 KERNEL_SOURCES = ("paper_1102_4666_amd/csrc/bsde_path.h",
                   "paper_1102_4666_amd/csrc/bsde_common.h",
+                  "paper_1102_4666_amd/csrc/bsde_f64_math.h",
                   "paper_1102_4666_amd/csrc/bsde_inst_d5.hip")
 
 
@@ -216,10 +255,7 @@ HEADLINE_NAME = ("d=5 American geometric-basket put, penalised BSDE (penalty 1),
 FORCED_TILING = None
 
 
-def steps_of(cfg, n=None):
-    if n is None:
-        import oracle
-        n = oracle.sizes(cfg)[0]
+def steps_of(cfg, n):
     return n * cfg["M"] * cfg["N"] * cfg["K_it"]
 
 
@@ -282,11 +318,10 @@ def timed_jobs(cfg, steps, warmup, stream, tune=True):
 
 
 def roofline(cfg, n, path_ms, tiling, precision):
-    import oracle
-    p = oracle.sizes(cfg)[1]
     d = cfg["d"]
     C = 2 + d + d * (d + 1) // 2
-    fl, fl_mfma = flop_per_path_step(d, p, C, cfg["N"], cfg.get("vol_kind", "bump"),
+    p, live = live_channel_entries(d, cfg["eta"], cfg.get("q", 1.0))
+    fl, fl_mfma = flop_per_path_step(d, p, C, live, cfg["N"], cfg.get("vol_kind", "bump"),
                                      cfg.get("payoff", "put"))
     launch_steps = n * cfg["M"] * cfg["N"]
     t = path_ms * 1e-3
@@ -300,6 +335,7 @@ def roofline(cfg, n, path_ms, tiling, precision):
             "launch_ms": path_ms, "path_steps_per_launch": launch_steps,
             "flop_per_path_step": fl,
             "of_which_contraction_flop_per_path_step": fl_mfma,
+            "channel_table_entries": {"live": live, "dense": p * C},
             "target_frac": 0.5,
             "counters": counter_figures(tiling, path_ms) if precision == "fp64" else None}
 
@@ -657,8 +693,7 @@ def d10_sparsity_study(seeds=8):
                 p = P.p if q == 1.0 else None
             ms.append(1e3 * (time.perf_counter() - t))
         if p is None:
-            import oracle
-            p = len(oracle.index_set(11, eta, q))
+            p = len(index_set(10, eta, q))
         m, sd = float(np.mean(prices)), float(np.std(prices, ddof=1))
         out.append({"eta": eta, "q": q, "p": p, "mean_price": m, "seed_std": sd,
                     "std_of_mean": sd / np.sqrt(seeds), "bias": m - D10_BENCHMARK,

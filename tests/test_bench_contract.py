@@ -38,20 +38,34 @@ def test_issue_cycle_model_uses_measured_costs():
 
 def test_flop_count_of_the_path_kernel():
     b = _bench()
-    # d = 1, eta = 4 (p = 15, C = 4), N = 50, arithmetic put: 16 FLOP per
-    # asset-step plus the per-path work over 50 steps
-    tot, mf = b.flop_per_path_step(1, 15, 4, 50, "bump", "put")
-    per_path = 4 + 24 + 24 + 3 * (2 + 3 * 3) + 28 + 120 + 30 + 6 + 2 + 10 + 12
+    # index sets: binom(d + 1 + eta, eta) functions at total degree; the
+    # paper's d = 10 hyperbolic set eta = 5, q = 0.6 has 221
+    assert [len(b.index_set(d, e)) for d, e in ((1, 4), (5, 3), (10, 3))] == [15, 84, 364]
+    assert len(b.index_set(10, 5, 0.6)) == 221
+    # live entries of the channel table: all p for u, then for each of the
+    # d + 1 first derivatives the functions one degree lower (binom(d + eta,
+    # eta - 1) of them) and for each of the d (d + 1) / 2 second
+    # derivatives those two degrees lower (binom(d - 1 + eta, eta - 2))
+    from math import comb
+    for d, e in ((1, 4), (2, 5), (5, 3), (10, 3)):
+        p, live = b.live_channel_entries(d, e)
+        assert live == p + (d + 1) * comb(d + e, e - 1) + d * (d + 1) // 2 * comb(d - 1 + e, e - 2)
+    assert b.live_channel_entries(5, 3) == (84, 357)
+    assert b.live_channel_entries(10, 3) == (364, 1882)
+    # d = 1, eta = 4 (p = 15, C = 4, 41 live entries), N = 50, arithmetic
+    # put: 16 FLOP per asset-step plus the per-path work over 50 steps
+    tot, mf = b.flop_per_path_step(1, 15, 4, 41, 50, "bump", "put")
+    per_path = 4 + 24 + 24 + 3 * (2 + 3 * 3) + 28 + 2 * 41 + 30 + 6 + 2 + 10 + 12
     assert tot == pytest.approx(16 + per_path / 50)
-    assert mf == pytest.approx(120 / 50)
+    assert mf == pytest.approx(2 * 41 / 50)
     # d = 5, eta = 3 (p = 84, C = 22), geometric put: 20 per asset-step
-    tot, mf = b.flop_per_path_step(5, 84, 22, 50, "bump", "put_geom")
-    assert mf == pytest.approx(2 * 84 * 22 / 50)
-    assert 180 < tot < 195
+    tot, mf = b.flop_per_path_step(5, 84, 22, 357, 50, "bump", "put_geom")
+    assert mf == pytest.approx(2 * 357 / 50)
+    assert 120 < tot < 135
     # d = 10, eta = 3 (p = 364, C = 67)
-    tot, mf = b.flop_per_path_step(10, 364, 67, 50, "bump", "put")
-    assert mf == pytest.approx(2 * 364 * 67 / 50)
-    assert 1200 < tot < 1250
+    tot, mf = b.flop_per_path_step(10, 364, 67, 1882, 50, "bump", "put")
+    assert mf == pytest.approx(2 * 1882 / 50)
+    assert 310 < tot < 330
 
 
 def test_traffic_is_null_unless_measured_for_these_sources():
@@ -77,7 +91,7 @@ def test_counter_figures_follow_the_recorded_profile():
     try:
         b.COUNTERS = dict(saved, sources_sha16=b.kernel_sources_sha16(), tiling=[4, 1])
         c = b.counter_figures([4, 1], 36.9)
-        assert 0 < c["valu_issue"] <= 1 and 0 < c["mfma_busy"] <= 1
+        assert 0 < c["valu_issue"] <= 1 and 0 <= c["mfma_busy"] <= 1
         assert c["fp64_vector_tflops_issued"] == pytest.approx(
             saved["fp64_vector_flop_per_launch"] / 36.9e-3 / 1e12)
         assert b.counter_figures([2, 2], 36.9) is None
