@@ -171,11 +171,12 @@ ISSUE_CYCLES_D1_FP32 = {
     # the compare that selects step j*
     "record": ISSUE_COST["intv"],
     # per path over N = 50: U and bridge Philox blocks, one Box-Muller pair,
-    # 156 other FP32 operations
+    # 137 other FP32 operations (56 of them the products with the 41 live
+    # channel-table entries and u at T)
     "per_path": (2 * (16 * ISSUE_COST["four"] + 3 * ISSUE_COST["four"] +
                       15 * ISSUE_COST["intv"]) +
                  2 * (2 * ISSUE_COST["four"] + 4 * ISSUE_COST["trans"] +
-                      4 * ISSUE_COST["f32v"]) + 156 * ISSUE_COST["f32v"]) / 50.0,
+                      4 * ISSUE_COST["f32v"]) + 137 * ISSUE_COST["f32v"]) / 50.0,
 }
 
 # HBM traffic of one launch of the headline path kernel, from rocprofv3
@@ -388,16 +389,20 @@ def accuracy_gate(stream):
 def batched_vs_fp64(stream, reps=2):
     """The batched FP32-path form against the plain FP64 per-problem form on
     the same GPU at penalty 1, where both must pass the accuracy gate: the
-    d = 1, 2 and 5 workloads solved in one bsde_solve_batch call (one
-    persistent path launch per Picard step and signature, the schedule
-    captured as a hipGraph), against the same three solved one after the
-    other by bsde_solve in FP64."""
+    d = 1, 2 and 5 workloads and the d = 10 request shape of the serving mix
+    solved in one bsde_solve_batch call (one persistent path launch per
+    Picard step and signature, the signatures as parallel branches, the
+    schedule captured as a hipGraph), against the same four solved one after
+    the other by bsde_solve in FP64.  The d <= 5 results are gated against
+    the stored oracle results; the d = 10 shape (too large for the oracle as
+    a whole) against the FP64 per-problem result, whose per-point parity
+    with the oracle tests/test_gpu_d10.py checks."""
     import torch
 
     import paper_1102_4666_amd as bsde
     import workloads
-    names = ("amer_put_d1", "amer_basket_d2", "geo_basket_d5")
-    gold = {nm: _golden(nm + "_w1") for nm in names}
+    names = ("amer_put_d1", "amer_basket_d2", "geo_basket_d5", "put_basket_d10")
+    gold = {nm: _golden(nm + "_w1") for nm in names[:3]}
 
     def run(prec, batched):
         probs = [bsde.Problem(getattr(workloads, nm)(omega=1.0, precision=prec))
@@ -412,29 +417,40 @@ def batched_vs_fp64(stream, reps=2):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         steps = sum(P.n * P.cfg["M"] * P.cfg["N"] * P.cfg["K_it"] for P in probs)
-        err = {}
+        res = {}
         for nm, P in zip(names, probs):
             price, delta = P.price_delta()
-            g = gold[nm]
-            if g is not None:
-                err[nm] = gate(prec, price[0], delta[0], g["price"][-1],
-                               g["delta"][-1], P.cfg["K"], 1.0)
+            res[nm] = (price[0], delta[0], P.cfg["K"])
             P.close()
-        return dt, steps, err
+        return dt, steps, res
 
-    out = {}
+    out, results = {}, {}
     for prec, batched, key in (("fp32", True, "batched_fp32_paths"),
                                ("fp64", False, "per_problem_fp64")):
         run(prec, batched)  # warm-up (kernel load, tuning table)
         best = None
         for _ in range(reps):
-            dt, steps, err = run(prec, batched)
+            dt, steps, res = run(prec, batched)
             best = dt if best is None else min(best, dt)
+        results[prec] = res
         out[key] = {"seconds": best, "path_steps": steps,
-                    "path_steps_per_s": steps / best, "accuracy": err,
-                    "all_gates_pass": all(e["gate_pass"] for e in err.values())}
+                    "path_steps_per_s": steps / best}
+    for prec, key in (("fp32", "batched_fp32_paths"), ("fp64", "per_problem_fp64")):
+        err = {}
+        for nm in names:
+            price, delta, K = results[prec][nm]
+            g = gold.get(nm)
+            if g is not None:
+                err[nm] = gate(prec, price, delta, g["price"][-1], g["delta"][-1], K, 1.0)
+            elif prec == "fp32":
+                p64, d64, _ = results["fp64"][nm]
+                err[nm] = dict(gate("fp32", price, delta, p64, d64, K, 1.0),
+                               reference="FP64 per-problem result")
+        out[key]["accuracy"] = err
+        out[key]["all_gates_pass"] = all(e["gate_pass"] for e in err.values())
     out["problems"] = ("d=1 (128x16 grid, M=4000), d=2 (32^2x16, M=2000), "
-                       "d=5 (4096x10, M=1000); N=50, penalty 1")
+                       "d=5 (4096x10, M=1000), d=10 (8192x10, eta=3, M=500); "
+                       "N=50, 10 or 8 Picard iterations, penalty 1")
     out["speedup"] = out["per_problem_fp64"]["seconds"] / \
         out["batched_fp32_paths"]["seconds"]
     return out

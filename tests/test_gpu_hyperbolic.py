@@ -10,11 +10,20 @@ FP64 oracle.
    total-degree kernel with the coefficients outside the set held at zero:
    the same comparison, in FP64 and FP32 paths.
 
+3. The largest set (q = 0.7, p = 386) at the shape of the paper's d = 10
+   runs (n = 1000 points, M = 30,000, N = 10) with the narrow domain of
+   those runs (one standard deviation: many paths leave it, where Chebyshev
+   values of degree 5 grow large), iteration 1 from the least-squares fit of
+   the payoff at the points -- the polynomial handed to the oracle as its
+   monomial coefficients and to the library as point values -- on 16
+   sampled points.
+
 Tolerances are those of every parity test: corrections within
 1e-8 / 2e-3 (1 + |c| + sd) for FP64 / FP32 paths (sd the oracle's sample
 standard deviation of the path terms at the point), |d price| <= 1e-4 K /
 5e-4 K, |d delta| <= 1e-4 / 5e-3."""
 import math
+import multiprocessing as mp
 
 import numpy as np
 import pytest
@@ -76,3 +85,34 @@ def test_hyperbolic_set_on_the_total_degree_kernel(prec):
     # coefficients outside the set held at zero
     assert p == 35
     assert np.count_nonzero(alpha) == len(oracle.index_set(3, 4, 0.6)) == 16
+
+
+def _corrections_at(args):
+    cfg, alpha, k, i = args
+    c, v = oracle.corrections(cfg, alpha, k, i, i + 1)
+    return float(c[0]), float(v[0])
+
+
+def test_d10_q07_study_shape_iteration1_sampled():
+    from workloads import call_basket_d10_hyperbolic
+    cfg = call_basket_d10_hyperbolic()
+    cfg.update(q=0.7, redraw=0, K_it=2)
+    n, p = oracle.sizes(cfg)
+    assert p == 386
+    pts = oracle.points(cfg)
+    y = np.array([oracle.payoff(cfg, pts[i, 1:]) for i in range(n)])
+    alpha = oracle.fit(cfg, y)
+    print("d=10 eta=5 q=0.7 at the study shape, iteration 1", flush=True)
+    with bsde.Problem(cfg) as P:
+        P.fit_values(y, 1)
+        P.solve()
+        c1 = P.corrections(1)[0]
+    idx = np.sort(np.random.default_rng(8).choice(n, 16, replace=False))
+    with mp.get_context("fork").Pool(8) as pool:
+        ref = pool.map(_corrections_at, [(cfg, alpha, 1, int(i)) for i in idx])
+    worst = 0.0
+    for i, (c, v) in zip(idx, ref):
+        err = abs(c1[i] - c) / (1.0 + abs(c) + math.sqrt(max(v, 0.0)))
+        worst = max(worst, err)
+        assert err <= TOL["fp32"]["c"], (int(i), c1[i], c, err)
+    print("  16 sampled points, max scaled error %.3g" % worst, flush=True)

@@ -125,6 +125,17 @@ def call_basket_d10_hyperbolic(precision: str = "fp32") -> dict:
                    width=1.0, M=30000, precision=precision, seed=0)
 
 
+def put_basket_d10(omega: float = 1.0, precision: str = "fp32", M: int = 500) -> dict:
+    """The d = 10 request shape of the serving mix: arithmetic put on 10
+    assets, bump local vol with levels U[0.15,0.35], rho = 0.2, 8192 random
+    spatial points x 10 times, total degree 3 (p = 364), N = 50, 10 Picard
+    iterations, M = 500."""
+    return problem(d=10, vol_kind="bump", vol_level=vol_levels(10, 0),
+                   bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, S0=100.0,
+                   T=1.0, payoff="put", grid="random", n_t=10, n_x=8192, eta=3,
+                   N=50, K_it=10, M=M, omega=omega, precision=precision)
+
+
 def serving_request(idx: int, rng: np.random.Generator,
                     dims=(1, 2, 5, 10)) -> dict:
     """One request of the serving mix: d drawn from dims, strike U[80,120],
@@ -142,10 +153,7 @@ def serving_request(idx: int, rng: np.random.Generator,
     elif d == 5:
         base = geo_basket_d5()
     else:
-        base = problem(d=10, vol_kind="bump", vol_level=vol_levels(10, 0),
-                       bump_a=0.25, bump_c=100.0, rho=0.2, r=0.05, S0=100.0,
-                       T=1.0, payoff="put", grid="random", n_t=10,
-                       n_x=8192, eta=3, N=50, K_it=10)
+        base = put_basket_d10()
         M = 500   # the d = 10 request shape of the mix is stated at M = 500
     cfg = copy.deepcopy(base)
     cfg.update(K=K, M=M, omega=(1.0 if american else 0.0), seed=1 + idx,
@@ -155,4 +163,4 @@ def serving_request(idx: int, rng: np.random.Generator,
 
 WORKLOADS = {"eur_put_d1": eur_put_d1, "amer_put_d1": amer_put_d1,
              "amer_basket_d2": amer_basket_d2, "geo_basket_d5": geo_basket_d5,
-             "eur_put_d1_kernel": eur_put_d1_kernel}
+             "eur_put_d1_kernel": eur_put_d1_kernel, "put_basket_d10": put_basket_d10}
