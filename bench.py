@@ -185,14 +185,14 @@ ISSUE_CYCLES_D1_FP32 = {
 # profiles/copy_calibration.md).  Valid only for the kernel sources whose
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
-TRAFFIC = {"sources_sha16": "be075b9fe4249ea8", "tiling": [4, 1],
+TRAFFIC = {"sources_sha16": "3d81224559807f60", "tiling": [4, 1],
            "fetch_kib": 27960.0, "write_kib": 5177000.0,
            "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
 # Counter-derived figures of the same kernel (same profile, same guard):
 # VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
-COUNTERS = {"sources_sha16": "be075b9fe4249ea8", "tiling": [4, 1],
+COUNTERS = {"sources_sha16": "3d81224559807f60", "tiling": [4, 1],
             "valu_issue": 0.914, "mfma_busy": 0.0,
             "fp64_vector_flop_per_launch": 8.09e11,
             "fp64_matrix_flop_per_launch": 0.0,

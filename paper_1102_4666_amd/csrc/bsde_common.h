@@ -220,11 +220,9 @@ __host__ __device__ constexpr int num_channels(int d)
     return 2 + d + d * (d + 1) / 2;
 }
 
-// the channel table Gamma is stored as pad16(p) rows of pad16(C) entries,
-// zero outside p x C, so that 16 x 16 matrix-core tiles read it in bounds
+// the set-up's basis and Gram matrices have pad16(p) columns, zero beyond
+// p, so that 16 x 16 matrix-core tiles read them in bounds
 __host__ __device__ constexpr int pad16(int x) { return (x + 15) & ~15; }
-
-__host__ __device__ constexpr int pad32(int x) { return (x + 31) & ~31; }
 
 // The channel table the path kernels read (FP64 and FP32 alike) holds the
 // live rows of the p x C table packed (see channel_row_live) in three

@@ -103,13 +103,14 @@ static void complete(bsde_server_s *S, Request *q, int status)
 
 // Relative GPU cost of one Picard iteration of a problem: its path-steps
 // over the path-kernel rate of its dimension (path-steps/s measured on
-// MI355X with FP32 paths; FP64 paths are about 6x slower).  Used only to
-// group iterations into engine steps.
+// MI355X with FP32 paths at the benchmark workloads; FP64 paths are 3-4x
+// slower).  Used only to group iterations into engine steps and problems
+// into the light and heavy lanes.
 static double iteration_cost(const bsde_problem_s *h)
 {
-    double rate = h->d <= 1 ? 9e11 : h->d <= 2 ? 4e11 : h->d <= 3 ? 3e11
-                : h->d <= 5 ? 1.8e11 : 5e10;
-    if (h->precision != BSDE_FP32_PATHS) rate /= 6.0;
+    double rate = h->d <= 1 ? 1.6e12 : h->d <= 2 ? 7e11 : h->d <= 3 ? 5e11
+                : h->d <= 5 ? 3e11 : 1.1e11;
+    if (h->precision != BSDE_FP32_PATHS) rate /= 3.5;
     return (double)h->n * h->M * h->N / rate + 2e-5; // + launch overheads
 }
 
