@@ -185,18 +185,28 @@ ISSUE_CYCLES_D1_FP32 = {
 # profiles/copy_calibration.md).  Valid only for the kernel sources whose
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
-TRAFFIC = {"sources_sha16": "3d81224559807f60", "tiling": [4, 1],
-           "fetch_kib": 27960.0, "write_kib": 5177000.0,
-           "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
-# Counter-derived figures of the same kernel (same profile, same guard):
+TRAFFIC = [
+    {"sources_sha16": "9c20d55c9e89f3c3", "tiling": [1, 4],
+     "fetch_kib": 16810.0, "write_kib": 1754000.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+    {"sources_sha16": "9c20d55c9e89f3c3", "tiling": [4, 1],
+     "fetch_kib": 28360.0, "write_kib": 5364000.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+]
+# Counter-derived figures of the same kernel (same profiles, same guard):
 # VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
-COUNTERS = {"sources_sha16": "3d81224559807f60", "tiling": [4, 1],
-            "valu_issue": 0.914, "mfma_busy": 0.0,
-            "fp64_vector_flop_per_launch": 8.09e11,
-            "fp64_matrix_flop_per_launch": 0.0,
-            "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"}
+COUNTERS = [
+    {"sources_sha16": "9c20d55c9e89f3c3", "tiling": [1, 4],
+     "valu_issue": 0.915, "mfma_busy": 0.0,
+     "fp64_vector_flop_per_launch": 8.09e11, "fp64_matrix_flop_per_launch": 0.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+    {"sources_sha16": "9c20d55c9e89f3c3", "tiling": [4, 1],
+     "valu_issue": 0.914, "mfma_busy": 0.0,
+     "fp64_vector_flop_per_launch": 8.16e11, "fp64_matrix_flop_per_launch": 0.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+]
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 KERNEL_SOURCES = ("paper_1102_4666_amd/csrc/bsde_path.h",
                   "paper_1102_4666_amd/csrc/bsde_common.h",
@@ -212,30 +222,37 @@ def kernel_sources_sha16():
     return h.hexdigest()[:16]
 
 
-def _measured_for(rec, tiling):
-    return (rec is not None and tiling is not None and list(tiling) == list(rec["tiling"])
-            and rec["sources_sha16"] == kernel_sources_sha16())
+def _measured_for(recs, tiling):
+    """The profile record of these kernel sources at this tiling, or None."""
+    if tiling is None:
+        return None
+    for rec in recs or ():
+        if list(tiling) == list(rec["tiling"]) and \
+                rec["sources_sha16"] == kernel_sources_sha16():
+            return rec
+    return None
 
 
 def traffic_bytes(tiling):
-    if not _measured_for(TRAFFIC, tiling):
+    rec = _measured_for(TRAFFIC, tiling)
+    if rec is None:
         return None
-    return (TRAFFIC["fetch_kib"] * FETCH_FACTOR +
-            TRAFFIC["write_kib"] * WRITE_FACTOR) * 1024
+    return (rec["fetch_kib"] * FETCH_FACTOR + rec["write_kib"] * WRITE_FACTOR) * 1024
 
 
 def counter_figures(tiling, path_ms):
     """The profile's counter-derived figures when the kernel and tiling are
     the profiled ones (the FLOP rates over this run's launch time)."""
-    if not _measured_for(COUNTERS, tiling):
+    rec = _measured_for(COUNTERS, tiling)
+    if rec is None:
         return None
     t = path_ms * 1e-3
-    return {"valu_issue": COUNTERS["valu_issue"], "mfma_busy": COUNTERS["mfma_busy"],
-            "fp64_vector_tflops_issued": COUNTERS["fp64_vector_flop_per_launch"] / t / 1e12,
-            "fp64_vector_frac_issued": COUNTERS["fp64_vector_flop_per_launch"] / t /
+    return {"valu_issue": rec["valu_issue"], "mfma_busy": rec["mfma_busy"],
+            "fp64_vector_tflops_issued": rec["fp64_vector_flop_per_launch"] / t / 1e12,
+            "fp64_vector_frac_issued": rec["fp64_vector_flop_per_launch"] / t /
             FP64_VECTOR_PEAK,
-            "fp64_matrix_tflops_issued": COUNTERS["fp64_matrix_flop_per_launch"] / t / 1e12,
-            "profile": COUNTERS["profile"]}
+            "fp64_matrix_tflops_issued": rec["fp64_matrix_flop_per_launch"] / t / 1e12,
+            "profile": rec["profile"]}
 
 
 # ---------------------------------------------------------------------------

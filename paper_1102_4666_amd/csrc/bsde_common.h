@@ -464,10 +464,35 @@ struct BatchTileDesc {
     double *partial;       // n x groups x 2 sums
 };
 
+// Count, mean and sum of squared deviations of two sets of samples
+// combined into those of their union (the pairwise update of Chan, Golub and
+// LeVeque): with d = mean_b - mean_a and n = n_a + n_b,
+// mean = mean_a + d n_b / n, M2 = M2_a + M2_b + d^2 n_a n_b / n.  Both sums of
+// squares stay sums of squared deviations from a mean, so the variance does
+// not come from the difference of two large sums.
+__host__ __device__ inline void combine_moments(double &n, double &mean, double &m2,
+                                                double nb, double meanb, double m2b)
+{
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+        n = nb;
+        mean = meanb;
+        m2 = m2b;
+        return;
+    }
+    const double nt = n + nb;
+    const double d = meanb - mean;
+    const double f = nb / nt;
+    mean = __builtin_fma(d, f, mean);
+    m2 = __builtin_fma(d * d, n * f, m2 + m2b);
+    n = nt;
+}
+
 // One problem of the batched reduction / update kernels (one iteration).
 struct BatchUpdateDesc {
-    const double *partial; // n x groups x 2 sums of the path kernel
+    const double *partial; // n x groups x 2: mean and M2 of each group's paths
     int n, groups, M, p, C;
+    int ppg;               // paths per group (256 x paths per lane)
     double *c, *var;       // this iteration's slices
     const double *W;       // p x n pseudo-inverse
     double *beta;          // p

@@ -33,7 +33,7 @@ hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream
                        const PathParams &prm, const double *pts,
                        const void *gamma, double *partial,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_update(int n, int groups, int M, int p, int C,
+hipError_t launch_update(int n, int groups, int M, int ppg, int p, int C,
                          hipStream_t s, const double *partial, double *c,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
@@ -74,7 +74,7 @@ hipError_t launch_kernel_update(const PathParams &prm, int d, const double *pts,
                                 const double *yprev, const double *c, double *ynew,
                                 void *table, int fp32, hipStream_t s);
 hipError_t launch_finalize(const double *partial, int n, int groups, int M,
-                           double *c, double *var, hipStream_t s);
+                           int ppg, double *c, double *var, hipStream_t s);
 } // namespace bsde
 
 using namespace bsde;
@@ -1240,7 +1240,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
             // c^k, then y^k = u^k(points) + c^k with u^k = h[y^{k-1}]
             // (alpha row k; row 0 = 0 is u^0 = 0) into row k + 1 and the table
             double *ck = h->d_c + (size_t)k * h->n;
-            HIP_TRY(launch_finalize(h->d_partial, h->n, groups, h->M, ck,
+            HIP_TRY(launch_finalize(h->d_partial, h->n, groups, h->M, kBlock * ppl, ck,
                                     h->d_var + (size_t)k * h->n, s));
             if (per == 5) HIP_TRY(hipEventRecord(e[2], s));
             HIP_TRY(launch_kernel_update(prm, h->d, h->d_pts,
@@ -1253,7 +1253,7 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
             }
             continue;
         }
-        HIP_TRY(launch_update(h->n, groups, h->M, h->p, h->C, s, h->d_partial,
+        HIP_TRY(launch_update(h->n, groups, h->M, kBlock * ppl, h->p, h->C, s, h->d_partial,
                               h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
                               h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
                               h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
@@ -1330,12 +1330,13 @@ int num_cus()
     return cus;
 }
 
-BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, bool advance)
+BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, int ppl, bool advance)
 {
     BatchUpdateDesc u{};
     u.partial = h->d_partial;
     u.n = h->n;
     u.groups = groups;
+    u.ppg = kBlock * ppl;
     u.M = h->M;
     u.p = h->p;
     u.C = h->C;
@@ -1417,7 +1418,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                 t.partial = h->d_partial;
                 td.push_back(t);
                 begin.push_back(begin.back() + (long long)h->n * G[q]);
-                upd.push_back(update_desc(h, h->k_done + step, G[q], true));
+                upd.push_back(update_desc(h, h->k_done + step, G[q], PPL[q], true));
                 max_n = std::max(max_n, h->n);
                 max_p = std::max(max_p, h->p);
                 max_C = std::max(max_C, h->C);
@@ -1436,7 +1437,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     }
     std::vector<BatchUpdateDesc> init;
     for (int q = 0; q < count; ++q) {
-        init.push_back(update_desc(probs[q], probs[q]->k_done, G[q], false));
+        init.push_back(update_desc(probs[q], probs[q]->k_done, G[q], PPL[q], false));
         max_C_all = std::max(max_C_all, probs[q]->C);
     }
     const size_t init_off = put(init.data(), sizeof(BatchUpdateDesc) * init.size());

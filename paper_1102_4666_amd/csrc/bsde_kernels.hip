@@ -16,27 +16,30 @@
 namespace bsde {
 
 // c_i and sample variance from the per-workgroup sums (fixed order in g)
+// the groups' means and sums of squared deviations combined in group order;
+// group g holds the paths g ppg .. (g + 1) ppg - 1 below M
 __device__ __forceinline__ void finalize_point(const double *__restrict__ partial,
-                                               int i, int groups, int M,
+                                               int i, int groups, int M, int ppg,
                                                double *__restrict__ c,
                                                double *__restrict__ var)
 {
-    double s = 0.0, s2 = 0.0;
+    double n = 0.0, mean = 0.0, m2 = 0.0;
     for (int g = 0; g < groups; ++g) {
-        s += partial[2 * ((size_t)i * groups + g)];
-        s2 += partial[2 * ((size_t)i * groups + g) + 1];
+        const int ng = min(ppg, M - g * ppg);
+        if (ng <= 0) break;
+        combine_moments(n, mean, m2, (double)ng, partial[2 * ((size_t)i * groups + g)],
+                        partial[2 * ((size_t)i * groups + g) + 1]);
     }
-    const double mean = s / M;
     c[i] = mean;
-    var[i] = M > 1 ? (s2 - s * mean) / (M - 1) : 0.0;
+    var[i] = M > 1 ? m2 / (M - 1) : 0.0;
 }
 
 __global__ void finalize_kernel(const double *__restrict__ partial, int n,
-                                int groups, int M, double *__restrict__ c,
+                                int groups, int M, int ppg, double *__restrict__ c,
                                 double *__restrict__ var)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) finalize_point(partial, i, groups, M, c, var);
+    if (i < n) finalize_point(partial, i, groups, M, ppg, c, var);
 }
 
 // beta_l = sum_i W[l][i] c_i (W = R^{-1} Q', row-major p x n): lanes
@@ -116,7 +119,7 @@ __global__ void batch_finalize_kernel(const BatchUpdateDesc *__restrict__ d)
 {
     const BatchUpdateDesc &q = d[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < q.n) finalize_point(q.partial, i, q.groups, q.M, q.c, q.var);
+    if (i < q.n) finalize_point(q.partial, i, q.groups, q.M, q.ppg, q.c, q.var);
 }
 
 __global__ __launch_bounds__(256) void batch_project_kernel(
@@ -191,10 +194,10 @@ hipError_t launch_kernel_update(const PathParams &prm, int d, const double *pts,
 }
 
 hipError_t launch_finalize(const double *partial, int n, int groups, int M,
-                           double *c, double *var, hipStream_t s)
+                           int ppg, double *c, double *var, hipStream_t s)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
-                       partial, n, groups, M, c, var);
+                       partial, n, groups, M, ppg, c, var);
     return hipGetLastError();
 }
 
@@ -347,7 +350,7 @@ int batch_occupancy(int d, int eta, int q10, bool fp32, int vol)
     return 0;
 }
 
-hipError_t launch_update(int n, int groups, int M, int p, int C,
+hipError_t launch_update(int n, int groups, int M, int ppg, int p, int C,
                          hipStream_t s, const double *partial, double *c,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
@@ -355,7 +358,7 @@ hipError_t launch_update(int n, int groups, int M, int p, int C,
                          const int *cpos, hipEvent_t *ev /* 3 events or NULL */)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0,
-                       s, partial, n, groups, M, c, var);
+                       s, partial, n, groups, M, ppg, c, var);
     if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(project_kernel, dim3(p), dim3(256), 0, s, W, c, n,
                        beta);

@@ -325,7 +325,8 @@ __device__ __forceinline__ ConstAssets<Real> &reload_consts(uint64_t cbase)
 // The Monte Carlo path kernel.
 // Grid: n * groups workgroups of kBlock lanes; workgroup (i, g) runs the
 // paths m = (g * ppl + r) * kBlock + lane, r < ppl, m < M, of point i and
-// writes its FP64 sums (sum a_m, sum a_m^2) to partial[2 (i groups + g)].
+// writes the mean and the sum of squared deviations of its FP64 path terms
+// to partial[2 (i groups + g)].
 // ---------------------------------------------------------------------------
 // Gamma is read-only, uniform across the workgroup and read once per basis
 // function and channel per path: its loads must stay scalar (SGPR) loads,
@@ -425,7 +426,10 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
         __syncthreads();
     }
 
-    double sum = 0.0, sumsq = 0.0;
+    // this lane's paths: count, mean and sum of squared deviations, updated
+    // path by path (Welford), so the sum of squares never dwarfs the spread
+    int cnt = 0;
+    double mean = 0.0, m2 = 0.0;
     for (int rr = 0; rr < prm.paths_per_lane; ++rr) {
         int m = (g * prm.paths_per_lane + rr) * kBlock + (int)threadIdx.x;
         const bool valid = m < prm.M;
@@ -748,34 +752,37 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
         // penalised driver f = -r u + omega (Phi - u)_+ and the path term
         const Real f = -r * u + omega * fmax(phi_tau - u, Real(0));
         const Real a = (T - t0) * (f + gen) + terminal;
-        const double ad = valid ? (double)a : 0.0;
-        sum += ad;
-        sumsq += ad * ad;
+        const double ad = (double)a;
+        cnt += 1;
+        const double dev = ad - mean;
+        mean += dev / (double)cnt;
+        m2 = fma(dev, ad - mean, m2);
     }
 
-    // fixed-order reduction: butterfly within the wavefront, then waves in
-    // order through LDS
+    // fixed-order reduction of the lanes' moments (combine_moments):
+    // butterfly within the wavefront, then waves in order through LDS
+    double n = (double)cnt;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        sum += __shfl_xor(sum, off);
-        sumsq += __shfl_xor(sumsq, off);
+        const double nb = __shfl_xor(n, off), mb = __shfl_xor(mean, off),
+                     m2b = __shfl_xor(m2, off);
+        combine_moments(n, mean, m2, nb, mb, m2b);
     }
-    __shared__ double red[2][kBlock / 64];
+    __shared__ double red[3][kBlock / 64];
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        red[0][wave] = sum;
-        red[1][wave] = sumsq;
+        red[0][wave] = n;
+        red[1][wave] = mean;
+        red[2][wave] = m2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0, s2 = 0.0;
+        double nw = 0.0, mw = 0.0, m2w = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) {
-            s += red[0][w];
-            s2 += red[1][w];
-        }
-        out[0] = s;
-        out[1] = s2;
+        for (int w = 0; w < kBlock / 64; ++w)
+            combine_moments(nw, mw, m2w, red[0][w], red[1][w], red[2][w]);
+        out[0] = mw;
+        out[1] = m2w;
     }
     __syncthreads(); // red[] may be reused by the next tile
 }

@@ -74,31 +74,35 @@ def test_traffic_is_null_unless_measured_for_these_sources():
     try:
         b.TRAFFIC = None
         assert b.traffic_bytes([1, 4]) is None
-        b.TRAFFIC = {"sources_sha16": b.kernel_sources_sha16(), "tiling": [1, 4],
-                     "fetch_kib": 100.0, "write_kib": 50.0}
+        rec = {"sources_sha16": b.kernel_sources_sha16(), "tiling": [1, 4],
+               "fetch_kib": 100.0, "write_kib": 50.0}
+        b.TRAFFIC = [rec, dict(rec, tiling=[4, 1], fetch_kib=300.0)]
         assert b.traffic_bytes([1, 4]) == (100.0 * 2.0 + 50.0 * 1.0) * 1024
+        assert b.traffic_bytes([4, 1]) == (300.0 * 2.0 + 50.0 * 1.0) * 1024
         assert b.traffic_bytes([2, 2]) is None
-        b.TRAFFIC = dict(b.TRAFFIC, sources_sha16="0" * 16)
+        b.TRAFFIC = [dict(rec, sources_sha16="0" * 16)]
         assert b.traffic_bytes([1, 4]) is None
     finally:
         b.TRAFFIC = saved
-
 
 
 def test_counter_figures_follow_the_recorded_profile():
     b = _bench()
     saved = b.COUNTERS
     try:
-        b.COUNTERS = dict(saved, sources_sha16=b.kernel_sources_sha16(), tiling=[4, 1])
+        rec = dict(saved[0], sources_sha16=b.kernel_sources_sha16(), tiling=[4, 1])
+        b.COUNTERS = [rec]
         c = b.counter_figures([4, 1], 36.9)
         assert 0 < c["valu_issue"] <= 1 and 0 <= c["mfma_busy"] <= 1
         assert c["fp64_vector_tflops_issued"] == pytest.approx(
-            saved["fp64_vector_flop_per_launch"] / 36.9e-3 / 1e12)
+            rec["fp64_vector_flop_per_launch"] / 36.9e-3 / 1e12)
         assert b.counter_figures([2, 2], 36.9) is None
-        b.COUNTERS = dict(b.COUNTERS, sources_sha16="0" * 16)
+        b.COUNTERS = [dict(rec, sources_sha16="0" * 16)]
         assert b.counter_figures([4, 1], 36.9) is None
     finally:
         b.COUNTERS = saved
+    # the recorded profiles are of the current kernel sources
+    assert all(r["sources_sha16"] == b.kernel_sources_sha16() for r in b.COUNTERS + b.TRAFFIC)
 
 
 def test_gate_labels_the_diverging_penalty():

@@ -18,7 +18,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RES = os.path.join(ROOT, "paper_1102_4666_amd", "_build", "resources.txt")
 # kernel-name pattern -> largest spill allowed (bytes per lane)
-ALLOWED = {"path_kernelILi10ELi2Ef": 80, "path_kernelILi10ELi3Ef": 96,
+ALLOWED = {"path_kernelILi10ELi2Ef": 80, "path_kernelILi10ELi3Ef": 168,
            "path_kernelILi10ELi5Ef": 240, "path_kernelILi10ELi2Ed": 320,
            "path_kernelILi10ELi3Ed": 640, "path_kernelILi5ELi2Ed": 288,
            "path_kernelILi5ELi3Ed": 352, "path_kernelILi3ELi4Ed": 72}
