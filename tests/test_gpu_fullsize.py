@@ -157,6 +157,13 @@ def test_full_size_against_stored_oracle(name, prec):
               "absolute term %.3g)" % (k, diff[worst] / bound[worst], worst,
                                             c_cmp[k][worst], c_ref[k][worst], ls_abs))
         assert diff[worst] <= bound[worst], (k, worst, diff[worst], bound[worst])
+    big = var_ref > 1e-12 * var_ref.max()
+    vrel = np.abs(got["var"] - var_ref)[big] / var_ref[big]
+    print("  sample variances: max relative difference %.3g" % vrel.max())
+    if prec == "fp64" and not diverging:
+        # the sample variance of every point and iteration, to the
+        # single-precision rounding of the stored values
+        np.testing.assert_allclose(got["var"], var_ref, rtol=2e-6, atol=1e-12)
     pref, dref = g["price"][-1], np.array(g["delta"][-1])
     dp = abs(got["price"] - pref)
     dd = float(np.abs(got["delta"] - dref).max())

@@ -133,10 +133,12 @@ def test_parity_with_oracle(name, prec, oracle_results):
     K = cfg["K"]
     assert abs(got["price"] - ref["price"]) <= tol["price"] * K, (got["price"], ref["price"])
     np.testing.assert_allclose(got["delta"], ref["delta"], rtol=0, atol=tol["delta"])
-    # sample variances of the path terms agree to Monte Carlo rounding
+    # sample variances of the path terms: FP64 paths to rounding (both sides
+    # form them from deviations from the mean), FP32 paths to their rounding
+    # of the path terms
     np.testing.assert_allclose(got["var"], ref["var"],
-                               rtol=1e-6 if prec == "fp64" else 5e-2,
-                               atol=1e-9 if prec == "fp64" else 1e-2)
+                               rtol=1e-9 if prec == "fp64" else 5e-2,
+                               atol=1e-12 if prec == "fp64" else 1e-2)
 
 
 def test_first_iteration_fp64_matches_per_point_oracle():
