@@ -491,17 +491,19 @@ __host__ __device__ inline void combine_moments(double &n, double &mean, double 
 // One problem of the batched reduction / update kernels (one iteration).
 struct BatchUpdateDesc {
     const double *partial; // n x groups x 2: mean and M2 of each group's paths
-    int n, groups, M, p, C;
+    int n, groups, M, p;
     int ppg;               // paths per group (256 x paths per lane)
+    int nnz;               // entries of the packed channel table
     double *c, *var;       // this iteration's slices
     const double *W;       // p x n pseudo-inverse
     double *beta;          // p
     const double *alpha_in;
     double *alpha_out;
-    const double *Dmat;    // (C-1) x p x p
+    const int *rowptr;     // the channel update (sparse rows of the packed table)
+    const int *cols;
+    const double *vals;
     double *g64;
     float *g32;            // FP32 table
-    const int *cpos;       // C x p packed positions of the live rows (-1: none)
 };
 
 } // namespace bsde

@@ -33,23 +33,23 @@ hipError_t launch_path(int d, int eta, int q10, bool fp32, int blocks, hipStream
                        const PathParams &prm, const double *pts,
                        const void *gamma, double *partial,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_update(int n, int groups, int M, int ppg, int p, int C,
+hipError_t launch_update(int n, int groups, int M, int ppg, int p, int nnz,
                          hipStream_t s, const double *partial, double *c,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
-                         const double *Dmat, double *g64, float *g32,
-                         const int *cpos, hipEvent_t *ev);
-hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
-                           const double *Dmat, double *g64, float *g32,
-                           const int *cpos);
+                         const int *rowptr, const int *cols, const double *vals,
+                         double *g64, float *g32, hipEvent_t *ev);
+hipError_t launch_channels(int p, int nnz, hipStream_t s, const double *alpha,
+                           const int *rowptr, const int *cols, const double *vals,
+                           double *g64, float *g32);
 hipError_t launch_batch(int d, int eta, int q10, bool fp32, int vol, int blocks,
                         hipStream_t s, const BatchTileDesc *probs, int nprob,
                         const long long *tile_begin, unsigned int *counter);
 int batch_occupancy(int d, int eta, int q10, bool fp32, int vol);
 bool variant_exists(int d, int eta, int q10, bool fp32, int vol);
-hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
+hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_cb,
                                hipStream_t s, const BatchUpdateDesc *d);
-hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
+hipError_t launch_batch_channels(int nprob, int max_cb, hipStream_t s,
                                  const BatchUpdateDesc *d);
 hipError_t launch_reset_counters(unsigned int *c, int n, hipStream_t s);
 hipError_t launch_basis_matrix(const double *pts, int n, int ld, int dp,
@@ -668,7 +668,7 @@ static bsde_status device_pseudo_inverse(bsde_problem_s *h, const std::vector<in
 static size_t table_floats(const bsde_problem_s *h)
 {
     if (h->kop) return 0; // the kernel operator reads its point table instead
-    return table_entries(h->p, h->C);
+    return (size_t)h->n_live;
 }
 
 static void free_device(bsde_problem_s *h)
@@ -679,10 +679,10 @@ static void free_device(bsde_problem_s *h)
     pool_free(h->d_partial);
     pool_free(h->d_c);
     pool_free(h->d_var);
-    h->d_pts = h->d_W = h->d_D = h->d_alpha = h->d_beta = h->d_g64 = nullptr;
+    h->d_pts = h->d_W = h->d_vals = h->d_alpha = h->d_beta = h->d_g64 = nullptr;
     h->d_partial = h->d_c = h->d_var = nullptr;
     h->d_g32 = nullptr;
-    h->d_cpos = nullptr;
+    h->d_rowptr = h->d_cols = nullptr;
     h->d_block = nullptr;
 }
 
@@ -920,55 +920,44 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_ERANK, "fewer points than basis functions");
     }
 
-    // channel matrices: first derivatives in each variate, then products
+    // The derivative channels as sparse rows over the basis: the derivative
+    // of T_a in one variate is a combination of the T_b, b < a, a - b odd
+    // (cheb_deriv_coef), so row mu of d/dz_v holds the functions mu + k e_v of
+    // the set, k odd; rows columns ascending.  Channel 1 is d_t (2/T d/dz_0),
+    // channel 2 + j d_{x_j} (scale_j d/dz_{1+j}), then the second
+    // derivatives, the products of two of those.
     std::map<std::vector<int8_t>, int> pos;
     for (int l = 0; l < h->p; ++l)
         pos[std::vector<int8_t>(&h->nu[(size_t)l * dp], &h->nu[(size_t)l * dp] + dp)] = l;
-    const size_t pp = (size_t)h->p * h->p;
-    std::vector<double> Dv((size_t)dp * pp, 0.0); // d/dz_v, unscaled
-    for (int v = 0; v < dp; ++v)
+    using SRow = std::vector<std::pair<int, double>>;
+    std::vector<std::vector<SRow>> Dv(dp, std::vector<SRow>(h->p));
+    for (int v = 0; v < dp && !kop; ++v) {
         for (int l = 0; l < h->p; ++l) {
             std::vector<int8_t> e(&h->nu[(size_t)l * dp], &h->nu[(size_t)l * dp] + dp);
-            int a = e[v];
+            const int a = e[v];
             for (int bb = 0; bb < a; ++bb) {
-                double cf = cheb_deriv_coef(a, bb);
+                const double cf = cheb_deriv_coef(a, bb);
                 if (cf == 0.0) continue;
                 std::vector<int8_t> mu = e;
                 mu[v] = (int8_t)bb;
-                Dv[(size_t)v * pp + (size_t)pos[mu] * h->p + l] += cf;
+                Dv[v][pos[mu]].push_back({l, cf});
             }
         }
-    std::vector<double> Dm((size_t)(h->C - 1) * pp, 0.0);
+        for (auto &r : Dv[v]) std::sort(r.begin(), r.end());
+    }
     const double tfac = 2.0 / payoff->T;
-    for (size_t e = 0; e < pp; ++e) Dm[e] = tfac * Dv[e]; // channel 1: d_t
-    h->Dfirst.assign((size_t)d * pp, 0.0);
-    for (int j = 0; j < d; ++j)
-        for (size_t e = 0; e < pp; ++e) {
-            double v = b.scale[j] * Dv[(size_t)(1 + j) * pp + e];
-            Dm[(size_t)(1 + j) * pp + e] = v;
-            h->Dfirst[(size_t)j * pp + e] = v;
-        }
-    int ch = 1 + d;
-    for (int j = 0; j < d; ++j)
-        for (int k = j; k < d; ++k, ++ch) {
-            const double *A1 = &h->Dfirst[(size_t)j * pp];
-            const double *A2 = &h->Dfirst[(size_t)k * pp];
-            double *O = &Dm[(size_t)ch * pp];
-            for (int l = 0; l < h->p; ++l)
-                for (int mm = 0; mm < h->p; ++mm) {
-                    double a1 = A1[(size_t)l * h->p + mm];
-                    if (a1 == 0.0) continue;
-                    for (int c = 0; c < h->p; ++c)
-                        O[(size_t)l * h->p + c] += a1 * A2[(size_t)mm * h->p + c];
-                }
-        }
-
-    // positions of the live rows of each channel in the packed table, in
-    // the order the path kernels read it (bsde_common.h): channel 0; each
-    // second derivative over its rows; then row by row the time derivative
-    // and the gradient.  The kernel's index set is the set of rows here.
+    h->Dx.assign(kop ? 0 : d, std::vector<SRow>(h->p));
+    for (int j = 0; j < d && !kop; ++j)
+        for (int l = 0; l < h->p; ++l)
+            for (const auto &x : Dv[1 + j][l]) h->Dx[j][l].push_back({x.first, b.scale[j] * x.second});
+    // the packed channel table (bsde_common.h) as a sparse matrix over the
+    // coefficients, in the order the path kernels read it: channel 0; each
+    // second derivative over its live rows; then row by row the time
+    // derivative and the gradient.  The kernel's index set is the set of
+    // rows here.
+    std::vector<int> csr_ptr(1, 0), csr_col;
+    std::vector<double> csr_val;
     if (!kop) {
-        h->cpos.assign((size_t)h->C * h->p, -1);
         auto in_set = [&](const int *mu) {
             std::vector<int8_t> key(dp);
             for (int v = 0; v < dp; ++v) key[v] = (int8_t)mu[v];
@@ -977,20 +966,34 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         auto live = [&](int l, int c) {
             return channel_row_live<kMaxD + 1>(&h->nu[(size_t)l * dp], dp, c, in_set);
         };
-        int e = 0;
-        for (int l = 0; l < h->p; ++l) h->cpos[l] = e++;
-        for (int c = 2 + d; c < h->C; ++c)
-            for (int l = 0; l < h->p; ++l)
-                if (live(l, c)) h->cpos[(size_t)c * h->p + l] = e++;
+        auto put = [&](const SRow &r, double f) {
+            for (const auto &x : r) {
+                csr_col.push_back(x.first);
+                csr_val.push_back(f * x.second);
+            }
+            csr_ptr.push_back((int)csr_col.size());
+        };
+        for (int l = 0; l < h->p; ++l) put(SRow{{l, 1.0}}, 1.0);
+        for (int c = 2 + d; c < h->C; ++c) {
+            const int j = hess_j(d, c - 2 - d), k = hess_k(d, c - 2 - d);
+            for (int l = 0; l < h->p; ++l) {
+                if (!live(l, c)) continue;
+                // row l of (d/dx_j)(d/dx_k): sum over the middle function mm,
+                // in ascending order
+                std::map<int, double> acc;
+                for (const auto &x1 : h->Dx[j][l])
+                    for (const auto &x2 : h->Dx[k][x1.first]) acc[x2.first] += x1.second * x2.second;
+                put(SRow(acc.begin(), acc.end()), 1.0);
+            }
+        }
         for (int l = 0; l < h->p; ++l)
             for (int c = 1; c < 2 + d; ++c)
-                if (live(l, c)) h->cpos[(size_t)c * h->p + l] = e++;
+                if (live(l, c)) put(Dv[c - 1][l], c == 1 ? tfac : b.scale[c - 2]);
+        h->n_live = (int)csr_ptr.size() - 1;
     }
 
     if (kop) {
         // the coefficients of a kernel-operator problem are its point values
-        Dm.clear();
-        h->Dfirst.clear();
         h->p = h->n;
     }
 
@@ -1004,16 +1007,18 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     // block (256-byte aligned parts)
     auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t real_size = precision == BSDE_FP32_PATHS ? sizeof(float) : sizeof(double);
-    const size_t b_pts = sizeof(double) * h->pts.size(), b_D = sizeof(double) * Dm.size(),
+    const size_t b_pts = sizeof(double) * h->pts.size(),
+                 b_val = sizeof(double) * csr_val.size(),
                  b_alpha = sizeof(double) * (size_t)(h->K_it + 1) * h->p,
                  b_g64 = sizeof(double) * table_floats(h),
                  b_g32 = sizeof(float) * table_floats(h),
-                 b_cpos = sizeof(int) * h->cpos.size(),
+                 b_ptr = kop ? 0 : sizeof(int) * csr_ptr.size(),
+                 b_col = sizeof(int) * csr_col.size(),
                  b_ktab = kop ? real_size * kKernelRow * (size_t)h->n : 0;
-    const size_t o_D = al256(b_pts), o_alpha = o_D + al256(b_D),
+    const size_t o_val = al256(b_pts), o_alpha = o_val + al256(b_val),
                  o_g64 = o_alpha + al256(b_alpha), o_g32 = o_g64 + al256(b_g64),
-                 o_cpos = o_g32 + al256(b_g32), o_ktab = o_cpos + al256(b_cpos),
-                 n_block = o_ktab + al256(b_ktab);
+                 o_ptr = o_g32 + al256(b_g32), o_col = o_ptr + al256(b_ptr),
+                 o_ktab = o_col + al256(b_col), n_block = o_ktab + al256(b_ktab);
     bool ok = dalloc(&h->d_block, n_block) &&
               (kop || dalloc((void **)&h->d_W, sizeof(double) * (size_t)h->p * h->n)) &&
               dalloc((void **)&h->d_beta, sizeof(double) * h->p) &&
@@ -1029,11 +1034,12 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     {
         char *b = (char *)h->d_block;
         h->d_pts = (double *)b;
-        h->d_D = (double *)(b + o_D);
+        h->d_vals = (double *)(b + o_val);
         h->d_alpha = (double *)(b + o_alpha);
         h->d_g64 = (double *)(b + o_g64);
         h->d_g32 = (float *)(b + o_g32);
-        h->d_cpos = b_cpos ? (int *)(b + o_cpos) : nullptr;
+        h->d_rowptr = b_ptr ? (int *)(b + o_ptr) : nullptr;
+        h->d_cols = b_ptr ? (int *)(b + o_col) : nullptr;
         h->d_ktab = kop ? (void *)(b + o_ktab) : nullptr;
     }
     // the kernel operator's table: rows {z_0, .., z_d, y = 0} in the path
@@ -1056,9 +1062,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     // uploads and the set-up kernels go to a set-up stream of the library
     // (non-blocking: a problem created while another one solves does not
     // wait for it).  The block goes up in one copy from pinned staging
-    // memory: points, channel matrices and zeros for the starting
-    // coefficients and the channel tables (whose padding stays zero: the
-    // update kernels write only the p x C entries).
+    // memory: points, the channel update's sparse rows and zeros for the
+    // starting coefficients and the channel tables.
     hipStream_t us = nullptr;
     size_t pin_cap = 0;
     void *pin = n_block <= kPinnedMax ? pinned_get(n_block, &pin_cap) : nullptr;
@@ -1066,18 +1071,21 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
     if (e == hipSuccess && pin) {
         std::memset(pin, 0, n_block);
         std::memcpy(pin, h->pts.data(), b_pts);
-        if (b_D) std::memcpy((char *)pin + o_D, Dm.data(), b_D);
-        if (b_cpos) std::memcpy((char *)pin + o_cpos, h->cpos.data(), b_cpos);
+        if (b_val) std::memcpy((char *)pin + o_val, csr_val.data(), b_val);
+        if (b_ptr) std::memcpy((char *)pin + o_ptr, csr_ptr.data(), b_ptr);
+        if (b_col) std::memcpy((char *)pin + o_col, csr_col.data(), b_col);
         if (b_ktab) std::memcpy((char *)pin + o_ktab, ktab.data(), b_ktab);
         e = hipMemcpyAsync(h->d_block, pin, n_block, hipMemcpyHostToDevice, us);
     } else if (e == hipSuccess) {
         e = hipMemcpyAsync(h->d_pts, h->pts.data(), b_pts, hipMemcpyHostToDevice, us);
-        if (e == hipSuccess && b_D)
-            e = hipMemcpyAsync(h->d_D, Dm.data(), b_D, hipMemcpyHostToDevice, us);
+        if (e == hipSuccess && b_val)
+            e = hipMemcpyAsync(h->d_vals, csr_val.data(), b_val, hipMemcpyHostToDevice, us);
         if (e == hipSuccess)
-            e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, o_ktab - o_alpha, us);
-        if (e == hipSuccess && b_cpos)
-            e = hipMemcpyAsync(h->d_cpos, h->cpos.data(), b_cpos, hipMemcpyHostToDevice, us);
+            e = hipMemsetAsync((char *)h->d_block + o_alpha, 0, o_ptr - o_alpha, us);
+        if (e == hipSuccess && b_ptr)
+            e = hipMemcpyAsync(h->d_rowptr, csr_ptr.data(), b_ptr, hipMemcpyHostToDevice, us);
+        if (e == hipSuccess && b_col)
+            e = hipMemcpyAsync(h->d_cols, csr_col.data(), b_col, hipMemcpyHostToDevice, us);
         if (e == hipSuccess && b_ktab)
             e = hipMemcpyAsync(h->d_ktab, ktab.data(), b_ktab, hipMemcpyHostToDevice, us);
     }
@@ -1092,7 +1100,8 @@ bsde_status bsde_create_problem(int d, const bsde_sigma *sigma, double r,
         return fail(BSDE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     // pseudo-inverse of the basis matrix of the grid, on the device (it
-    // synchronizes the set-up stream: Dm and the points may go out of scope)
+    // synchronizes the set-up stream: the sparse rows and the points may go
+    // out of scope)
     // (the kernel operator fits nothing: only the upload to wait for)
     bsde_status pst = BSDE_OK;
     if (!kop) {
@@ -1209,8 +1218,8 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
     // channel table of the starting coefficients (the kernel operator's
     // table already holds the current point values)
     if (!h->kop)
-        HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                                h->d_D, h->d_g64, h->d_g32, h->d_cpos));
+        HIP_TRY(launch_channels(h->p, h->n_live, s, h->d_alpha + (size_t)h->k_done * h->p,
+                                h->d_rowptr, h->d_cols, h->d_vals, h->d_g64, h->d_g32));
     for (int it = 0; it < iters; ++it) {
         const int k = h->k_done + it;
         hipEvent_t *e = per ? &ev[2 + (size_t)per * it] : nullptr;
@@ -1253,12 +1262,13 @@ bsde_status bsde_solve(bsde_problem h, void *hip_stream)
             }
             continue;
         }
-        HIP_TRY(launch_update(h->n, groups, h->M, kBlock * ppl, h->p, h->C, s, h->d_partial,
-                              h->d_c + (size_t)k * h->n, h->d_var + (size_t)k * h->n,
-                              h->d_W, h->d_beta, h->d_alpha + (size_t)k * h->p,
-                              h->d_alpha + (size_t)(k + 1) * h->p, h->d_D, h->d_g64,
-                              h->d_g32, h->d_cpos,
-                              per == 5 ? e + 2 : nullptr)); // records e[2..4]
+        HIP_TRY(launch_update(h->n, groups, h->M, kBlock * ppl, h->p, h->n_live, s,
+                              h->d_partial, h->d_c + (size_t)k * h->n,
+                              h->d_var + (size_t)k * h->n, h->d_W, h->d_beta,
+                              h->d_alpha + (size_t)k * h->p,
+                              h->d_alpha + (size_t)(k + 1) * h->p, h->d_rowptr, h->d_cols,
+                              h->d_vals, h->d_g64, h->d_g32,
+                              per == 5 ? e + 2 : nullptr)); // records e[2..4] // records e[2..4]
     }
     HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipEventSynchronize(ev[1]));
@@ -1339,17 +1349,18 @@ BatchUpdateDesc update_desc(bsde_problem h, int k, int groups, int ppl, bool adv
     u.ppg = kBlock * ppl;
     u.M = h->M;
     u.p = h->p;
-    u.C = h->C;
+    u.nnz = h->n_live;
     u.c = h->d_c + (size_t)std::min(k, h->K_it - 1) * h->n;
     u.var = h->d_var + (size_t)std::min(k, h->K_it - 1) * h->n;
     u.W = h->d_W;
     u.beta = h->d_beta;
     u.alpha_in = h->d_alpha + (size_t)k * h->p;
     u.alpha_out = advance ? h->d_alpha + (size_t)(k + 1) * h->p : nullptr;
-    u.Dmat = h->d_D;
+    u.rowptr = h->d_rowptr;
+    u.cols = h->d_cols;
+    u.vals = h->d_vals;
     u.g64 = h->d_g64;
     u.g32 = h->d_g32;
-    u.cpos = h->d_cpos;
     return u;
 }
 } // namespace
@@ -1387,13 +1398,13 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         return off;
     };
     struct PathLaunch { Sig sig; size_t desc_off, begin_off; int nprob; long long tiles; int counter; };
-    struct StepPlan { std::vector<PathLaunch> paths; size_t upd_off; int nact, max_n, max_p, max_C; };
+    struct StepPlan { std::vector<PathLaunch> paths; size_t upd_off; int nact, max_n, max_p, max_cb; };
     std::vector<StepPlan> plan(S);
     int n_counters = 0;
-    int max_C_all = 0;
+    int max_cb_all = 0; // workgroups of the channel update (256 entries each)
     for (int step = 0; step < S; ++step) {
         std::vector<BatchUpdateDesc> upd;
-        int max_n = 0, max_p = 0, max_C = 0;
+        int max_n = 0, max_p = 0, max_cb = 0;
         for (auto &kv : sigs) {
             std::vector<int> act;
             for (int q : kv.second)
@@ -1421,7 +1432,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                 upd.push_back(update_desc(h, h->k_done + step, G[q], PPL[q], true));
                 max_n = std::max(max_n, h->n);
                 max_p = std::max(max_p, h->p);
-                max_C = std::max(max_C, h->C);
+                max_cb = std::max(max_cb, (h->n_live + 255) / 256);
             }
             PathLaunch pl{kv.first, put(td.data(), sizeof(BatchTileDesc) * td.size()),
                           put(begin.data(), sizeof(long long) * begin.size()),
@@ -1432,13 +1443,13 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
         plan[step].nact = (int)upd.size();
         plan[step].max_n = max_n;
         plan[step].max_p = max_p;
-        plan[step].max_C = max_C;
-        max_C_all = std::max(max_C_all, max_C);
+        plan[step].max_cb = max_cb;
+        max_cb_all = std::max(max_cb_all, max_cb);
     }
     std::vector<BatchUpdateDesc> init;
     for (int q = 0; q < count; ++q) {
         init.push_back(update_desc(probs[q], probs[q]->k_done, G[q], PPL[q], false));
-        max_C_all = std::max(max_C_all, probs[q]->C);
+        max_cb_all = std::max(max_cb_all, (probs[q]->n_live + 255) / 256);
     }
     const size_t init_off = put(init.data(), sizeof(BatchUpdateDesc) * init.size());
     const size_t ctr_off = (blob.size() + 255) & ~(size_t)255;
@@ -1483,7 +1494,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
     auto enqueue = [&]() -> hipError_t {
         hipError_t e = launch_reset_counters(counters, std::max(1, n_counters), s);
         if (e != hipSuccess) return e;
-        e = launch_batch_channels(count, max_C_all, s,
+        e = launch_batch_channels(count, max_cb_all, s,
                                   (const BatchUpdateDesc *)(dblob + init_off));
         if (e != hipSuccess) return e;
         for (int step = 0; step < S; ++step) {
@@ -1514,7 +1525,7 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                 if (e != hipSuccess) return e;
             }
             e = launch_batch_update(plan[step].nact, plan[step].max_n, plan[step].max_p,
-                                    plan[step].max_C, s,
+                                    plan[step].max_cb, s,
                                     (const BatchUpdateDesc *)(dblob + plan[step].upd_off));
             if (e != hipSuccess) return e;
         }
@@ -1544,9 +1555,9 @@ bsde_status bsde::run_batch(bsde_problem *probs, int count, hipStream_t s,
                                                  pl.counter});
             launches.insert(launches.end(), {-1, (long long)plan[step].upd_off, plan[step].nact,
                                              plan[step].max_n, plan[step].max_p,
-                                             plan[step].max_C});
+                                             plan[step].max_cb});
         }
-        launches.insert(launches.end(), {count, max_C_all, (long long)init_off, n_counters,
+        launches.insert(launches.end(), {count, max_cb_all, (long long)init_off, n_counters,
                                          (long long)(side != nullptr)});
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
@@ -1638,13 +1649,17 @@ size_t bsde::problem_device_bytes(int d, const bsde_grid *grid, int M, int K_it)
     tmp.M = M;
     int groups, ppl;
     auto_tiling(&tmp, groups, ppl);
-    // the block of points, channel matrices, coefficients and tables (one
-    // allocation, 256-byte aligned parts), then the separate buffers
+    // the block of points, the channel update's sparse rows, coefficients
+    // and tables (one allocation, 256-byte aligned parts), then the separate
+    // buffers; at most p C table entries, each row of the update at most 16
+    // non-zeros (a row of a mixed second derivative has one per pair of odd
+    // degree steps k1 + k2 <= eta: 10 at eta = 8, the most of any set built)
     auto al256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t block = al256(n * (d + 1) * 8) + al256((C - 1) * p * p * 8) +
-                         al256((size_t)(K_it + 1) * p * 8) +
-                         al256(table_entries(p, (int)C) * 8) +
-                         al256(table_entries(p, (int)C) * 4) + al256(C * p * 4);
+    const size_t entries = table_entries(p, (int)C), nonzeros = 16 * entries;
+    const size_t block = al256(n * (d + 1) * 8) + al256(nonzeros * 8) +
+                         al256((size_t)(K_it + 1) * p * 8) + al256(entries * 8) +
+                         al256(entries * 4) + al256((entries + 1) * 4) +
+                         al256(nonzeros * 4);
     const size_t sizes[] = {block, (size_t)p * n * 8, (size_t)p * 8,
                             (size_t)K_it * n * 8,
                             (size_t)K_it * n * 8,
@@ -1757,8 +1772,8 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
     }
     const int k = std::min(h->k_done, h->K_it - 1);
     if (!h->kop)
-        HIP_TRY(launch_channels(h->p, h->C, s, h->d_alpha + (size_t)h->k_done * h->p,
-                                h->d_D, h->d_g64, h->d_g32, h->d_cpos));
+        HIP_TRY(launch_channels(h->p, h->n_live, s, h->d_alpha + (size_t)h->k_done * h->p,
+                                h->d_rowptr, h->d_cols, h->d_vals, h->d_g64, h->d_g32));
     hipEvent_t e0, e1;
     HIP_TRY(event_get(&e0));
     HIP_TRY(event_get(&e1));
@@ -1939,12 +1954,11 @@ bsde_status bsde_query_price_delta(bsde_problem h, int nq, const double *t,
         }
         return BSDE_OK;
     }
-    const size_t pp = (size_t)p * p;
     std::vector<double> g((size_t)d * p, 0.0); // d_{x_j} coefficients
     for (int j = 0; j < d; ++j)
         for (int l = 0; l < p; ++l) {
             double s = 0.0;
-            for (int m = 0; m < p; ++m) s += h->Dfirst[(size_t)j * pp + (size_t)l * p + m] * alpha[m];
+            for (const auto &x : h->Dx[j][l]) s += x.second * alpha[x.first];
             g[(size_t)j * p + l] = s;
         }
     for (int qi = 0; qi < nq; ++qi) {

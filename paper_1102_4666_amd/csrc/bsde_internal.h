@@ -26,16 +26,19 @@ struct bsde_problem_s {
     std::vector<char> active;    // in the hyperbolic set
     std::vector<double> pts;     // n x (d+1)
     std::vector<double> lo, hi;
-    std::vector<double> Dfirst;  // d x p x p: d_{x_j} channel matrices
-    std::vector<int> cpos;       // C x p: entry of (l, c) in the packed table, or -1
+    // d x p sparse rows (column, value) of d/dx_j on the basis, columns ascending
+    std::vector<std::vector<std::vector<std::pair<int, double>>>> Dx;
+    int n_live = 0;              // entries of the packed channel table
     // device
-    double *d_pts = nullptr, *d_W = nullptr, *d_D = nullptr,
+    double *d_pts = nullptr, *d_W = nullptr, *d_vals = nullptr,
            *d_alpha = nullptr, *d_beta = nullptr, *d_g64 = nullptr,
            *d_partial = nullptr, *d_c = nullptr, *d_var = nullptr;
     float *d_g32 = nullptr;
-    int *d_cpos = nullptr; // C x p packed positions of the channel table's live rows
-    // d_pts, d_D, d_alpha, d_g64, d_g32, d_cpos and d_ktab live in this one
-    // allocation
+    // the channel update as a sparse matrix over the packed table: entry e
+    // is sum_k vals[k] alpha[cols[k]], k in rowptr[e] .. rowptr[e+1]-1
+    int *d_rowptr = nullptr, *d_cols = nullptr;
+    // d_pts, d_vals, d_alpha, d_g64, d_g32, d_rowptr, d_cols and d_ktab live in
+    // this one allocation
     void *d_block = nullptr;
     // kernel operator of Section 3.2 (kop): bandwidth and the path kernel's
     // table of rows {z_0, .., z_d, y} (FP32 or FP64 as the paths); d_alpha

@@ -69,46 +69,39 @@ __global__ __launch_bounds__(256) void project_kernel(
 
 constexpr int kMaxP = 512;
 
-// channel c: Gamma[l][c] = sum_m D_c[l][m] a_m with a = alpha_in + beta
-// (channel 0 is the identity and also stores a as the next coefficients),
-// in FP64 and FP32, each live row l to entry cpos[c p + l] of the packed
-// table (layout in bsde_common.h).
-__device__ __forceinline__ void channel_col(
+// Entry e of the packed channel table (layout in bsde_common.h):
+// Gamma_e = sum_k vals[k] a[cols[k]], k in rowptr[e] .. rowptr[e+1]-1, with
+// a = alpha_in + beta; the sparse rows are those of the derivative channels
+// D_c alpha (channel 0, the first p entries, is a itself and also stores a
+// as the next coefficients).  FP64 and FP32 copies.
+__device__ __forceinline__ void channel_entries(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
-    double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, int c, double *__restrict__ g64, float *__restrict__ g32,
-    const int *__restrict__ cpos)
+    double *__restrict__ alpha_out, const int *__restrict__ rowptr,
+    const int *__restrict__ cols, const double *__restrict__ vals, int p,
+    int nnz, int blk, double *__restrict__ g64, float *__restrict__ g32)
 {
     __shared__ double a[kMaxP];
     for (int m = threadIdx.x; m < p; m += 256)
         a[m] = alpha_in[m] + (beta ? beta[m] : 0.0);
     __syncthreads();
-    for (int l = threadIdx.x; l < p; l += 256) {
-        if (c == 0 && alpha_out) alpha_out[l] = a[l];
-        const int e = cpos[(size_t)c * p + l];
-        if (e < 0) continue;
-        double v;
-        if (c == 0) {
-            v = a[l];
-        } else {
-            const double *drow = Dmat + ((size_t)(c - 1) * p + l) * p;
-            v = 0.0;
-            for (int m = 0; m < p; ++m) v += drow[m] * a[m];
-        }
-        g64[e] = v;
-        g32[e] = (float)v;
-    }
+    const int e = blk * 256 + (int)threadIdx.x;
+    if (e >= nnz) return;
+    if (alpha_out && e < p) alpha_out[e] = a[e];
+    double v = 0.0;
+    for (int k = rowptr[e]; k < rowptr[e + 1]; ++k) v += vals[k] * a[cols[k]];
+    g64[e] = v;
+    g32[e] = (float)v;
 }
 
-// one workgroup per channel
+// 256 entries per workgroup
 __global__ __launch_bounds__(256) void channel_kernel(
     const double *__restrict__ alpha_in, const double *__restrict__ beta,
-    double *__restrict__ alpha_out, const double *__restrict__ Dmat, int p,
-    int C, double *__restrict__ g64, float *__restrict__ g32,
-    const int *__restrict__ cpos)
+    double *__restrict__ alpha_out, const int *__restrict__ rowptr,
+    const int *__restrict__ cols, const double *__restrict__ vals, int p, int nnz,
+    double *__restrict__ g64, float *__restrict__ g32)
 {
-    channel_col(alpha_in, beta, alpha_out, Dmat, p, C, blockIdx.x, g64, g32,
-                cpos);
+    channel_entries(alpha_in, beta, alpha_out, rowptr, cols, vals, p, nnz, blockIdx.x,
+                    g64, g32);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,10 +126,10 @@ __global__ __launch_bounds__(256) void batch_channel_kernel(
     const BatchUpdateDesc *__restrict__ d, int with_beta)
 {
     const BatchUpdateDesc &q = d[blockIdx.y];
-    if ((int)blockIdx.x < q.C)
-        channel_col(q.alpha_in, with_beta ? q.beta : nullptr,
-                    with_beta ? q.alpha_out : nullptr, q.Dmat, q.p, q.C,
-                    blockIdx.x, q.g64, q.g32, q.cpos);
+    if ((int)blockIdx.x * 256 < q.nnz)
+        channel_entries(q.alpha_in, with_beta ? q.beta : nullptr,
+                        with_beta ? q.alpha_out : nullptr, q.rowptr, q.cols, q.vals,
+                        q.p, q.nnz, blockIdx.x, q.g64, q.g32);
 }
 
 // Point values of the kernel operator (Section 3.2) for the next iteration:
@@ -207,22 +200,22 @@ __global__ void reset_counters_kernel(unsigned int *c, int n)
     if (i < n) c[i] = 0u;
 }
 
-hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_C,
+hipError_t launch_batch_update(int nprob, int max_n, int max_p, int max_cb,
                                hipStream_t s, const BatchUpdateDesc *d)
 {
     hipLaunchKernelGGL(batch_finalize_kernel,
                        dim3((max_n + 255) / 256, nprob), dim3(256), 0, s, d);
     hipLaunchKernelGGL(batch_project_kernel, dim3(max_p, nprob), dim3(256), 0,
                        s, d);
-    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_C, nprob), dim3(256), 0,
+    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_cb, nprob), dim3(256), 0,
                        s, d, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_channels(int nprob, int max_C, hipStream_t s,
+hipError_t launch_batch_channels(int nprob, int max_cb, hipStream_t s,
                                  const BatchUpdateDesc *d)
 {
-    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_C, nprob), dim3(256), 0,
+    hipLaunchKernelGGL(batch_channel_kernel, dim3(max_cb, nprob), dim3(256), 0,
                        s, d, 0);
     return hipGetLastError();
 }
@@ -350,12 +343,12 @@ int batch_occupancy(int d, int eta, int q10, bool fp32, int vol)
     return 0;
 }
 
-hipError_t launch_update(int n, int groups, int M, int ppg, int p, int C,
+hipError_t launch_update(int n, int groups, int M, int ppg, int p, int nnz,
                          hipStream_t s, const double *partial, double *c,
                          double *var, const double *W, double *beta,
                          const double *alpha_in, double *alpha_out,
-                         const double *Dmat, double *g64, float *g32,
-                         const int *cpos, hipEvent_t *ev /* 3 events or NULL */)
+                         const int *rowptr, const int *cols, const double *vals,
+                         double *g64, float *g32, hipEvent_t *ev /* 3 events or NULL */)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0,
                        s, partial, n, groups, M, ppg, c, var);
@@ -363,19 +356,19 @@ hipError_t launch_update(int n, int groups, int M, int ppg, int p, int C,
     hipLaunchKernelGGL(project_kernel, dim3(p), dim3(256), 0, s, W, c, n,
                        beta);
     if (ev) (void)hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha_in,
-                       beta, alpha_out, Dmat, p, C, g64, g32, cpos);
+    hipLaunchKernelGGL(channel_kernel, dim3((nnz + 255) / 256), dim3(256), 0, s,
+                       alpha_in, beta, alpha_out, rowptr, cols, vals, p, nnz, g64, g32);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
-hipError_t launch_channels(int p, int C, hipStream_t s, const double *alpha,
-                           const double *Dmat, double *g64, float *g32,
-                           const int *cpos)
+hipError_t launch_channels(int p, int nnz, hipStream_t s, const double *alpha,
+                           const int *rowptr, const int *cols, const double *vals,
+                           double *g64, float *g32)
 {
-    hipLaunchKernelGGL(channel_kernel, dim3(C), dim3(256), 0, s, alpha,
-                       (const double *)nullptr, (double *)nullptr, Dmat, p,
-                       C, g64, g32, cpos);
+    hipLaunchKernelGGL(channel_kernel, dim3((nnz + 255) / 256), dim3(256), 0, s,
+                       alpha, (const double *)nullptr, (double *)nullptr, rowptr,
+                       cols, vals, p, nnz, g64, g32);
     return hipGetLastError();
 }
 
