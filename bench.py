@@ -186,10 +186,10 @@ ISSUE_CYCLES_D1_FP32 = {
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
 TRAFFIC = [
-    {"sources_sha16": "a6400b6745046d6e", "tiling": [1, 4],
+    {"sources_sha16": "58ae56878bae5897", "tiling": [1, 4],
      "fetch_kib": 16810.0, "write_kib": 1754000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "a6400b6745046d6e", "tiling": [4, 1],
+    {"sources_sha16": "58ae56878bae5897", "tiling": [4, 1],
      "fetch_kib": 28360.0, "write_kib": 5364000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
@@ -198,11 +198,11 @@ TRAFFIC = [
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
 COUNTERS = [
-    {"sources_sha16": "a6400b6745046d6e", "tiling": [1, 4],
+    {"sources_sha16": "58ae56878bae5897", "tiling": [1, 4],
      "valu_issue": 0.915, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 8.09e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "a6400b6745046d6e", "tiling": [4, 1],
+    {"sources_sha16": "58ae56878bae5897", "tiling": [4, 1],
      "valu_issue": 0.914, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 8.16e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},

@@ -243,10 +243,10 @@ __device__ __forceinline__ void philox_round_dev(u32x4 &c, uint32_t &k0, uint32_
 // other three words are uniform.  Rounds 1 and 2 keep their hoistable work
 // on the uniform words; after round 2 only word 3 is still uniform, and from
 // round 4 on every word varies, so with kXor3 round 3 takes the three-input
-// XOR for word 0 and rounds 4-10 for both.  The FP32 kernels below d = 10
-// take it (10 fewer of the ~53 vector instructions of a block); the others
-// keep the two-XOR form, under which the d = 1 FP64 kernel fits 128
-// registers (four waves per SIMD) and the d = 10 kernels spill less.
+// XOR for word 0 and rounds 4-10 for both.  All kernels but the FP64 d = 1
+// ones take it (10 fewer of the ~53 vector instructions of a block; the
+// d = 10 launches 3-5% faster); the FP64 d = 1 kernels keep the two-XOR
+// form, under which they fit 128 registers (four waves per SIMD).
 // After the second round the key passes through an empty asm statement, so
 // that the keys of rounds 3-10, k + r (W0, W1), are formed on the scalar
 // unit per block instead of being hoisted out of the path loops, where
@@ -346,7 +346,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
     constexpr int SG = (D % 4 == 0) ? 1 : ((D % 2 == 0) ? 2 : 4);
     constexpr int NB = SG * D / 4;
     constexpr int NBB = (D + 3) / 4; // bridge blocks
-    constexpr bool kXor3 = (sizeof(Real) == 4 && D < 10) || (sizeof(Real) == 8 && D == 5); // Philox XOR form
+    constexpr bool kXor3 = sizeof(Real) == 4 || D >= 2; // Philox XOR form
     // FP32 round keys in vector registers (16 of them): at d = 1, and at
     // d = 2 from eta = 5 on, where the kernel's own registers already hold
     // it to four waves per SIMD and the keys still fit (below, they would
