@@ -526,6 +526,10 @@ def serve(n_requests, n_sat, n_check, seed=0, dims=(1, 2, 5, 10)):
                 if ta > now:
                     time.sleep(ta - now)
                 out.append(S.submit(cfg))
+                if len(out) % 100 == 0:
+                    print("serving %s: %d/%d submitted after %.1f s, %d completed" %
+                          (tag, len(out), len(reqs), time.perf_counter() - t0,
+                           S.stats()["completed"]), file=sys.stderr, flush=True)
             res = []
             for j, t in enumerate(out):
                 res.append(S.poll(t))
