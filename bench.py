@@ -706,20 +706,25 @@ def single_launches(names, euler_steps=None, precision="fp32", overrides=None):
 # n = 1000 points redrawn every iteration, M = 30,000, N = 10, 10 Picard
 # iterations; benchmark price 7.0207, CI (7.0125, 7.0288).
 D10_BENCHMARK = 7.0207
-D10_SETS = ((2, 1.0), (3, 1.0), (5, 0.5), (5, 0.6), (5, 0.7))
+# (eta, q, M): total degree 2 and 3, the hyperbolic sets eta = 5 with
+# q = 0.5, 0.6, 0.7, and the paper's other two curves of Section 6.2.1,
+# eta = 4, q = 0.6 and eta = 5, q = 0.6 at M = 5000
+D10_SETS = ((2, 1.0, 30000), (3, 1.0, 30000), (4, 0.6, 30000), (5, 0.5, 30000),
+            (5, 0.6, 30000), (5, 0.6, 5000), (5, 0.7, 30000))
 
 
 def d10_sparsity_study(seeds=8):
     """Bias against sparsity of the index set: the paper's d = 10 call
-    basket on the total-degree sets eta = 2, 3 and the hyperbolic sets
-    eta = 5, q = 0.5, 0.6, 0.7, each over `seeds` seeds; mean, seed spread
-    and the difference from the benchmark price."""
+    basket on the total-degree sets eta = 2, 3, the hyperbolic sets eta = 4,
+    q = 0.6 and eta = 5, q = 0.5, 0.6, 0.7 (and q = 0.6 at M = 5000), each
+    over `seeds` seeds; mean, seed spread and the difference from the
+    benchmark price."""
     import paper_1102_4666_amd as bsde
     import workloads
     out = []
-    for eta, q in D10_SETS:
+    for eta, q, M in D10_SETS:
         cfg = workloads.call_basket_d10_hyperbolic()
-        cfg.update(eta=eta, q=q)
+        cfg.update(eta=eta, q=q, M=M)
         prices, ms = [], []
         p = None
         for seed in range(seeds):
@@ -732,14 +737,14 @@ def d10_sparsity_study(seeds=8):
         if p is None:
             p = len(index_set(10, eta, q))
         m, sd = float(np.mean(prices)), float(np.std(prices, ddof=1))
-        out.append({"eta": eta, "q": q, "p": p, "mean_price": m, "seed_std": sd,
+        out.append({"eta": eta, "q": q, "M": M, "p": p, "mean_price": m, "seed_std": sd,
                     "std_of_mean": sd / np.sqrt(seeds), "bias": m - D10_BENCHMARK,
                     "ms_per_solve": float(np.mean(ms))})
-        print("d=10 eta=%d q=%g p=%d: %.4f +- %.4f" % (eta, q, p, m, sd),
+        print("d=10 eta=%d q=%g M=%d p=%d: %.4f +- %.4f" % (eta, q, M, p, m, sd),
               file=sys.stderr, flush=True)
     return {"workload": "d=10 European call basket (Section 6.2.1), n=1000 uniform "
-                        "points redrawn every iteration, domain +-1 sd, M=30000, "
-                        "N=10, 10 Picard iterations, FP32 paths",
+                        "points redrawn every iteration, domain +-1 sd, M=30000 "
+                        "unless stated, N=10, 10 Picard iterations, FP32 paths",
             "benchmark": D10_BENCHMARK, "seeds": seeds, "sets": out}
 
 

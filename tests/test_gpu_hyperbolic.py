@@ -1,8 +1,8 @@
 """Hyperbolic index sets (Section 4.2, eq. hyper_set) on the GPU against the
 FP64 oracle.
 
-1. d = 10, eta = 5 with q = 0.5, 0.6 and 0.7 (p = 111, 221, 386): each set
-   has path kernels of its own.  Whole solves at M = 512 paths per point (two
+1. d = 10, eta = 5 with q = 0.5, 0.6 and 0.7 (p = 111, 221, 386), and
+   eta = 4 with q = 0.6 (p = 100): each set has path kernels of its own.  Whole solves at M = 512 paths per point (two
    paths per lane), N = 10 Euler steps, two Picard iterations, on uniform
    points (t, x) over [0, T] x D, every per-point correction, the price and
    the deltas compared with the oracle (which builds the same set itself).
@@ -60,16 +60,17 @@ def _compare(cfg, tiling=None, workers=8):
     return p, alpha
 
 
-@pytest.mark.parametrize("q,p_expected", [(0.5, 111), (0.6, 221), (0.7, 386)])
-def test_d10_eta5_hyperbolic_sets_against_oracle(q, p_expected):
+@pytest.mark.parametrize("eta,q,p_expected",
+                         [(5, 0.5, 111), (5, 0.6, 221), (5, 0.7, 386), (4, 0.6, 100)])
+def test_d10_hyperbolic_sets_against_oracle(eta, q, p_expected):
     n = int(math.ceil(1.25 * p_expected))
     cfg = problem(d=10, vol_kind="bump",
                   vol_level=[0.15 + 0.02 * j for j in range(10)], bump_a=0.25,
                   rho=0.2, payoff="call", S0=100.0, grid="uniform", n_x=n,
-                  eta=5, q=q, M=512, N=10, K_it=2, omega=1.0,
+                  eta=eta, q=q, M=512, N=10, K_it=2, omega=1.0,
                   precision="fp32", seed=13)
-    print("d=10 eta=5 q=%g (n=%d)" % (q, n), flush=True)
-    assert len(oracle.index_set(11, 5, q)) == p_expected
+    print("d=10 eta=%d q=%g (n=%d)" % (eta, q, n), flush=True)
+    assert len(oracle.index_set(11, eta, q)) == p_expected
     p, _ = _compare(cfg, tiling=(1, 2))
     assert p == p_expected
 
