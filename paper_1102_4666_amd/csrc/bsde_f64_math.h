@@ -224,38 +224,41 @@ BSDE_F64_HD inline double exp_nonpos(double x)
 // ---------------------------------------------------------------------------
 // Table-driven forms for the FP64 path kernels, with the tables in LDS
 // (filled by each workgroup at the start of a tile):
-//  - sine and cosine of the Box-Muller angle: the turn in 256 sectors
-//    centred at j/256 turns (the axes are centres, so results near zero
-//    keep their relative accuracy); the word's remainder rho = w - j 2^24
-//    is exact, r = 2 pi (rho + 1/2) 2^-32 lies in [-pi/256, pi/256], where
-//    sin r and cos r to degrees 7 and 6 leave remainders below 2e-23 and
-//    2e-20; then the angle-addition formulas with the table's sine and
-//    cosine of 2 pi j / 256;
-//  - e^x for x <= 0: x = (64 n + j) ln 2 / 64 + r, |r| <= ln 2 / 128, e^r
-//    to degree 5 (remainder below 4e-17 of e^r), times the table entry
-//    2^(j/64) and 2^n.
+//  - sine and cosine of the Box-Muller angle: the turn in 1024 sectors
+//    centred at j/1024 turns (the axes are centres, so results near zero
+//    keep their relative accuracy); the word's remainder rho = w - j 2^22
+//    is exact, r = 2 pi (rho + 1/2) 2^-32 lies in [-pi/1024, pi/1024],
+//    where sin r and cos r to degrees 5 and 4 leave remainders below 2e-19
+//    of r and 2e-18; then the angle-addition formulas with the table's sine
+//    and cosine of 2 pi j / 1024;
+//  - e^x for x <= 0: x = (256 n + j) ln 2 / 256 + r, |r| <= ln 2 / 512, e^r
+//    to degree 4 (remainder below 4e-17 of e^r), times the table entry
+//    2^(j/256) and 2^n.
+// The larger tables (18 KB of LDS a workgroup) take one degree off each
+// series: two fused multiply-adds fewer per Box-Muller pair and one fewer
+// per volatility.
 // ---------------------------------------------------------------------------
-constexpr int kSinCosBins = 256;
-constexpr int kExpBins = 64;
+constexpr int kSinCosBins = 1024;
+constexpr int kExpBins = 256;
 struct Tables {
-    double sc[kSinCosBins][2]; // sin, cos of 2 pi j / 256
-    double ex[kExpBins];       // 2^(j/64)
+    double sc[kSinCosBins][2]; // sin, cos of 2 pi j / 1024
+    double ex[kExpBins];       // 2^(j/256)
 };
-// ln 2 / 64 in two parts: the first has 36 significant bits, so n kLn2_64Hi
-// is exact for |n| < 2^17
-constexpr double kLn2_64Hi = 0.010830424696223417;
-constexpr double kLn2_64Lo = 2.572804622327669e-14;
+// ln 2 / 256 in two parts: the first has 35 significant bits, so
+// n kLn2_256Hi is exact for |n| < 2^18 (x >= -708 gives |n| < 261,500)
+constexpr double kLn2_256Hi = 0.0027076061741126978;
+constexpr double kLn2_256Lo = -5.0411407304988844e-14;
 
 // entries first, first + stride, ... of both tables
 BSDE_F64_HD inline void fill_tables(Tables &T, int first, int stride)
 {
     for (int t = first; t < kSinCosBins + kExpBins; t += stride) {
         if (t < kSinCosBins) {
-            // j/256 turns = q/4 + f/256, f in [-32, 32)
-            const uint32_t q = ((uint32_t)(t + 32) >> 6) & 3u;
-            const int f = t - (int)(((uint32_t)(t + 32) >> 6) << 6);
+            // j/1024 turns = q/4 + f/1024, f in [-128, 128)
+            const uint32_t q = ((uint32_t)(t + 128) >> 8) & 3u;
+            const int f = t - (int)(((uint32_t)(t + 128) >> 8) << 8);
             double sx, cx;
-            sincos_reduced((double)f * (6.283185307179586476925286766559 / 256.0), sx, cx);
+            sincos_reduced((double)f * (6.283185307179586476925286766559 / 1024.0), sx, cx);
             rotate_quarters(q, sx, cx, T.sc[t][0], T.sc[t][1]);
         } else {
             T.ex[t - kSinCosBins] = exp2((double)(t - kSinCosBins) / (double)kExpBins);
@@ -265,17 +268,14 @@ BSDE_F64_HD inline void fill_tables(Tables &T, int first, int stride)
 
 BSDE_F64_HD inline void sincos_turn_tab(uint32_t w, const Tables &T, double &s, double &c)
 {
-    // nearest sector centre j 2^24 (mod 2^32) and the signed remainder
-    const uint32_t j = (w + 0x00800000u) >> 24;
-    const int32_t rho = (int32_t)(w - (j << 24));
+    // nearest sector centre j 2^22 (mod 2^32) and the signed remainder
+    const uint32_t j = (w + 0x00200000u) >> 22;
+    const int32_t rho = (int32_t)(w - (j << 22));
     const double r = __builtin_fma((double)rho, kTwoPiUlp, 0.5 * kTwoPiUlp);
     const double r2 = r * r;
-    // sin r = r + r^3 (-1/6 + r^2 (1/120 - r^2/5040)), cos r = 1 + r^2 (-1/2 +
-    // r^2 (1/24 - r^2/720))
-    double ps = __builtin_fma(r2, kS[2], kS[1]);
-    ps = __builtin_fma(ps, r2, kS[0]);
-    double pc = __builtin_fma(r2, kC[2], kC[1]);
-    pc = __builtin_fma(pc, r2, kC[0]);
+    // sin r = r + r^3 (-1/6 + r^2/120), cos r = 1 + r^2 (-1/2 + r^2/24)
+    const double ps = __builtin_fma(r2, kS[1], kS[0]);
+    const double pc = __builtin_fma(r2, kC[1], kC[0]);
     const double sr = __builtin_fma(r * r2, ps, r);
     const double cr = __builtin_fma(r2, pc, 1.0);
     const double sa = T.sc[j & (kSinCosBins - 1)][0], ca = T.sc[j & (kSinCosBins - 1)][1];
@@ -286,18 +286,17 @@ BSDE_F64_HD inline void sincos_turn_tab(uint32_t w, const Tables &T, double &s, 
 BSDE_F64_HD inline double exp_nonpos_tab(double x, const Tables &T)
 {
     x = __builtin_fmax(x, -708.0);
-    const double N = __builtin_rint(x * 92.332482616893656811); // 64 / ln 2
-    double r = __builtin_fma(-N, kLn2_64Hi, x);
-    r = __builtin_fma(-N, kLn2_64Lo, r);
-    // e^r - 1 = r + r^2 (1/2 + r (1/6 + r (1/24 + r / 120)))
-    double q = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    q = __builtin_fma(q, r, 1.0 / 6.0);
+    const double N = __builtin_rint(x * 369.32993046757465); // 256 / ln 2
+    double r = __builtin_fma(-N, kLn2_256Hi, x);
+    r = __builtin_fma(-N, kLn2_256Lo, r);
+    // e^r - 1 = r + r^2 (1/2 + r (1/6 + r / 24))
+    double q = __builtin_fma(r, 1.0 / 24.0, 1.0 / 6.0);
     q = __builtin_fma(q, r, 0.5);
     const double em1 = __builtin_fma(q * r, r, r);
     const int Ni = (int)N;
     const double t = T.ex[Ni & (kExpBins - 1)];
-    // times 2^n, n = floor(N / 64) in [-704, 0] (the result stays normal)
-    return __builtin_ldexp(__builtin_fma(t, em1, t), Ni >> 6);
+    // times 2^n, n = floor(N / 256) in [-1022, 0] (the result stays normal)
+    return __builtin_ldexp(__builtin_fma(t, em1, t), Ni >> 8);
 }
 
 } // namespace f64

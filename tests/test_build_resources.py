@@ -21,7 +21,7 @@ RES = os.path.join(ROOT, "paper_1102_4666_amd", "_build", "resources.txt")
 # kernel-name pattern -> largest spill allowed (bytes per lane)
 ALLOWED = {"path_kernelILi10ELi2Ef": 80, "path_kernelILi10ELi3Ef": 168,
            "path_kernelILi10ELi5Ef": 240, "path_kernelILi10ELi2Ed": 320,
-           "path_kernelILi10ELi3Ed": 640, "path_kernelILi5ELi2Ed": 288,
+           "path_kernelILi10ELi3Ed": 640, "path_kernelILi5ELi2Ed": 320,
            "path_kernelILi5ELi3Ed": 352, "path_kernelILi3ELi4Ed": 72,
            "path_kernelILi10ELi4Ef": 272}
 

@@ -4,7 +4,7 @@ and checked against 120-bit references (mpmath): the logarithm and the
 quarter-turn sine/cosine of the Box-Muller words, the square root of the
 Box-Muller radius, and the exponential of non-positive arguments of the
 local volatility -- the series forms and the forms from the kernels'
-tables (256 sectors of the turn, 64 powers 2^(j/64)).  The host build
+tables (1024 sectors of the turn, 256 powers 2^(j/256)).  The host build
 refines seeds of single-precision accuracy, no better than the device's
 hardware seeds.  No GPU needed."""
 import os
@@ -111,10 +111,10 @@ def test_quarter_turn_sine_and_cosine(driver):
 
 @pytest.mark.parametrize("form", ["s", "S"])
 def test_sector_sine_and_cosine(driver, form):
-    # "s": quarter turns and series; "S": 256 sectors from the LDS table
+    # "s": quarter turns and series; "S": 1024 sectors from the LDS table
     mpmath.mp.prec = 120
-    ws = _words() + [(j * 2 ** 24 + o) % 2 ** 32 for j in range(257)
-                     for o in (-2 ** 23 - 1, -2 ** 23, -1, 0, 1, 2 ** 23 - 1)]
+    ws = _words() + [(j * 2 ** 22 + o) % 2 ** 32 for j in range(1025)
+                     for o in (-2 ** 21 - 1, -2 ** 21, -1, 0, 1, 2 ** 21 - 1)]
     out = _run(driver, ["%s %d" % (form, w) for w in ws])
     worst = 0.0
     for w, ln in zip(ws, out):
@@ -131,6 +131,9 @@ def test_exp_of_non_positive_arguments(driver, form):
     xs = list(-rng.uniform(0, 1, 2000) ** 2 * 40) + list(-rng.uniform(0, 708, 1000))
     xs += [0.0, -0.0, -1e-300, -1e-20, -0.3465735902799726, -0.34657359027997264,
            -707.9, -708.0]
+    # half-way points of the exponential table's bins, where |r| is largest
+    xs += [-(k + 0.5) * float(mpmath.log(2)) / 256 * (1 + e) for k in range(0, 4096, 37)
+           for e in (-1e-15, 0.0, 1e-15)]
     out = _run(driver, ["%s %.17g" % (form, x) for x in xs])
     worst = max(_ulps(float(v), mpmath.exp(mpmath.mpf(x))) for x, v in zip(xs, out))
     assert worst <= 1.5, worst
