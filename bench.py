@@ -192,6 +192,9 @@ TRAFFIC = [
     {"sources_sha16": "bea2752418f4c03b", "tiling": [4, 1],
      "fetch_kib": 25730.0, "write_kib": 3351000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+    {"sources_sha16": "bea2752418f4c03b", "tiling": [2, 2],
+     "fetch_kib": 18720.0, "write_kib": 1763000.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
 # Counter-derived figures of the same kernel (same profiles, same guard):
 # VALU issue = SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / cycles, matrix cores
@@ -205,6 +208,10 @@ COUNTERS = [
     {"sources_sha16": "bea2752418f4c03b", "tiling": [4, 1],
      "valu_issue": 0.906, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 7.78e11, "fp64_matrix_flop_per_launch": 0.0,
+     "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
+    {"sources_sha16": "bea2752418f4c03b", "tiling": [2, 2],
+     "valu_issue": 0.912, "mfma_busy": 0.0,
+     "fp64_vector_flop_per_launch": 7.71e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
