@@ -186,14 +186,14 @@ ISSUE_CYCLES_D1_FP32 = {
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
 TRAFFIC = [
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [1, 4],
-     "fetch_kib": 14870.0, "write_kib": 883400.0,
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [1, 4],
+     "fetch_kib": 14090.0, "write_kib": 934600.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [4, 1],
-     "fetch_kib": 25730.0, "write_kib": 3351000.0,
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [4, 1],
+     "fetch_kib": 24310.0, "write_kib": 3686000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [2, 2],
-     "fetch_kib": 18720.0, "write_kib": 1763000.0,
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [2, 2],
+     "fetch_kib": 17950.0, "write_kib": 1832000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
 # Counter-derived figures of the same kernel (same profiles, same guard):
@@ -201,17 +201,17 @@ TRAFFIC = [
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
 COUNTERS = [
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [1, 4],
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [1, 4],
      "valu_issue": 0.907, "mfma_busy": 0.0,
-     "fp64_vector_flop_per_launch": 7.67e11, "fp64_matrix_flop_per_launch": 0.0,
+     "fp64_vector_flop_per_launch": 7.45e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [4, 1],
-     "valu_issue": 0.906, "mfma_busy": 0.0,
-     "fp64_vector_flop_per_launch": 7.78e11, "fp64_matrix_flop_per_launch": 0.0,
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [4, 1],
+     "valu_issue": 0.909, "mfma_busy": 0.0,
+     "fp64_vector_flop_per_launch": 7.57e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "bea2752418f4c03b", "tiling": [2, 2],
-     "valu_issue": 0.912, "mfma_busy": 0.0,
-     "fp64_vector_flop_per_launch": 7.71e11, "fp64_matrix_flop_per_launch": 0.0,
+    {"sources_sha16": "eebba33c70b96b77", "tiling": [2, 2],
+     "valu_issue": 0.909, "mfma_busy": 0.0,
+     "fp64_vector_flop_per_launch": 7.49e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
