@@ -10,9 +10,9 @@ FP64 oracle.
    total-degree kernel with the coefficients outside the set held at zero:
    the same comparison, in FP64 and FP32 paths.
 
-3. The largest set (q = 0.7, p = 386) at the shape of the paper's d = 10
-   runs (n = 1000 points, M = 30,000, N = 10) with the narrow domain of
-   those runs (one standard deviation: many paths leave it, where Chebyshev
+3. The largest set (q = 0.7, p = 386) and the sparsest (eta = 4, q = 0.6,
+   p = 100) at the shape of the paper's d = 10 runs (n = 1000 points,
+   M = 30,000, N = 10) with the narrow domain of those runs (one standard deviation: many paths leave it, where Chebyshev
    values of degree 5 grow large), iteration 1 from the least-squares fit of
    the payoff at the points -- the polynomial handed to the oracle as its
    monomial coefficients and to the library as point values -- on 16
@@ -94,16 +94,17 @@ def _corrections_at(args):
     return float(c[0]), float(v[0])
 
 
-def test_d10_q07_study_shape_iteration1_sampled():
+@pytest.mark.parametrize("eta,q,p_expected", [(5, 0.7, 386), (4, 0.6, 100)])
+def test_d10_study_shape_iteration1_sampled(eta, q, p_expected):
     from workloads import call_basket_d10_hyperbolic
     cfg = call_basket_d10_hyperbolic()
-    cfg.update(q=0.7, redraw=0, K_it=2)
+    cfg.update(eta=eta, q=q, redraw=0, K_it=2)
     n, p = oracle.sizes(cfg)
-    assert p == 386
+    assert p == p_expected
     pts = oracle.points(cfg)
     y = np.array([oracle.payoff(cfg, pts[i, 1:]) for i in range(n)])
     alpha = oracle.fit(cfg, y)
-    print("d=10 eta=5 q=0.7 at the study shape, iteration 1", flush=True)
+    print("d=10 eta=%d q=%g at the study shape, iteration 1" % (eta, q), flush=True)
     with bsde.Problem(cfg) as P:
         P.fit_values(y, 1)
         P.solve()
