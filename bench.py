@@ -186,13 +186,13 @@ ISSUE_CYCLES_D1_FP32 = {
 # hash is recorded with it and for the tiling it was taken at; otherwise
 # the line reports null.
 TRAFFIC = [
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [1, 4],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [1, 4],
      "fetch_kib": 14090.0, "write_kib": 934600.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [4, 1],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [4, 1],
      "fetch_kib": 24310.0, "write_kib": 3686000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [2, 2],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [2, 2],
      "fetch_kib": 17950.0, "write_kib": 1832000.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
 ]
@@ -201,15 +201,15 @@ TRAFFIC = [
 # busy = SQ_VALU_MFMA_BUSY_CYCLES / 1024 SIMDs / cycles, FP64 vector FLOP
 # issued = 64 (2 FMA + MUL + ADD + TRANS) instructions per launch.
 COUNTERS = [
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [1, 4],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [1, 4],
      "valu_issue": 0.907, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 7.45e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [4, 1],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [4, 1],
      "valu_issue": 0.909, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 7.57e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},
-    {"sources_sha16": "eebba33c70b96b77", "tiling": [2, 2],
+    {"sources_sha16": "ea70fccb41332a0b", "tiling": [2, 2],
      "valu_issue": 0.909, "mfma_busy": 0.0,
      "fp64_vector_flop_per_launch": 7.49e11, "fp64_matrix_flop_per_launch": 0.0,
      "profile": "profiles/path_kernel_d5_fp64_geo_basket_d5.md"},

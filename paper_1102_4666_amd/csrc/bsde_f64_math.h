@@ -301,5 +301,30 @@ BSDE_F64_HD inline double exp_nonpos_tab(double x, const Tables &T)
     return __builtin_ldexp(__builtin_fma(t, em1, t), Ni >> 8);
 }
 
+// 2^(-t/256) for t >= 0: the bump volatility's e^{-(x - log c)^2} when the
+// FP64 paths carry y = kappa (x - log c) with kappa^2 = 256 log2 e, so that
+// t = y^2 needs no reduction constant: t clamped at 261,485 (2^-1021.4, far
+// below the volatility's rounding), N = rint(t) and f = t - N (exact, in
+// [-1/2, 1/2]), 2^(-f/256) = e^{-f ln 2 / 256} by its Maclaurin series in f
+// to degree 4 (remainder below 4e-17), times the table entry 2^(j/256) and
+// 2^n for -N = 256 n + j.
+// Coefficients (-ln 2 / 256)^k / k!, k = 1..4
+constexpr double kE2m[4] = {-0.0027076061740622863, 3.6655655969101062e-06,
+                            -3.3083026805413713e-09, 2.239395190875157e-12};
+BSDE_F64_HD inline double exp2_neg_tab(double t, const Tables &T)
+{
+    t = __builtin_fmin(t, 261485.0);
+    const double N = __builtin_rint(t);
+    const double f = t - N; // exact
+    double q = __builtin_fma(f, kE2m[3], kE2m[2]);
+    q = __builtin_fma(q, f, kE2m[1]);
+    q = __builtin_fma(q, f, kE2m[0]);
+    const double em1 = q * f;
+    const int Ni = -(int)N;
+    const double e = T.ex[Ni & (kExpBins - 1)];
+    // times 2^n, n = floor(-N / 256) in [-1022, 0] (the result stays normal)
+    return __builtin_ldexp(__builtin_fma(e, em1, e), Ni >> 8);
+}
+
 } // namespace f64
 } // namespace bsde

@@ -149,16 +149,23 @@ __device__ __forceinline__ Real local_vol(Real level, Real level_a, Real lc,
 }
 
 // Coordinates of the Euler state.  With the bump volatility the paths carry
-// y = kappa (x - log c) -- kappa^2 = log2 e in FP32, 1 in FP64 -- so that
-// the volatility costs a square, one exponential and one fused multiply-add
-// per asset and step: level + (level a) 2^{-y^2} (FP32), level + (level a)
-// e^{-y^2} (FP64).  Every increment of x is scaled by kappa as well.  The
-// other volatility kinds keep y = x.
-template <int VOL, typename Real>
+// y = kappa (x - log c) -- kappa^2 = log2 e in FP32, 256 log2 e in FP64 at
+// d = 10, 1 in the other FP64 kernels -- so that the volatility costs a
+// square, one exponential and one fused multiply-add per asset and step:
+// level + (level a) 2^{-y^2} (FP32), level + (level a) 2^{-y^2/256} (FP64,
+// d = 10: the table exponential needs no reduction by ln 2), level +
+// (level a) e^{-y^2} (other FP64; there the scaled form saves nothing: the
+// vector instruction it takes off the volatility comes back as 64-bit
+// literal moves in the rest of the step).  Every increment of x is scaled
+// by kappa as well.  The other volatility kinds keep y = x.
+template <int VOL, typename Real, int D>
 struct EulerState {
     static constexpr bool kShift = VOL == kVolBump;
+    static constexpr bool kExp2F64 = kShift && sizeof(Real) == 8 && D >= 10;
     static constexpr Real kappa =
-        (kShift && sizeof(Real) == 4) ? Real(1.2011224087864498) : Real(1);
+        !kShift ? Real(1)
+                : (sizeof(Real) == 4 ? Real(1.2011224087864498)
+                                     : (kExp2F64 ? Real(19.217958540583197) : Real(1)));
     static __device__ __forceinline__ Real to(Real x, Real lc)
     {
         if constexpr (kShift) return (x - lc) * kappa;
@@ -175,6 +182,8 @@ struct EulerState {
         if constexpr (kShift) {
             if constexpr (sizeof(Real) == 4)
                 return fmaf(level_a, __builtin_amdgcn_exp2f(-y * y), level);
+            else if constexpr (kExp2F64)
+                return fma(level_a, f64::exp2_neg_tab(y * y, f64_tables), level);
             else
                 return fma(level_a, f64::exp_nonpos_tab(-y * y, f64_tables), level);
         } else {
@@ -369,7 +378,7 @@ __device__ __forceinline__ void run_tile(const PathParams &prm, uint64_t cbase,
     const Real h = (T - t0) / (Real)prm.N;
     // Euler state coordinates y = kappa (x - off); step normals come out of
     // Box-Muller already scaled by kappa sqrt(h)
-    using ES = EulerState<VOL, Real>;
+    using ES = EulerState<VOL, Real, D>;
     const Real step_scale = Arith<Real>::bm_scale(h * (ES::kappa * ES::kappa));
     const Real r = (Real)prm.r, omega = (Real)prm.omega, K = (Real)prm.K;
     const Real lc = (Real)prm.log_bump_c;

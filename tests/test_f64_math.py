@@ -33,6 +33,9 @@ int main() {
         } else if (kind[0] == 'q') {
             double x; if (std::scanf("%lf", &x) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::sqrt_nonneg(x));
+        } else if (kind[0] == 'X') {
+            double t; if (std::scanf("%lf", &t) != 1) return 1;
+            std::printf("%.17g\n", bsde::f64::exp2_neg_tab(t, T));
         } else if (kind[0] == 'E') {
             double x; if (std::scanf("%lf", &x) != 1) return 1;
             std::printf("%.17g\n", bsde::f64::exp_nonpos_tab(x, T));
@@ -141,6 +144,26 @@ def test_exp_of_non_positive_arguments(driver, form):
     tail = _run(driver, ["%s -709" % form, "%s -1e10" % form])
     for v in tail:
         assert float(v) == pytest.approx(float(mpmath.exp(-708)), rel=1e-15)
+
+
+def test_power_of_two_of_the_scaled_square(driver):
+    # 2^(-t/256), t = y^2 with the FP64 bump state y = kappa (x - log c),
+    # kappa^2 = 256 log2 e (the d = 10 kernels): random squares below the
+    # clamp, half-integers (f = +-1/2, the largest series argument), the
+    # table's period 256, and the clamp
+    mpmath.mp.prec = 120
+    rng = np.random.default_rng(6)
+    ts = list((rng.uniform(0, 26, 2000) * 19.2) ** 2) + list(rng.uniform(0, 261485, 1000))
+    ts += [0.0, 0.5, 1.5, 255.5, 256.0, 256.5, 511.49999999999994, 1e-300, 1e-12,
+           261484.5, 261485.0]
+    ts += [k + 0.5 * (1 + e) for k in range(0, 5000, 41) for e in (-1e-15, 0.0)]
+    out = _run(driver, ["X %.17g" % t for t in ts])
+    worst = max(_ulps(float(v), mpmath.power(2, -mpmath.mpf(t) / 256)) for t, v in zip(ts, out))
+    assert worst <= 1.5, worst
+    # beyond the clamp the value stays 2^(-261485/256), a normal number
+    for v in _run(driver, ["X 261486", "X 1e12"]):
+        assert float(v) == pytest.approx(float(mpmath.power(2, -mpmath.mpf(261485) / 256)),
+                                         rel=1e-15)
 
 
 def test_square_root_of_the_radius(driver):
