@@ -243,6 +243,30 @@ bsde_status bsde_set_tiling(bsde_problem h, int groups_per_point,
 bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups,
                           int *paths_per_lane, double *ms);
 
+/* Tiling a problem will run with: groups per point and paths per lane as
+ * set by bsde_set_tiling or bsde_autotune, or taken from a tiling recorded
+ * for its signature when it was created (0, 0 = the automatic choice made at
+ * each solve).  Errors: EINVAL for a null argument. */
+bsde_status bsde_get_tiling(bsde_problem h, int *groups_per_point,
+                            int *paths_per_lane);
+
+/* Persistence of the tilings bsde_autotune has recorded in this process, so
+ * that a later process starts its problems with them without timing again.
+ * bsde_autotune_save writes every record to the text file path (replaced if
+ * it exists), one line per signature: the architecture of the current
+ * device (e.g. gfx950), d, eta, 10 q, precision, volatility kind, M, N, size
+ * class of n, groups per point, paths per lane; lines starting with # are
+ * comments.  bsde_autotune_load merges the records of path whose
+ * architecture is that of the current device into this process's records
+ * (a record of the same signature is replaced) and skips those of other
+ * architectures; problems created afterwards start with them.  *count
+ * (may be NULL) receives the number of records written or taken.  Errors:
+ * EINVAL for a null path, a file that cannot be opened, or a malformed line
+ * (load then changes nothing: every line is checked first, including that
+ * the tiling covers M); EDEVICE when the device cannot be queried. */
+bsde_status bsde_autotune_save(const char *path, int *count);
+bsde_status bsde_autotune_load(const char *path, int *count);
+
 /* Average duration in milliseconds of the last solve's kernels, measured
  * with HIP events on the solve's stream, per Picard iteration unless noted:
  * [0] Monte Carlo path kernel, [1] reduction of the per-point sums,

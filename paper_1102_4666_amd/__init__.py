@@ -35,6 +35,7 @@ EXPORTS = [
     "bsde_problem_sizes", "bsde_get_points", "bsde_get_coefficients",
     "bsde_set_coefficients", "bsde_fit_values", "bsde_get_corrections",
     "bsde_set_tiling", "bsde_autotune", "bsde_last_timings", "bsde_set_timing",
+    "bsde_get_tiling", "bsde_autotune_save", "bsde_autotune_load",
     "bsde_solve_batch", "bsde_solve_batch_noalloc",
     "bsde_destroy", "bsde_status_string", "bsde_last_error",
     "bsde_server_create", "bsde_server_submit", "bsde_server_poll",
@@ -120,6 +121,9 @@ def lib():
         L.bsde_last_timings.argtypes = [H, _dp]
         L.bsde_set_timing.argtypes = [H, C.c_int]
         L.bsde_autotune.argtypes = [H, C.c_void_p, _ip, _ip, _dp]
+        L.bsde_get_tiling.argtypes = [H, _ip, _ip]
+        L.bsde_autotune_save.argtypes = [C.c_char_p, _ip]
+        L.bsde_autotune_load.argtypes = [C.c_char_p, _ip]
         L.bsde_solve_batch.argtypes = [C.POINTER(H), C.c_int, C.c_void_p,
                                        C.c_int, _dp]
         L.bsde_solve_batch_noalloc.argtypes = [C.POINTER(H), C.c_int, C.c_void_p]
@@ -269,6 +273,28 @@ def bsde_autotune(h, stream=None):
     return g.value, p_.value, ms.value
 
 
+def bsde_get_tiling(h):
+    g, p_ = C.c_int(), C.c_int()
+    _check(lib().bsde_get_tiling(h, C.byref(g), C.byref(p_)), "bsde_get_tiling")
+    return g.value, p_.value
+
+
+def bsde_autotune_save(path):
+    """Write the tilings recorded by bsde_autotune in this process to path;
+    returns the number of records."""
+    n = C.c_int()
+    _check(lib().bsde_autotune_save(os.fsencode(path), C.byref(n)), "bsde_autotune_save")
+    return n.value
+
+
+def bsde_autotune_load(path):
+    """Merge the tilings recorded in path for this device's architecture;
+    returns the number of records taken."""
+    n = C.c_int()
+    _check(lib().bsde_autotune_load(os.fsencode(path), C.byref(n)), "bsde_autotune_load")
+    return n.value
+
+
 def bsde_set_timing(h, level):
     _check(lib().bsde_set_timing(h, int(level)), "bsde_set_timing")
 
@@ -358,6 +384,9 @@ class Problem:
         """0 = whole solve only, 1 = path kernel per iteration (default),
         2 = every kernel (each level adds event records to the stream)."""
         bsde_set_timing(self.h, level)
+
+    def tiling(self):
+        return bsde_get_tiling(self.h)
 
     def autotune(self, stream=None):
         """(groups per point, paths per lane, path-kernel ms) chosen."""

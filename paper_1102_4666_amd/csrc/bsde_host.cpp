@@ -1814,6 +1814,99 @@ bsde_status bsde_autotune(bsde_problem h, void *hip_stream, int *groups_out,
     return BSDE_OK;
 }
 
+// Architecture name of the current device ("gfx950"), the key under which
+// recorded tilings are saved: a tiling measured on one architecture says
+// nothing about another.
+static bsde_status device_arch(std::string &arch)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    if (arch.empty()) return fail(BSDE_EDEVICE, "device reports no architecture name");
+    return BSDE_OK;
+}
+
+bsde_status bsde_autotune_save(const char *path, int *count)
+{
+    if (!path) return fail(BSDE_EINVAL, "null path");
+    std::string arch;
+    const bsde_status st = device_arch(arch);
+    if (st != BSDE_OK) return st;
+    std::vector<std::pair<TuneKey, std::pair<int, int>>> rows;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        rows.assign(g_tuned.begin(), g_tuned.end());
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(BSDE_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "# bsde path tilings: arch d eta q10 precision vol M N size_class "
+                    "groups_per_point paths_per_lane\n");
+    for (const auto &r : rows) {
+        const TuneKey &k = r.first;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d\n", arch.c_str(), k.d, k.eta,
+                     k.q10, k.prec, k.vol, k.M, k.N, k.nclass, r.second.first,
+                     r.second.second);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) return fail(BSDE_EINVAL, std::string("cannot write ") + path);
+    if (count) *count = (int)rows.size();
+    return BSDE_OK;
+}
+
+bsde_status bsde_autotune_load(const char *path, int *count)
+{
+    if (!path) return fail(BSDE_EINVAL, "null path");
+    std::string arch;
+    const bsde_status st = device_arch(arch);
+    if (st != BSDE_OK) return st;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(BSDE_EINVAL, std::string("cannot read ") + path);
+    // parse every line first: a malformed file changes nothing
+    std::vector<std::pair<TuneKey, std::pair<int, int>>> rows;
+    char line[512];
+    int lineno = 0;
+    bool bad = false;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        const char *q = line;
+        while (*q == ' ' || *q == '\t') ++q;
+        if (*q == '#' || *q == '\n' || *q == '\0') continue;
+        char a[64];
+        TuneKey k;
+        int groups = 0, ppl = 0;
+        if (std::sscanf(q, "%63s %d %d %d %d %d %d %d %d %d %d", a, &k.d, &k.eta, &k.q10,
+                        &k.prec, &k.vol, &k.M, &k.N, &k.nclass, &groups, &ppl) != 11 ||
+            groups < 1 || ppl < 1 || k.M < 1 ||
+            (long long)groups * ppl * kBlock < (long long)k.M) {
+            bad = true;
+            break;
+        }
+        if (arch == a) rows.push_back({k, {groups, ppl}});
+    }
+    std::fclose(f);
+    if (bad)
+        return fail(BSDE_EINVAL, std::string(path) + ": malformed tiling record on line " +
+                                     std::to_string(lineno));
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        for (const auto &r : rows) g_tuned[r.first] = r.second;
+    }
+    if (count) *count = (int)rows.size();
+    return BSDE_OK;
+}
+
+bsde_status bsde_get_tiling(bsde_problem h, int *groups_per_point, int *paths_per_lane)
+{
+    if (!h || !groups_per_point || !paths_per_lane) return fail(BSDE_EINVAL, "null argument");
+    *groups_per_point = h->groups;
+    *paths_per_lane = h->ppl;
+    return BSDE_OK;
+}
+
 bsde_status bsde_set_timing(bsde_problem h, int level)
 {
     if (!h) return fail(BSDE_EINVAL, "null handle");

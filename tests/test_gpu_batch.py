@@ -101,3 +101,57 @@ def test_autotune_records_tiling_for_later_problems():
     b = run_gpu(cfg, tiling=(groups, ppl))
     np.testing.assert_array_equal(a["c"], b["c"])
     np.testing.assert_array_equal(a["alpha"], b["alpha"])
+
+
+def test_recorded_tilings_persist_by_architecture(tmp_path):
+    # signatures no other test tunes (N = 13 to 16): records for this
+    # device's architecture are taken by problems created after the load,
+    # records of another architecture are skipped, a malformed file changes
+    # nothing, and save writes back what was loaded
+    from gpu_util import run_gpu
+
+    def cfg_n(N):
+        return problem(d=1, vol_kind="bump", bump_a=0.25, n_t=5, n_x=12, eta=4,
+                       M=1100, N=N, K_it=2, precision="fp32", seed=11)
+
+    # the architecture the library keys its records by: the first field of
+    # a saved record
+    with bsde.Problem(cfg_n(16)) as P:
+        P.autotune()
+    first = tmp_path / "first.txt"
+    assert bsde.bsde_autotune_save(str(first)) >= 1
+    rows = [ln.split() for ln in first.read_text().splitlines() if not ln.startswith("#")]
+    arch = rows[0][0]
+    assert arch.startswith("gfx") and all(r[0] == arch for r in rows)
+
+    with bsde.Problem(cfg_n(13)) as P:
+        n = P.n
+        assert P.tiling() == (0, 0)
+    size_class = int(np.ceil(np.log2(n)))
+
+    def rec(a, N, groups, ppl):
+        return "%s 1 4 10 %d %d 1100 %d %d %d %d" % (
+            a, bsde.PRECISIONS["fp32"], bsde.VOL_KINDS["bump"], N, size_class, groups, ppl)
+
+    f = tmp_path / "tilings.txt"
+    f.write_text("# recorded tilings\n" + rec(arch, 13, 3, 2) + "\n" +
+                 rec("gfx000", 14, 5, 1) + "\n")
+    assert bsde.bsde_autotune_load(str(f)) == 1
+    with bsde.Problem(cfg_n(13)) as P:
+        assert P.tiling() == (3, 2)
+    with bsde.Problem(cfg_n(14)) as P:
+        assert P.tiling() == (0, 0)
+    # the loaded tiling is the one the solve runs: bitwise equal to setting it
+    a = run_gpu(cfg_n(13))
+    b = run_gpu(cfg_n(13), tiling=(3, 2))
+    np.testing.assert_array_equal(a["c"], b["c"])
+    # a tiling that does not cover M (1 x 2 x 256 < 1100) rejects the file
+    bad = tmp_path / "bad.txt"
+    bad.write_text(rec(arch, 15, 4, 1) + "\n" + rec(arch, 15, 1, 2) + "\n")
+    with pytest.raises(bsde.BsdeError):
+        bsde.bsde_autotune_load(str(bad))
+    with bsde.Problem(cfg_n(15)) as P:
+        assert P.tiling() == (0, 0)
+    out = tmp_path / "saved.txt"
+    assert bsde.bsde_autotune_save(str(out)) >= 1
+    assert rec(arch, 13, 3, 2) in out.read_text().splitlines()
