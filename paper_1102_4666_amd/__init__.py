@@ -103,6 +103,16 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libbsde.so is not built; run "
                               "`python -m paper_1102_4666_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own copy of the
+        # runtime library under the same soname, and whichever is loaded
+        # first serves every later user.  Loading torch first binds the
+        # library to torch's runtime, so that torch's streams and device
+        # memory are valid handles here (and torch still initialises after
+        # the library has touched the device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         H = C.c_void_p
         L.bsde_create_problem.argtypes = [
